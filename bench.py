@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X QAOA contraction on one GPU.
+
+Workload (the headline configuration): one amplitude <0...0|U|+> of the p=2
+QAOA MaxCut ansatz on a seeded random 3-regular graph with n=60 vertices,
+step-dependent slicing over 8 variables (256 slices), min-fill orders,
+(gamma, beta) drawn uniformly from [0, pi).  One step = one full amplitude:
+gate tensors, the serial prefix, all 256 slices, the FP64 slice sum.
+
+Reported beside the optimised complex64 path: the plain complex128 path
+(one launch per bucket step per slice), the relative error of both against
+the complex128 oracle, per-kernel-class HIP-event timings for the roofline,
+and the oracle itself timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QAOA amplitudes/s and edge-energies/s vs plain complex128 path at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def build_plan(precision, slice_batch=0):
+    from paper_2012_02430_amd import api
+    from paper_2012_02430_amd import network as N
+    from workloads import regular_graph
+
+    n, p, k = 60, 2, 8
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(k, algo="min_fill")
+    plan = api.Plan(net, sch.order, sch.groups, precision=precision, slice_batch=slice_batch)
+    return net, sch, plan, edges
+
+
+def time_calls(plan, g_dev, b_dev, out_dev, stream, steps, warmup):
+    import torch
+
+    from paper_2012_02430_amd import _lib as L
+
+    lib = L.load()
+    for _ in range(warmup):
+        L.check(lib.qt_contract_amplitude(plan.handle, g_dev.data_ptr(), b_dev.data_ptr(), out_dev.data_ptr(),
+                                          stream.cuda_stream))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L.check(lib.qt_contract_amplitude(plan.handle, g_dev.data_ptr(), b_dev.data_ptr(), out_dev.data_ptr(),
+                                          stream.cuda_stream))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(edges, g, b, sch, budget_s):
+    """The oracle (numpy complex128, Algorithm 1 slice by slice) on the host."""
+    import oracle
+
+    T = oracle.amplitude_network(60, edges, g, b)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.sliced_values(T, sch.order, sch.groups)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 30:
+            break
+    return reps / el, reps, el
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
+              "described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2012_02430_amd import api
+    from workloads import qaoa_params
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    g, b = qaoa_params(2, 1, seed=1)
+    g, b = g[0], b[0]
+
+    net, sch, plan, edges = build_plan("c64")
+    _, _, plain, _ = build_plan("c128", slice_batch=1)
+    print(f"[bench] plan: width {sch.width} (prefix {sch.prefix_width}, slice {sch.slice_width}), "
+          f"unsliced {sch.unsliced_width}, step {sch.step}, 256 slices", flush=True)
+
+    # accuracy against the oracle
+    want = complex(oracle.sliced_values(oracle.amplitude_network(60, edges, g, b), sch.order, sch.groups).sum())
+    got = plan.contract_amplitude(g, b)
+    got_plain = plain.contract_amplitude(g, b)
+    err = abs(got - want) / abs(want)
+    err_plain = abs(got_plain - want) / abs(want)
+    per = oracle.sliced_values(oracle.amplitude_network(60, edges, g, b), sch.order, sch.groups)
+    cond = float(np.abs(per).sum() / abs(per.sum()))
+    print(f"[bench] amplitude {got:.10e}  oracle {want:.10e}  rel err c64 {err:.2e}  c128 {err_plain:.2e}",
+          flush=True)
+
+    g_dev = torch.tensor(g, dtype=torch.float64, device="cuda")
+    b_dev = torch.tensor(b, dtype=torch.float64, device="cuda")
+    out_dev = torch.zeros(3, dtype=torch.float64, device="cuda")
+
+    el = time_calls(plan, g_dev, b_dev, out_dev, stream, args.steps, args.warmup)
+    value = args.steps / el
+    print(f"[bench] c64 path: {value:.1f} amplitudes/s ({1e3 * el / args.steps:.3f} ms each)", flush=True)
+    el_plain = time_calls(plain, g_dev, b_dev, out_dev, stream, args.plain_steps, 1)
+    plain_value = args.plain_steps / el_plain
+    print(f"[bench] plain c128 path: {plain_value:.2f} amplitudes/s", flush=True)
+
+    # per-kernel-class HIP-event timings over the same number of steps
+    plan.profile_enable(True)
+    time_calls(plan, g_dev, b_dev, out_dev, stream, args.steps, 0)
+    prof = plan.profile_read(reset=True)
+    plan.profile_enable(False)
+    kernels = {k: {"launches": v[0], "ms": v[1], "avg_us": 1e3 * v[1] / v[0], "GB/s": v[2] / v[1] / 1e6 if v[1] else 0}
+               for k, v in prof.items()}
+    dom = max((k for k in prof if k != "other"), key=lambda k: prof[k][1])
+    launches, ms, bytes_, flops = prof[dom]
+    achieved = bytes_ / (ms * 1e-3) / 1e9
+    print(f"[bench] dominant kernel class {dom}: {launches} launches, avg {1e3 * ms / launches:.2f} us, "
+          f"{achieved:.1f} GB/s algorithmic", flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rate, reps, cel = cpu_baseline(edges, g, b, sch, args.cpu_seconds)
+        cpu = {"value": rate, "unit": "amplitudes/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full amplitudes (all 256 slices) of the same workload in {cel:.1f} s, "
+                         "numpy complex128, single thread"}
+        print(f"[bench] oracle on host: {rate:.3f} amplitudes/s", flush=True)
+
+    inf = plan.info()
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "QAOA p=2 MaxCut single amplitude <0|U|+>, seeded random 3-regular graph n=60, "
+                        "step-dependent slicing over 8 variables (256 slices), min-fill orders",
+            "n": 60, "p": 2, "slice_vars": 8, "slices": 256, "points": 1,
+            "precision": "complex64 mantissas + per-tensor power-of-two exponents, FP64 slice sum",
+            "width": sch.width, "unsliced_width": sch.unsliced_width, "slice_step": sch.step,
+        },
+        "rel_err_vs_oracle": err,
+        "condition_estimate": cond,
+        "plain_c128": {"value": plain_value, "unit": "amplitudes/s", "rel_err_vs_oracle": err_plain,
+                       "launches_per_amplitude": plain.info().n_launches},
+        "speedup_vs_plain_c128": value / plain_value,
+        "launches_per_amplitude": inf.n_launches,
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

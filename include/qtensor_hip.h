@@ -1,0 +1,236 @@
+/*
+ * qtensor_hip.h -- C-ABI of the MI355X bucket-elimination contractor for
+ * QAOA MaxCut tensor networks with step-dependent slicing.
+ *
+ * The method (Lykov et al., "Tensor Network Quantum Simulator With
+ * Step-Dependent Parallelization"):
+ *   circuit -> tensor expression over binary variables (Section IV-A, IV-B)
+ *   -> elimination order and slice set (Section V-A, Section VI-C, VI-D)
+ *   -> bucket elimination, sliced part batched over slices, then a sum over
+ *      slices (Algorithm 1; Eq. (2)).
+ *
+ * General conventions
+ *   - Every call returns a qt_status; no exception or abort crosses the ABI.
+ *     On failure qt_last_error() (thread-local) holds a message; HIP errors
+ *     come back as QT_EHIP with the HIP error string in the message.
+ *   - The caller owns every buffer it passes; the library copies what it
+ *     keeps.  Objects returned through qt_network** / qt_plan** are owned by
+ *     the caller and released with qt_free_network / qt_free_plan (a plan
+ *     keeps its own copy of the network; the network may be freed first).
+ *   - Parameter arrays (gammas, betas) and outputs may be host or device
+ *     pointers.  Results written to host memory are complete when the call
+ *     returns (the call synchronises `hip_stream`); results written to
+ *     device memory are ordered on `hip_stream` and the call does not wait.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  The
+ *     library allocates its device workspace on first use of a plan and
+ *     keeps it with the plan; calls on one plan must not overlap.
+ *   - A value is reported as qt_amp: (re + i im) * 2^log2_scale, with re/im
+ *     and the scale in FP64.  Gate tensors |+> are stored as (1, 1) and
+ *     their 2^{-1/2} factors are carried exactly in log2_scale.
+ */
+#ifndef QTENSOR_HIP_H
+#define QTENSOR_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qt_network qt_network; /* opaque, library-owned storage */
+typedef struct qt_plan qt_plan;       /* opaque, library-owned storage */
+
+typedef enum {
+  QT_OK = 0,
+  QT_EINVAL = -1,          /* bad argument (null pointer, size out of range) */
+  QT_ENOMEM = -2,          /* host or device allocation failed */
+  QT_EPLAN = -3,           /* order / slice schedule inconsistent with the network */
+  QT_EHIP = -4,            /* a HIP runtime call failed */
+  QT_EUNSUPPORTED = -5,    /* valid request outside what this build handles */
+  QT_EFAULT_INJECTED = -6  /* test hook QT_FAULT_AFTER_SLICE fired */
+} qt_status;
+
+/* Arithmetic of the bucket steps.
+ *   QT_C128         complex128 throughout, no scaling: the plain path.
+ *   QT_C64_SCALED   complex64 mantissas with a per-tensor power-of-two
+ *                   exponent (renormalised after every step from the
+ *                   measured max|x|), FP64 slice sum.
+ *   QT_C64_SCALED_MFMA_FP32, QT_C64_SCALED_MFMA_BF16X3
+ *                   as QT_C64_SCALED, with buckets that are dense
+ *                   contractions run as complex GEMM on the matrix cores. */
+typedef enum {
+  QT_C128 = 0,
+  QT_C64_SCALED = 1,
+  QT_C64_SCALED_MFMA_FP32 = 2,
+  QT_C64_SCALED_MFMA_BF16X3 = 3
+} qt_precision;
+
+/* Tensor kinds (Section III-A gates; Section IV-B graph model: diagonal
+ * gates are written on the variables they share with their wires).
+ *   VEC_PLUS   |+> (also <+| of the energy network) on (x)          values (1, 1) * 2^{-1/2}
+ *   ZZ         exp(-i gamma_k (1 - Z_a Z_b)/2) on (x_a, x_b)       [[1, e^{-i g}], [e^{-i g}, 1]]
+ *   RX         exp(-i beta_k X) from x_in to x_out                  [[cos b, -i sin b], [-i sin b, cos b]]
+ *   BRA_BIT    <z| on an output variable (layer field = z)          e_z
+ *   ZZ_DAG     adjoint of ZZ, analytic in gamma                     [[1, e^{+i g}], [e^{+i g}, 1]]
+ *   RX_DAG     adjoint of RX, analytic in beta                      [[cos b, i sin b], [i sin b, cos b]]
+ *   OBS_CUT    (1 - Z_u Z_v)/2 on (x_u, x_v)                        [[0, 1], [1, 0]]
+ *   DENSE      caller-supplied values
+ * Parametrised kinds take gamma_k / beta_k with k = `layer` (1-based). */
+typedef enum {
+  QT_T_VEC_PLUS = 0,
+  QT_T_ZZ = 1,
+  QT_T_RX = 2,
+  QT_T_BRA_BIT = 3,
+  QT_T_ZZ_DAG = 4,
+  QT_T_RX_DAG = 5,
+  QT_T_OBS_CUT = 6,
+  QT_T_DENSE = 7
+} qt_tkind;
+
+typedef struct {
+  int32_t kind;         /* qt_tkind */
+  int32_t rank;         /* number of variables: 1 (VEC_PLUS, BRA_BIT), 2 (ZZ, RX, *_DAG, OBS_CUT), 1..24 (DENSE) */
+  int32_t layer;        /* 1..p for ZZ/RX/ZZ_DAG/RX_DAG; the bit z (0/1) for BRA_BIT; ignored otherwise */
+  const int32_t* vars;  /* `rank` distinct variable ids in [0, n_vars) */
+  const double* dense;  /* DENSE only: 2^rank interleaved (re, im); vars[0] is the most significant axis */
+} qt_tensor_desc;
+
+typedef struct {
+  int32_t n_vars;       /* size of the variable id space (ids need not all be used) */
+  int32_t n_tensors;
+  int32_t p;            /* number of QAOA layers (length of gammas / betas) */
+  const qt_tensor_desc* tensors;
+} qt_network_desc;
+
+/* Elimination order and step-dependent slicing schedule (Section VI-C, VI-D;
+ * Algorithm 1).  `order` lists every variable of the network that is not
+ * sliced, in elimination order.  Group g fixes its `group_len[g]` variables
+ * (concatenated in `slice_vars`) after `group_step[g]` variables of `order`
+ * have been eliminated; the first group_step[0] buckets form the serial
+ * prefix, run once and shared by every slice.  The slice id's bits are the
+ * slice variables' values, first listed variable most significant (the
+ * binary representation of the rank in Algorithm 1).  This build runs
+ * n_groups <= 1 (all slice variables at one step, r = n in Section VI-D). */
+typedef struct {
+  const int32_t* order;
+  int32_t n_order;
+  int32_t n_groups;
+  const int32_t* group_step;
+  const int32_t* group_len;
+  const int32_t* slice_vars;
+  int32_t precision;    /* qt_precision */
+  int64_t slice_batch;  /* slices processed per launch; 0 = as many as fit the workspace budget */
+} qt_plan_desc;
+
+typedef struct {
+  double re, im;        /* mantissa */
+  double log2_scale;    /* value = (re + i im) * 2^log2_scale */
+} qt_amp;
+
+/* Summary of a compiled plan (for reporting; algorithmic counts per point). */
+typedef struct {
+  int32_t n_steps;          /* bucket steps (prefix + per-slice) */
+  int32_t n_prefix_steps;
+  int32_t width;            /* max over steps of the eliminated variable's neighbour count (contraction width c) */
+  int32_t prefix_width;
+  int32_t slice_width;      /* width of the per-slice part */
+  int32_t n_slice_vars;
+  int64_t n_slices;
+  int64_t slice_batch;      /* slices per launch actually used */
+  double prefix_bytes;      /* algorithmic bytes of the prefix (inputs read + output written) */
+  double slice_bytes;       /* algorithmic bytes of one slice's steps */
+  double prefix_flops;      /* real flops of the prefix */
+  double slice_flops;       /* real flops of one slice */
+  int64_t workspace_bytes;  /* device workspace of the last run */
+  int32_t element_bytes;    /* 8 (complex64) or 16 (complex128) */
+  int32_t n_launches;       /* kernel launches of one amplitude at the last run's batch */
+} qt_plan_info;
+
+/* Copy a tensor network (Section IV-A: tensors over binary variables, each a
+ * clique of the line graph, Section IV-B).  Checks kinds, ranks and variable
+ * ids.  All inputs are copied. */
+qt_status qt_load_network(const qt_network_desc* desc, qt_network** out);
+
+/* Compile a plan: validate the order and slice schedule (QT_EPLAN if `order`
+ * is not a permutation of the unsliced variables, if slice variables repeat
+ * or overlap the order, or if group steps are out of [0, n_order]), run the
+ * bucket assignment of Algorithm 1 symbolically (each tensor goes to the
+ * bucket of its earliest variable; each result to the bucket of its earliest
+ * remaining variable), lay out every intermediate, and upload the step
+ * tables.  No kernel runs. */
+qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* desc, qt_plan** out);
+
+/* One amplitude at one parameter point: gate tensors materialised on the
+ * device from (gamma, beta) (p values each), the serial prefix, all slices
+ * (batched), the FP64 slice sum.  `out` receives the sum. */
+qt_status qt_contract_amplitude(qt_plan* plan, const double* gammas, const double* betas,
+                                qt_amp* out, void* hip_stream);
+
+/* Batched contraction: every plan at every point (gammas/betas are
+ * [n_points][p], row-major), restricted to slice ids in
+ * [slice_begin, slice_end) (the resumable unit of work; slices are
+ * independent, Eq. (2)).  out: [n_plans][n_points] partial sums over the
+ * range.  per_slice_out (optional, NULL to skip): [n_plans][n_points]
+ * [slice_end - slice_begin][3] doubles (re, im, log2_scale) per slice, the
+ * journal a caller keeps to resume.  Slices are summed in FP64 in slice-id
+ * order, so results are bitwise reproducible.  The test hook environment
+ * variable QT_FAULT_AFTER_SLICE=j makes the call return QT_EFAULT_INJECTED
+ * after the slices below j have been written to per_slice_out. */
+qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_points,
+                            const double* gammas, const double* betas,
+                            int64_t slice_begin, int64_t slice_end,
+                            qt_amp* out, double* per_slice_out, void* hip_stream);
+
+/* QAOA MaxCut energy E = sum_e <C_e> from per-edge lightcone networks
+ * (Section III-B: the energy is one amplitude of a duplicated expression;
+ * lightcone optimisation, Section III-A), all edges and points in one batched
+ * launch, and optionally its gradient by reverse-mode bucket elimination.
+ * `lightcones[e]` is the compiled plan of edge e's network (built with
+ * OBS_CUT, ZZ_DAG and RX_DAG tensors, no slicing).  gammas/betas are
+ * [n_points][p].  energy: [n_points] (required); dE_dgamma, dE_dbeta:
+ * [n_points][p] or NULL (no gradient pass); per_edge: [n_points][n_edges]
+ * or NULL.  Sums over edges run in FP64 in edge order. */
+qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
+                         const double* gammas, const double* betas,
+                         double* energy, double* dE_dgamma, double* dE_dbeta,
+                         double* per_edge, void* hip_stream);
+
+/* Introspection of a compiled plan. */
+qt_status qt_plan_get_info(const qt_plan* plan, qt_plan_info* out);
+
+/* Kernel classes reported by the profiler. */
+typedef enum {
+  QT_KCLASS_STEP_STREAM = 0, /* streaming bucket step, output >= 1024 elements per item */
+  QT_KCLASS_STEP_SMALL = 1,  /* bucket step with smaller outputs, one element per thread */
+  QT_KCLASS_LDS = 2,         /* LDS-resident multi-step contraction */
+  QT_KCLASS_GEMM = 3,        /* fused bucket as complex GEMM on MFMA */
+  QT_KCLASS_OTHER = 4,       /* gate materialisation, fills, per-slice products, slice sum */
+  QT_KCLASS_COUNT = 8
+} qt_kclass;
+
+typedef struct {
+  int64_t launches;
+  double ms;     /* summed kernel durations from HIP events recorded around each launch */
+  double bytes;  /* algorithmic bytes: elements of every input read plus the output written */
+  double flops;  /* algorithmic real flops */
+} qt_kernel_stats;
+
+/* Tracing: with `enable` != 0, later calls on `plan` record a HIP event pair
+ * around every kernel launch on the caller's stream (adds a few
+ * microseconds per launch); 0 turns recording off. */
+qt_status qt_profile_enable(qt_plan* plan, int32_t enable);
+
+/* Waits for the recorded events and adds their durations into
+ * out[QT_KCLASS_COUNT]; with `reset` != 0 the accumulated statistics are
+ * cleared afterwards. */
+qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_t reset);
+
+void qt_free_plan(qt_plan* plan);
+void qt_free_network(qt_network* net);
+const char* qt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTENSOR_HIP_H */

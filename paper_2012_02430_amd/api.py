@@ -1,0 +1,206 @@
+"""Python face of the C-ABI: networks, plans, contractions.
+
+Thin wrappers over ``_lib`` (ctypes).  Names follow the C entry points;
+objects own their C handles and free them on garbage collection.  Streams
+are HIP streams given as integers (``torch.cuda.current_stream().cuda_stream``)
+or None for the default stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from paper_2012_02430_amd import _lib as L
+from paper_2012_02430_amd.network import NetworkSpec
+
+PRECISIONS = {"c128": L.QT_C128, "c64": L.QT_C64_SCALED, "c64_mfma_fp32": L.QT_C64_SCALED_MFMA_FP32,
+              "c64_mfma_bf16x3": L.QT_C64_SCALED_MFMA_BF16X3}
+ORDER_ALGOS = {"min_degree": L.QT_ORDER_MIN_DEGREE, "min_fill": L.QT_ORDER_MIN_FILL, "rgreedy": L.QT_ORDER_RGREEDY}
+
+
+def amp_to_complex(re: float, im: float, log2_scale: float) -> complex:
+    """(re + i im) * 2^log2_scale in FP64."""
+    e = math.floor(log2_scale)
+    f = 2.0 ** (log2_scale - e)
+    return complex(math.ldexp(re * f, e), math.ldexp(im * f, e))
+
+
+class Network:
+    """A loaded tensor network (``qt_load_network``)."""
+
+    def __init__(self, spec: NetworkSpec):
+        lib = L.load()
+        self.spec = spec
+        self._keep = []
+        descs = (L.qt_tensor_desc * max(1, len(spec.tensors)))()
+        for i, t in enumerate(spec.tensors):
+            kind, layer, va = t[0], t[1], t[2]
+            arr = L.int32_array(va)
+            self._keep.append(arr)
+            descs[i].kind = kind
+            descs[i].rank = len(va)
+            descs[i].layer = layer
+            descs[i].vars = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+            if kind == L.QT_T_DENSE:
+                vals = np.asarray(t[3], dtype=np.complex128).reshape(-1)
+                dense = L.double_array(np.stack([vals.real, vals.imag], axis=1).reshape(-1))
+                self._keep.append(dense)
+                descs[i].dense = ctypes.cast(dense, ctypes.POINTER(ctypes.c_double))
+        nd = L.qt_network_desc(spec.n_vars, len(spec.tensors), spec.p, descs)
+        h = ctypes.c_void_p()
+        L.check(lib.qt_load_network(ctypes.byref(nd), ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            L.load().qt_free_network(self.handle)
+            self.handle = None
+
+    # ---- planning (host only, Section V-A / VI-C / VI-D)
+    def order_greedy(self, algo="min_fill", exclude=(), tau=1.0, repeats=1, seed=0):
+        lib = L.load()
+        cap = self.spec.n_vars
+        out = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        w = ctypes.c_int32()
+        ex = L.int32_array(exclude)
+        L.check(lib.qt_order_greedy(self.handle, ORDER_ALGOS[algo], ex, len(exclude), float(tau), int(repeats),
+                                    int(seed), out, ctypes.byref(n), ctypes.byref(w)))
+        return [out[i] for i in range(n.value)], w.value
+
+    def plan_slicing(self, n_slice_vars, algo="min_fill", max_candidates=0, threads=0, tau=1.0, repeats=1, seed=0):
+        lib = L.load()
+        cap = self.spec.n_vars
+        order = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        sl = (ctypes.c_int32 * max(1, n_slice_vars))()
+        res = L.qt_slicing_result()
+        wbs = (ctypes.c_int32 * (cap + 1))()
+        opts = L.qt_slicing_opts(ORDER_ALGOS[algo], n_slice_vars, max_candidates, threads, tau, repeats, seed)
+        L.check(lib.qt_plan_slicing(self.handle, ctypes.byref(opts), order, ctypes.byref(n), sl,
+                                    ctypes.byref(res), wbs))
+        return SlicingSchedule(
+            order=[order[i] for i in range(n.value)],
+            step=res.step,
+            slice_vars=[sl[i] for i in range(n_slice_vars)],
+            width=res.width,
+            prefix_width=res.prefix_width,
+            slice_width=res.slice_width,
+            unsliced_width=res.unsliced_width,
+            peak_step=res.peak_step,
+            cost=res.cost,
+            width_by_step={s: wbs[s] for s in range(cap + 1) if wbs[s] >= 0},
+        )
+
+
+@dataclass
+class SlicingSchedule:
+    order: list
+    step: int
+    slice_vars: list
+    width: int = 0
+    prefix_width: int = 0
+    slice_width: int = 0
+    unsliced_width: int = 0
+    peak_step: int = 0
+    cost: float = 0.0
+    width_by_step: dict = None
+
+    @property
+    def groups(self):
+        return [(self.step, list(self.slice_vars))] if self.slice_vars else []
+
+
+class Plan:
+    """A compiled plan (``qt_load_plan``) over a loaded network."""
+
+    def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0):
+        lib = L.load()
+        self.network = network
+        groups = list(groups)
+        self.order = list(order)
+        self.groups = groups
+        self.precision = precision
+        o = L.int32_array(self.order)
+        steps = L.int32_array([g[0] for g in groups])
+        lens = L.int32_array([len(g[1]) for g in groups])
+        sv = L.int32_array([v for g in groups for v in g[1]])
+        d = L.qt_plan_desc(ctypes.cast(o, ctypes.POINTER(ctypes.c_int32)), len(self.order), len(groups),
+                           ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32)),
+                           ctypes.cast(lens, ctypes.POINTER(ctypes.c_int32)),
+                           ctypes.cast(sv, ctypes.POINTER(ctypes.c_int32)),
+                           PRECISIONS[precision], int(slice_batch))
+        h = ctypes.c_void_p()
+        L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.p = network.spec.p
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            L.load().qt_free_plan(self.handle)
+            self.handle = None
+
+    def info(self) -> L.qt_plan_info:
+        inf = L.qt_plan_info()
+        L.check(L.load().qt_plan_get_info(self.handle, ctypes.byref(inf)))
+        return inf
+
+    @property
+    def n_slices(self) -> int:
+        return self.info().n_slices
+
+    def profile_enable(self, on=True):
+        L.check(L.load().qt_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, reset=True):
+        """{kernel class: (launches, ms, bytes, flops)} from HIP events."""
+        arr = (L.qt_kernel_stats * L.QT_KCLASS_COUNT)()
+        L.check(L.load().qt_profile_read(self.handle, arr, 1 if reset else 0))
+        return {name: (arr[i].launches, arr[i].ms, arr[i].bytes, arr[i].flops)
+                for i, name in L.QT_KCLASS_NAMES.items() if arr[i].launches}
+
+    def contract_amplitude(self, gammas, betas, stream=None) -> complex:
+        g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1)
+        b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1)
+        if g.size != self.p or b.size != self.p:
+            raise ValueError("gammas and betas need p values each")
+        out = L.qt_amp()
+        L.check(L.load().qt_contract_amplitude(self.handle, g.ctypes.data, b.ctypes.data, ctypes.byref(out),
+                                               stream or 0))
+        return amp_to_complex(out.re, out.im, out.log2_scale)
+
+    def contract_batch(self, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
+        """Partial sums over a slice range at every point; optional per-slice values.
+
+        Returns (values[n_points] complex, per_slice[n_points, n_range] complex or None).
+        """
+        return contract_batch([self], gammas, betas, slice_begin, slice_end, per_slice, stream)
+
+
+def contract_batch(plans, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
+    lib = L.load()
+    p = plans[0].p
+    g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1, p) if p else np.zeros((1, 0))
+    b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1, p) if p else np.zeros((1, 0))
+    n_points = g.shape[0]
+    if slice_end is None:
+        slice_end = plans[0].n_slices
+    n_range = slice_end - slice_begin
+    arr = (ctypes.c_void_p * len(plans))(*[pl.handle.value for pl in plans])
+    out = (L.qt_amp * (len(plans) * n_points))()
+    ps = np.zeros((len(plans), n_points, n_range, 3)) if per_slice else None
+    st = lib.qt_contract_batch(arr, len(plans), n_points, g.ctypes.data, b.ctypes.data, slice_begin, slice_end,
+                               ctypes.cast(out, ctypes.c_void_p), ps.ctypes.data if per_slice else None,
+                               stream or 0)
+    L.check(st)
+    vals = np.array([amp_to_complex(o.re, o.im, o.log2_scale) for o in out]).reshape(len(plans), n_points)
+    slices = None
+    if per_slice:
+        slices = np.vectorize(amp_to_complex)(ps[..., 0], ps[..., 1], ps[..., 2])
+    if len(plans) == 1:
+        return vals[0], (slices[0] if per_slice else None)
+    return vals, slices

@@ -1,0 +1,451 @@
+// Bucket-elimination kernels for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// A bucket step (Algorithm 1, inner loop and the sum over v) computes
+//   out[x] = prod_{j without v} T_j[x]  *  sum_{v=0,1} prod_{j with v} T_j[x, v]
+// for every output index x of every batch item (point, slice).  Every tensor
+// stores its variables ordered by one global key in which the eliminated
+// variable of a bucket is the lowest bit of every tensor of that bucket, so
+// the two v-values of an input are adjacent (one 16-byte load for complex64)
+// and every input's index is a monotone bit-extraction (pext) of the output
+// index: contiguous runs of output bits map to contiguous runs of input bits.
+// Slice variables carry the highest keys, so fixing them selects a
+// contiguous block (the paper's "first t indices" blocks, Section VI-B).
+#include <hip/hip_runtime.h>
+
+#include "qt_internal.h"
+
+namespace qt {
+namespace {
+
+constexpr int kWG = 256;
+constexpr int kEPT = 4;                 // elements per thread, BIG mode
+constexpr int kLgTile = 10;             // log2(kWG * kEPT)
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+template <typename E> struct Cx;
+template <> struct Cx<float2> {
+  using R = float;
+  __device__ static float2 one() { return make_float2(1.f, 0.f); }
+  __device__ static float2 from(double re, double im) { return make_float2((float)re, (float)im); }
+  __device__ static void load_pair(const void* p, int64_t idx, float2& a0, float2& a1) {
+    const float4 v = *(reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(p) + idx));
+    a0 = make_float2(v.x, v.y);
+    a1 = make_float2(v.z, v.w);
+  }
+};
+template <> struct Cx<double2> {
+  using R = double;
+  __device__ static double2 one() { return make_double2(1.0, 0.0); }
+  __device__ static double2 from(double re, double im) { return make_double2(re, im); }
+  __device__ static void load_pair(const void* p, int64_t idx, double2& a0, double2& a1) {
+    const double2* q = reinterpret_cast<const double2*>(p) + idx;
+    a0 = q[0];
+    a1 = q[1];
+  }
+};
+
+__device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevIn& in) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxRuns; ++i)
+    if (i < in.nruns) r |= ((x >> in.run_lo[i]) & ((1u << in.run_len[i]) - 1u)) << in.run_dst[i];
+  return r;
+}
+
+__device__ __forceinline__ uint32_t pext_bits(uint64_t x, uint32_t m) {
+  uint32_t r = 0;
+  int o = 0;
+  while (m) {
+    const int b = __ffs(m) - 1;
+    r |= (uint32_t)((x >> b) & 1u) << o;
+    ++o;
+    m &= m - 1;
+  }
+  return r;
+}
+
+// Exponent of the power of two that brings max|x| into [0.5, 1).
+__device__ __forceinline__ int scale_shift(uint32_t maxbits) {
+  if (maxbits == 0) return 0;
+  return ilogbf(__uint_as_float(maxbits)) + 1;
+}
+
+__device__ __forceinline__ float wave_max(float m) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+  return m;
+}
+
+template <typename E>
+__device__ __forceinline__ float abs_max(E v) {
+  return (float)fmax(fabs((double)v.x), fabs((double)v.y));
+}
+__device__ __forceinline__ float abs_max(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+
+// BIG mode: each workgroup covers one tile of kWG*kEPT outputs of one batch
+// item, so every per-item quantity (input bases, scale factors) is uniform.
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restrict__ exps,
+                                                  uint32_t* __restrict__ maxbits) {
+  using R = typename Cx<E>::R;
+  const uint32_t item = blockIdx.x >> s.lg_tiles;
+  const uint32_t tile = blockIdx.x & ((1u << s.lg_tiles) - 1u);
+  const uint32_t sb = item & ((1u << s.lg_nsb) - 1u);
+  const uint32_t pt = item >> s.lg_nsb;
+  const uint64_t sid = (uint64_t)s.chunk_base + sb;
+  const uint32_t tid = threadIdx.x;
+
+  int64_t base[kMaxIn];
+  uint32_t lanep[kMaxIn];
+  R scale[kMaxIn];
+  int eacc = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxIn; ++j) {
+    base[j] = 0;
+    lanep[j] = 0;
+    scale[j] = (R)1;
+    if (j < s.n_in) {
+      const DevIn& in = s.in[j];
+      base[j] = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                ((int64_t)pext_bits(sid, in.smask) << in.slow);
+      lanep[j] = pext_runs(tid, in);
+      if (SCALED && in.exp_base >= 0) {
+        const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+        const int sh = scale_shift(maxbits[slot]);
+        scale[j] = (R)ldexp(1.0, -sh);
+        eacc += exps[slot] + sh;
+      }
+    }
+  }
+  E* out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
+  float mx = 0.f;
+#pragma unroll
+  for (int e = 0; e < kEPT; ++e) {
+    const uint32_t hi = (tile << kLgTile) | ((uint32_t)e << 8);
+    E common = Cx<E>::one(), t0 = Cx<E>::one(), t1 = Cx<E>::one();
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      if (j < s.n_in) {
+        const DevIn& in = s.in[j];
+        const int64_t idx = base[j] + ((int64_t)(pext_runs(hi, in) + lanep[j]) << in.has_v);
+        if (in.has_v) {
+          E a0, a1;
+          Cx<E>::load_pair(in.ptr, idx, a0, a1);
+          if (SCALED) {
+            a0 = cscale(a0, scale[j]);
+            a1 = cscale(a1, scale[j]);
+          }
+          t0 = cmul(t0, a0);
+          t1 = cmul(t1, a1);
+        } else {
+          E a = reinterpret_cast<const E*>(in.ptr)[idx];
+          if (SCALED) a = cscale(a, scale[j]);
+          common = cmul(common, a);
+        }
+      }
+    }
+    const E res = s.sum ? cmul(common, cadd(t0, t1)) : common;
+    out[hi | tid] = res;
+    if (SCALED) mx = fmaxf(mx, abs_max(res));
+  }
+  if (SCALED) {
+    __shared__ float red[kWG / 64];
+    mx = wave_max(mx);
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+      float m = red[0];
+#pragma unroll
+      for (int w = 1; w < kWG / 64; ++w) m = fmaxf(m, red[w]);
+      const int slot = s.out_exp_base + (int)pt * s.out_exp_pt + (int)sb * s.out_exp_sb;
+      atomicMax(maxbits + slot, __float_as_uint(m));
+      if (tile == 0) exps[slot] = eacc;
+    }
+  }
+}
+
+// SMALL mode: one output element per thread over the flattened
+// (point, slice item, x) space; outputs smaller than a tile.
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(kWG) void k_step_small(const DevStep s, int* __restrict__ exps,
+                                                    uint32_t* __restrict__ maxbits, int64_t n_elems) {
+  using R = typename Cx<E>::R;
+  const int64_t g = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const bool valid = g < n_elems;
+  const uint32_t x = (uint32_t)(g & ((1ll << s.r) - 1));
+  const uint32_t item = (uint32_t)(g >> s.r);
+  const uint32_t sb = item & ((1u << s.lg_nsb) - 1u);
+  const uint32_t pt = item >> s.lg_nsb;
+  const uint64_t sid = (uint64_t)s.chunk_base + sb;
+  E res = Cx<E>::one();
+  int eacc = 0;
+  if (valid) {
+    E common = Cx<E>::one(), t0 = Cx<E>::one(), t1 = Cx<E>::one();
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      if (j < s.n_in) {
+        const DevIn& in = s.in[j];
+        R sc = (R)1;
+        if (SCALED && in.exp_base >= 0) {
+          const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+          const int sh = scale_shift(maxbits[slot]);
+          sc = (R)ldexp(1.0, -sh);
+          eacc += exps[slot] + sh;
+        }
+        const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                            ((int64_t)pext_bits(sid, in.smask) << in.slow) +
+                            ((int64_t)pext_runs(x, in) << in.has_v);
+        if (in.has_v) {
+          E a0, a1;
+          Cx<E>::load_pair(in.ptr, idx, a0, a1);
+          t0 = cmul(t0, cscale(a0, sc));
+          t1 = cmul(t1, cscale(a1, sc));
+        } else {
+          common = cmul(common, cscale(reinterpret_cast<const E*>(in.ptr)[idx], sc));
+        }
+      }
+    }
+    res = s.sum ? cmul(common, cadd(t0, t1)) : common;
+    reinterpret_cast<E*>(s.out)[g] = res;
+  }
+  if (SCALED) {
+    float m = valid ? abs_max(res) : 0.f;
+    const int seg = s.r < 6 ? s.r : 6;
+    for (int o = 1; o < (1 << seg); o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    const uint32_t lane = threadIdx.x & 63;
+    if (valid && (lane & ((1u << seg) - 1u)) == 0) {
+      const int slot = s.out_exp_base + (int)pt * s.out_exp_pt + (int)sb * s.out_exp_sb;
+      atomicMax(maxbits + slot, __float_as_uint(m));
+      if (x == 0) exps[slot] = eacc;
+    }
+  }
+}
+
+// Gate tensors from (gamma, beta), FP64 trigonometry rounded to the element
+// type (Section III-A conventions; see qtensor_hip.h for each kind).
+template <typename E>
+__global__ void k_leaves(const DevLeaf* __restrict__ leaves, int n_leaves, int leaf_block,
+                         const double* __restrict__ dense, const double* __restrict__ params, int p,
+                         int n_points, E* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_leaves * n_points) return;
+  const int pt = (int)(t / n_leaves);
+  const DevLeaf L = leaves[t % n_leaves];
+  E* o = out + (int64_t)pt * leaf_block + L.off;
+  const double* prm = params + (int64_t)pt * 2 * p;
+  switch (L.kind) {
+    case QT_T_VEC_PLUS:
+      o[0] = Cx<E>::from(1.0, 0.0);
+      o[1] = Cx<E>::from(1.0, 0.0);
+      break;
+    case QT_T_BRA_BIT:
+      o[0] = Cx<E>::from(L.layer == 0 ? 1.0 : 0.0, 0.0);
+      o[1] = Cx<E>::from(L.layer == 0 ? 0.0 : 1.0, 0.0);
+      break;
+    case QT_T_ZZ:
+    case QT_T_ZZ_DAG: {
+      double sn, cs;
+      sincos(prm[L.layer - 1], &sn, &cs);
+      const double im = L.kind == QT_T_ZZ ? -sn : sn;
+      o[0] = Cx<E>::from(1.0, 0.0);
+      o[1] = Cx<E>::from(cs, im);
+      o[2] = Cx<E>::from(cs, im);
+      o[3] = Cx<E>::from(1.0, 0.0);
+      break;
+    }
+    case QT_T_RX:
+    case QT_T_RX_DAG: {
+      double sn, cs;
+      sincos(prm[p + L.layer - 1], &sn, &cs);
+      const double im = L.kind == QT_T_RX ? -sn : sn;
+      o[0] = Cx<E>::from(cs, 0.0);
+      o[1] = Cx<E>::from(0.0, im);
+      o[2] = Cx<E>::from(0.0, im);
+      o[3] = Cx<E>::from(cs, 0.0);
+      break;
+    }
+    case QT_T_OBS_CUT:
+      o[0] = Cx<E>::from(0.0, 0.0);
+      o[1] = Cx<E>::from(1.0, 0.0);
+      o[2] = Cx<E>::from(1.0, 0.0);
+      o[3] = Cx<E>::from(0.0, 0.0);
+      break;
+    default: {  // DENSE, already permuted to storage order on the host
+      const int n = 1 << L.rank;
+      for (int i = 0; i < n; ++i) o[i] = Cx<E>::from(dense[2 * (L.dense_off + i)], dense[2 * (L.dense_off + i) + 1]);
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per-slice value: product of the plan's scalar factors (results of buckets
+// that closed to a scalar, Algorithm 1 "result <- result * R"), with its
+// exponent, in FP64.
+template <typename E, bool SCALED>
+__global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_points, int64_t n_items,
+                        const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
+                        double* __restrict__ per_slice, int64_t slice_end) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  const uint32_t sb = (uint32_t)(t & ((1ll << f.lg_nsb) - 1));
+  const uint32_t pt = (uint32_t)(t >> f.lg_nsb);
+  const uint64_t sid = (uint64_t)f.chunk_base + sb;
+  if ((int64_t)sid < f.slice_begin || (int64_t)sid >= slice_end) return;
+  double re = 1.0, im = 0.0, ex = f.log2_const;
+  for (int j = 0; j < f.n_factors; ++j) {
+    const DevIn in = fac[j];
+    const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                        ((int64_t)pext_bits(sid, in.smask) << in.slow);
+    const E a = reinterpret_cast<const E*>(in.ptr)[idx];
+    double ar = (double)a.x, ai = (double)a.y;
+    if (SCALED && in.exp_base >= 0) {
+      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+      const int sh = scale_shift(maxbits[slot]);
+      ar = ldexp(ar, -sh);
+      ai = ldexp(ai, -sh);
+      ex += exps[slot] + sh;
+    }
+    const double nr = re * ar - im * ai;
+    im = re * ai + im * ar;
+    re = nr;
+  }
+  double* o = per_slice + 3 * ((int64_t)pt * f.n_range + (int64_t)(sid - f.slice_begin));
+  o[0] = re;
+  o[1] = im;
+  o[2] = ex;
+}
+
+// Deterministic FP64 sum over slices (Algorithm 1's final reduction): common
+// exponent = max over non-zero slices, thread t adds slices t, t+256, ... in
+// order, then a fixed-shape tree over the 256 partial sums.
+__global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ per_slice, int64_t n_range,
+                                                   double* __restrict__ out) {
+  __shared__ double sre[256], sim[256];
+  const int pt = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* ps = per_slice + 3 * (int64_t)pt * n_range;
+  double emax = -INFINITY;
+  for (int64_t i = tid; i < n_range; i += 256)
+    if (ps[3 * i] != 0.0 || ps[3 * i + 1] != 0.0) emax = fmax(emax, ps[3 * i + 2]);
+  sre[tid] = emax;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) sre[tid] = fmax(sre[tid], sre[tid + o]);
+    __syncthreads();
+  }
+  emax = sre[0];
+  __syncthreads();
+  double re = 0.0, im = 0.0;
+  if (emax != -INFINITY) {
+    for (int64_t i = tid; i < n_range; i += 256) {
+      const double d = ps[3 * i + 2] - emax;
+      if (ps[3 * i] != 0.0 || ps[3 * i + 1] != 0.0) {
+        re += ldexp(ps[3 * i], (int)d) * exp2(d - (int)d);
+        im += ldexp(ps[3 * i + 1], (int)d) * exp2(d - (int)d);
+      }
+    }
+  }
+  sre[tid] = re;
+  sim[tid] = im;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      sre[tid] += sre[tid + o];
+      sim[tid] += sim[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[3 * pt] = sre[0];
+    out[3 * pt + 1] = sim[0];
+    out[3 * pt + 2] = emax == -INFINITY ? 0.0 : emax;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, const double* dense,
+                         const double* params, int p, int n_points, void* out, bool c128,
+                         hipStream_t stream) {
+  const int64_t n = (int64_t)n_leaves * n_points;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (c128)
+    hipLaunchKernelGGL(k_leaves<double2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params, p,
+                       n_points, reinterpret_cast<double2*>(out));
+  else
+    hipLaunchKernelGGL(k_leaves<float2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params, p,
+                       n_points, reinterpret_cast<float2*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits, int64_t n_elems,
+                       hipStream_t stream, int* n_launches, int* kclass) {
+  if (n_elems == 0) return hipSuccess;
+  if (n_launches) ++*n_launches;
+  if (kclass) *kclass = s.r >= kLgTile ? QT_KCLASS_STEP_STREAM : QT_KCLASS_STEP_SMALL;
+  if (s.r >= kLgTile) {
+    DevStep t = s;
+    t.lg_tiles = s.r - kLgTile;
+    const dim3 grid((unsigned)(n_elems >> kLgTile)), block(kWG);
+    if (c128)
+      hipLaunchKernelGGL((k_step_big<double2, false>), grid, block, 0, stream, t, exps, maxbits);
+    else if (scaled)
+      hipLaunchKernelGGL((k_step_big<float2, true>), grid, block, 0, stream, t, exps, maxbits);
+    else
+      hipLaunchKernelGGL((k_step_big<float2, false>), grid, block, 0, stream, t, exps, maxbits);
+  } else {
+    const dim3 grid((unsigned)((n_elems + kWG - 1) / kWG)), block(kWG);
+    if (c128)
+      hipLaunchKernelGGL((k_step_small<double2, false>), grid, block, 0, stream, s, exps, maxbits, n_elems);
+    else if (scaled)
+      hipLaunchKernelGGL((k_step_small<float2, true>), grid, block, 0, stream, s, exps, maxbits, n_elems);
+    else
+      hipLaunchKernelGGL((k_step_small<float2, false>), grid, block, 0, stream, s, exps, maxbits, n_elems);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items, bool c128,
+                        bool scaled, const int* exps, const uint32_t* maxbits, double* per_slice,
+                        int64_t slice_end, hipStream_t stream) {
+  const dim3 grid((unsigned)((n_items + 255) / 256)), block(256);
+  if (c128)
+    hipLaunchKernelGGL((k_final<double2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
+                       maxbits, per_slice, slice_end);
+  else if (scaled)
+    hipLaunchKernelGGL((k_final<float2, true>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
+                       maxbits, per_slice, slice_end);
+  else
+    hipLaunchKernelGGL((k_final<float2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
+                       maxbits, per_slice, slice_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_slice_sum, dim3(n_points), dim3(256), 0, stream, per_slice, n_range, out);
+  return hipGetLastError();
+}
+
+}  // namespace qt

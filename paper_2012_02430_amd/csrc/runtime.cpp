@@ -1,0 +1,491 @@
+// Execution of compiled plans: workspace, step descriptors and the launch
+// sequence of Algorithm 1 on one GPU -- gate tensors, the serial prefix,
+// the per-slice steps batched over slices (the loop over ranks becomes a
+// batch dimension), per-slice scalars, and the FP64 sum over slices.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "qt_internal.h"
+
+namespace qt {
+namespace {
+
+// Default device workspace budget for the per-slice arena.
+constexpr int64_t kDefaultBudget = 64ll << 30;
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+int ilog2(int64_t x) {
+  int r = 0;
+  while ((1ll << r) < x) ++r;
+  return r;
+}
+
+}  // namespace
+}  // namespace qt
+
+using namespace qt;
+
+struct qt_plan::Workspace {
+  int np = 0;
+  int64_t chunk = 0;
+  void* leaves = nullptr;
+  void* arena0 = nullptr;
+  void* arena1 = nullptr;
+  int* exps = nullptr;
+  uint32_t* maxbits = nullptr;
+  double* params = nullptr;
+  DevLeaf* dleaves = nullptr;
+  double* ddense = nullptr;
+  DevIn* dfinal = nullptr;
+  double* per_slice = nullptr;
+  int64_t per_slice_cap = 0;
+  double* sums = nullptr;
+  int64_t bytes = 0;
+  int64_t n_exp = 0, exp1_base = 0, exp1_count = 0;
+  std::vector<DevStep> steps;
+  std::vector<int64_t> step_elems;
+  std::vector<DevIn> finals;
+
+  void release() {
+    for (void* p : {leaves, arena0, arena1, (void*)exps, (void*)maxbits, (void*)params, (void*)dleaves,
+                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums})
+      if (p) (void)hipFree(p);
+    leaves = arena0 = arena1 = nullptr;
+    exps = nullptr;
+    maxbits = nullptr;
+    params = ddense = per_slice = sums = nullptr;
+    dleaves = nullptr;
+    dfinal = nullptr;
+    per_slice_cap = 0;
+    bytes = 0;
+  }
+  ~Workspace() { release(); }
+};
+
+struct qt_plan::Profile {
+  bool enabled = false;
+  struct Rec {
+    int kclass;
+    double bytes, flops;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  qt_kernel_stats acc[QT_KCLASS_COUNT] = {};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  hipError_t drain() {
+    for (auto& r : pending) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e != hipSuccess) return e;
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) return e;
+      qt_kernel_stats& k = acc[r.kclass];
+      k.launches += 1;
+      k.ms += ms;
+      k.bytes += r.bytes;
+      k.flops += r.flops;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+    return hipSuccess;
+  }
+  ~Profile() {
+    (void)drain();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+qt_plan::qt_plan() = default;
+qt_plan::~qt_plan() = default;
+
+namespace qt {
+namespace {
+// Records a HIP event pair around `launch` when profiling is on.
+template <class F>
+hipError_t timed(qt_plan& plan, hipStream_t stream, int kclass, double bytes, double flops, F launch) {
+  qt_plan::Profile* pr = plan.prof.get();
+  if (!pr || !pr->enabled) return launch();
+  hipEvent_t a = pr->get(), b = pr->get();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, stream);
+  if (e != hipSuccess) return e;
+  pr->pending.push_back({kclass, bytes, flops, a, b});
+  return hipSuccess;
+}
+}  // namespace
+}  // namespace qt
+
+namespace qt {
+namespace {
+
+template <class T>
+qt_status dev_alloc(T** p, int64_t count, int64_t& bytes) {
+  const size_t b = std::max<int64_t>(1, count) * sizeof(T);
+  if (hipMalloc((void**)p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QT_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+  }
+  bytes += (int64_t)b;
+  return QT_OK;
+}
+
+#define QT_TRY(expr)            \
+  do {                          \
+    qt_status _s = (expr);      \
+    if (_s != QT_OK) return _s; \
+  } while (0)
+
+bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t mask, int has_v, uint32_t smask,
+              int slow, int elt, DevIn& d) {
+  const SymTensor& st = plan.tensors[t];
+  std::memset(&d, 0, sizeof(d));
+  if (st.leaf >= 0) {
+    d.ptr = (const char*)ws.leaves + (int64_t)plan.dev_leaves[st.leaf].off * elt;
+    d.pt_stride = plan.leaf_block;
+    d.sb_stride = 0;
+    d.exp_base = -1;
+  } else if (st.level == 0) {
+    d.ptr = (const char*)ws.arena0 + st.unit_off * ws.np * elt;
+    d.pt_stride = 1ll << st.rank;
+    d.sb_stride = 0;
+    d.exp_base = st.exp_slot;
+    d.exp_pt = plan.n_exp0;
+    d.exp_sb = 0;
+  } else {
+    d.ptr = (const char*)ws.arena1 + st.unit_off * ws.np * ws.chunk * elt;
+    d.pt_stride = ws.chunk << st.rank;
+    d.sb_stride = 1ll << st.rank;
+    d.exp_base = (int32_t)(ws.exp1_base + st.exp_slot);
+    d.exp_pt = (int32_t)(ws.chunk * plan.n_exp1);
+    d.exp_sb = plan.n_exp1;
+  }
+  d.smask = smask;
+  d.slow = slow;
+  d.has_v = has_v;
+  // runs of contiguous set bits of the mask: (source bit, length, destination bit)
+  int n = 0, dst = 0;
+  for (int b = 0; b < 32;) {
+    if (!((mask >> b) & 1u)) {
+      ++b;
+      continue;
+    }
+    int e = b;
+    while (e < 32 && ((mask >> e) & 1u)) ++e;
+    if (n == kMaxRuns) return false;
+    d.run_lo[n] = (uint8_t)b;
+    d.run_len[n] = (uint8_t)(e - b);
+    d.run_dst[n] = (uint8_t)dst;
+    dst += e - b;
+    ++n;
+    b = e;
+  }
+  d.nruns = n;
+  return true;
+}
+
+qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
+  const bool c128 = plan.precision == QT_C128;
+  const int elt = c128 ? 16 : 8;
+  const int k = (int)plan.slice_vars.size();
+  int64_t chunk = 1;
+  if (k > 0) {
+    const int64_t n_slices = 1ll << k;
+    if (plan.slice_batch_req > 0) {
+      chunk = 1;
+      while (chunk * 2 <= std::min(plan.slice_batch_req, n_slices)) chunk *= 2;
+    } else {
+      int64_t budget = kDefaultBudget;
+      if (const char* e = std::getenv("QT_WORKSPACE_BUDGET")) budget = std::max<int64_t>(1, std::atoll(e));
+      const int64_t per = std::max<int64_t>(1, plan.arena1_units * np * elt);
+      chunk = 1;
+      while (chunk * 2 <= n_slices && chunk * 2 * per <= budget) chunk *= 2;
+    }
+  }
+  if (!plan.ws) plan.ws = std::make_unique<qt_plan::Workspace>();
+  auto& ws = *plan.ws;
+  if (ws.np != np || ws.chunk != chunk) {
+    ws.release();
+    ws.np = np;
+    ws.chunk = chunk;
+    int64_t& b = ws.bytes;
+    QT_TRY(dev_alloc((char**)&ws.leaves, (int64_t)plan.leaf_block * np * elt, b));
+    QT_TRY(dev_alloc((char**)&ws.arena0, std::max<int64_t>(1, plan.arena0_units) * np * elt, b));
+    QT_TRY(dev_alloc((char**)&ws.arena1, std::max<int64_t>(1, plan.arena1_units) * np * chunk * elt, b));
+    ws.exp1_base = (int64_t)np * plan.n_exp0;
+    ws.exp1_count = (int64_t)np * chunk * plan.n_exp1;
+    ws.n_exp = ws.exp1_base + ws.exp1_count;
+    QT_TRY(dev_alloc(&ws.exps, ws.n_exp, b));
+    QT_TRY(dev_alloc(&ws.maxbits, ws.n_exp, b));
+    QT_TRY(dev_alloc(&ws.params, (int64_t)np * 2 * std::max(1, plan.net.p), b));
+    QT_TRY(dev_alloc(&ws.dleaves, (int64_t)plan.dev_leaves.size(), b));
+    QT_TRY(dev_alloc(&ws.ddense, (int64_t)plan.dense_table.size(), b));
+    QT_TRY(dev_alloc(&ws.dfinal, (int64_t)plan.finals.size(), b));
+    QT_TRY(dev_alloc(&ws.sums, (int64_t)np * 3, b));
+    QT_HIP_CHECK(hipMemcpy(ws.dleaves, plan.dev_leaves.data(), plan.dev_leaves.size() * sizeof(DevLeaf),
+                           hipMemcpyHostToDevice));
+    QT_HIP_CHECK(hipMemcpy(ws.ddense, plan.dense_table.data(), plan.dense_table.size() * sizeof(double),
+                           hipMemcpyHostToDevice));
+    // step descriptors
+    ws.steps.clear();
+    ws.step_elems.clear();
+    for (const SymStep& st : plan.steps) {
+      DevStep d;
+      std::memset(&d, 0, sizeof(d));
+      const SymTensor& ot = plan.tensors[st.out];
+      DevIn od;
+      build_in(plan, ws, st.out, 0, 0, 0, 0, elt, od);
+      d.out = const_cast<void*>(od.ptr);
+      d.r = st.rank;
+      d.lg_nsb = st.level == 1 ? ilog2(chunk) : 0;
+      d.sum = st.sum;
+      d.n_in = (int)st.ins.size();
+      d.out_exp_base = od.exp_base;
+      d.out_exp_pt = od.exp_pt;
+      d.out_exp_sb = od.exp_sb;
+      for (size_t j = 0; j < st.ins.size(); ++j) {
+        const SymIn& si = st.ins[j];
+        if (!build_in(plan, ws, si.tensor, si.mask, si.has_v, si.smask, si.slow, elt, d.in[j]))
+          return fail(QT_EUNSUPPORTED, "input index map has more than 8 runs of bits");
+      }
+      ws.steps.push_back(d);
+      ws.step_elems.push_back((int64_t)np * (st.level == 1 ? chunk : 1) << ot.rank);
+    }
+    ws.finals.clear();
+    for (int t : plan.finals) {
+      const SymTensor& st = plan.tensors[t];
+      uint32_t smask = 0;
+      if (st.level == 0)
+        for (int x : st.vars)
+          for (int j = 0; j < k; ++j)
+            if (plan.slice_vars[j] == x) smask |= 1u << (k - 1 - j);
+      DevIn d;
+      build_in(plan, ws, t, 0, 0, smask, 0, elt, d);
+      ws.finals.push_back(d);
+    }
+    if (!ws.finals.empty())
+      QT_HIP_CHECK(hipMemcpy(ws.dfinal, ws.finals.data(), ws.finals.size() * sizeof(DevIn), hipMemcpyHostToDevice));
+    plan.info.slice_batch = chunk;
+  }
+  if (ws.per_slice_cap < (int64_t)np * n_range) {
+    if (ws.per_slice) (void)hipFree(ws.per_slice);
+    ws.per_slice = nullptr;
+    ws.per_slice_cap = 0;
+    int64_t dummy = 0;
+    QT_TRY(dev_alloc(&ws.per_slice, (int64_t)np * n_range * 3, dummy));
+    ws.per_slice_cap = (int64_t)np * n_range;
+  }
+  plan.info.workspace_bytes = ws.bytes + ws.per_slice_cap * 24;
+  return QT_OK;
+}
+
+qt_status upload_params(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream) {
+  const int p = plan.net.p;
+  if (p == 0) return QT_OK;
+  auto& ws = *plan.ws;
+  const size_t pitch = 2 * p * sizeof(double);
+  QT_HIP_CHECK(hipMemcpy2DAsync(ws.params, pitch, gammas, p * sizeof(double), p * sizeof(double), np,
+                                hipMemcpyDefault, stream));
+  QT_HIP_CHECK(hipMemcpy2DAsync(ws.params + p, pitch, betas, p * sizeof(double), p * sizeof(double), np,
+                                hipMemcpyDefault, stream));
+  return QT_OK;
+}
+
+// Runs one plan at np points over slices [begin, end); leaves the per-slice
+// values in ws.per_slice ([np][end - begin][3]) and the sums in ws.sums.
+qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
+                   int64_t stop, hipStream_t stream) {
+  const bool c128 = plan.precision == QT_C128;
+  const bool scaled = plan.precision != QT_C128;
+  const int k = (int)plan.slice_vars.size();
+  const int64_t n_range = end - begin;
+  QT_TRY(ensure_workspace(plan, np, n_range));
+  auto& ws = *plan.ws;
+  int launches = 0;
+  QT_TRY(upload_params(plan, np, gammas, betas, stream));
+  const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
+  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+    return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params, plan.net.p,
+                         np, ws.leaves, c128, stream);
+  }));
+  ++launches;
+  if (scaled && ws.exp1_base) {
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0,
+                       [&] { return launch_fill_u32(ws.maxbits, ws.exp1_base, 0u, stream); }));
+    ++launches;
+  }
+  auto step = [&](const DevStep& d, int i) -> hipError_t {
+    const SymStep& st = plan.steps[i];
+    const double items = (double)(ws.step_elems[i] >> st.rank);
+    const int kc = st.rank >= 10 ? QT_KCLASS_STEP_STREAM : QT_KCLASS_STEP_SMALL;
+    return timed(plan, stream, kc, st.bytes_c64 * eb * items, st.flops * items, [&] {
+      return launch_step(d, c128, scaled, ws.exps, ws.maxbits, ws.step_elems[i], stream, &launches, nullptr);
+    });
+  };
+  for (int i = 0; i < plan.n_prefix_steps; ++i) QT_HIP_CHECK(step(ws.steps[i], i));
+  DevFinal f{};
+  f.n_factors = (int)ws.finals.size();
+  f.slice_begin = begin;
+  f.n_range = n_range;
+  f.log2_const = plan.log2_const;
+  if (k == 0) {
+    f.lg_nsb = 0;
+    f.chunk_base = 0;
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+      return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream);
+    }));
+    ++launches;
+  } else {
+    const int64_t C = ws.chunk;
+    for (int64_t cb = begin & ~(C - 1); cb < stop; cb += C) {
+      if (scaled && ws.exp1_count) {
+        QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+          return launch_fill_u32(ws.maxbits + ws.exp1_base, ws.exp1_count, 0u, stream);
+        }));
+        ++launches;
+      }
+      for (size_t i = plan.n_prefix_steps; i < ws.steps.size(); ++i) {
+        DevStep d = ws.steps[i];
+        d.chunk_base = cb;
+        QT_HIP_CHECK(step(d, (int)i));
+      }
+      f.lg_nsb = ilog2(C);
+      f.chunk_base = cb;
+      QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+        return launch_final(f, ws.dfinal, np, (int64_t)np * C, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, stop,
+                            stream);
+      }));
+      ++launches;
+    }
+  }
+  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0,
+                     [&] { return launch_slice_sum(ws.per_slice, np, n_range, ws.sums, stream); }));
+  ++launches;
+  plan.info.n_launches = launches;
+  return QT_OK;
+}
+
+}  // namespace
+}  // namespace qt
+
+extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_points,
+                                       const double* gammas, const double* betas, int64_t slice_begin,
+                                       int64_t slice_end, qt_amp* out, double* per_slice_out, void* hip_stream) {
+  try {
+    if (!plans || n_plans <= 0 || n_points <= 0 || !out) return fail(QT_EINVAL, "qt_contract_batch: bad arguments");
+    const int p = plans[0] ? plans[0]->net.p : 0;
+    if (p > 0 && (!gammas || !betas)) return fail(QT_EINVAL, "qt_contract_batch: null parameters");
+    for (int i = 0; i < n_plans; ++i) {
+      if (!plans[i]) return fail(QT_EINVAL, "qt_contract_batch: null plan");
+      if (plans[i]->net.p != p) return fail(QT_EINVAL, "qt_contract_batch: plans differ in p");
+      const int64_t ns = 1ll << plans[i]->slice_vars.size();
+      if (slice_begin < 0 || slice_end > ns || slice_begin >= slice_end)
+        return fail(QT_EINVAL, "qt_contract_batch: slice range outside [0, n_slices)");
+    }
+    if ((slice_end - slice_begin) * n_points > (1ll << 28))
+      return fail(QT_EINVAL, "qt_contract_batch: slice range too long for one call");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int64_t stop = slice_end;
+    bool injected = false;
+    if (const char* e = std::getenv("QT_FAULT_AFTER_SLICE")) {
+      const int64_t j = std::atoll(e);
+      if (j >= slice_begin && j < slice_end) {
+        stop = j;
+        injected = true;
+      }
+    }
+    const bool out_dev = is_device_ptr(out);
+    const bool ps_dev = per_slice_out && is_device_ptr(per_slice_out);
+    const int64_t n_range = slice_end - slice_begin;
+    for (int i = 0; i < n_plans; ++i) {
+      qt_plan& plan = *plans[i];
+      if (stop > slice_begin) QT_TRY(run_plan(plan, n_points, gammas, betas, slice_begin, slice_end, stop, stream));
+      else QT_TRY(ensure_workspace(plan, n_points, n_range));
+      auto& ws = *plan.ws;
+      if (per_slice_out && stop > slice_begin) {
+        const size_t row = (size_t)n_range * 3 * sizeof(double);
+        const size_t width = (size_t)(stop - slice_begin) * 3 * sizeof(double);
+        QT_HIP_CHECK(hipMemcpy2DAsync(per_slice_out + (size_t)i * n_points * n_range * 3, row, ws.per_slice, row,
+                                      width, n_points, ps_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                      stream));
+      }
+      if (!injected)
+        QT_HIP_CHECK(hipMemcpyAsync(out + (size_t)i * n_points, ws.sums, (size_t)n_points * sizeof(qt_amp),
+                                    out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+    }
+    if (!out_dev || (per_slice_out && !ps_dev)) QT_HIP_CHECK(hipStreamSynchronize(stream));
+    if (injected) return fail(QT_EFAULT_INJECTED, "qt_contract_batch: QT_FAULT_AFTER_SLICE fired");
+    return QT_OK;
+  } catch (const std::exception& ex) {
+    return fail(QT_ENOMEM, std::string("qt_contract_batch: ") + ex.what());
+  }
+}
+
+extern "C" qt_status qt_contract_amplitude(qt_plan* plan, const double* gammas, const double* betas, qt_amp* out,
+                                           void* hip_stream) {
+  if (!plan) return fail(QT_EINVAL, "qt_contract_amplitude: null plan");
+  const int64_t ns = 1ll << plan->slice_vars.size();
+  return qt_contract_batch(&plan, 1, 1, gammas, betas, 0, ns, out, nullptr, hip_stream);
+}
+
+extern "C" void qt_free_plan(qt_plan* plan) { delete plan; }
+
+extern "C" qt_status qt_profile_enable(qt_plan* plan, int32_t enable) {
+  if (!plan) return fail(QT_EINVAL, "qt_profile_enable: null plan");
+  if (!plan->prof) plan->prof = std::make_unique<qt_plan::Profile>();
+  plan->prof->enabled = enable != 0;
+  return QT_OK;
+}
+
+extern "C" qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_t reset) {
+  if (!plan || !out) return fail(QT_EINVAL, "qt_profile_read: null argument");
+  if (!plan->prof) plan->prof = std::make_unique<qt_plan::Profile>();
+  QT_HIP_CHECK(plan->prof->drain());
+  for (int i = 0; i < QT_KCLASS_COUNT; ++i) out[i] = plan->prof->acc[i];
+  if (reset)
+    for (auto& a : plan->prof->acc) a = qt_kernel_stats{};
+  return QT_OK;
+}
+
+extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
+                                    const double* gammas, const double* betas, double* energy, double* dE_dgamma,
+                                    double* dE_dbeta, double* per_edge, void* hip_stream) {
+  (void)lightcones;
+  (void)n_edges;
+  (void)n_points;
+  (void)gammas;
+  (void)betas;
+  (void)energy;
+  (void)dE_dgamma;
+  (void)dE_dbeta;
+  (void)per_edge;
+  (void)hip_stream;
+  return fail(QT_EUNSUPPORTED, "qt_energy_grad: not built yet");
+}

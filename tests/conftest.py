@@ -19,3 +19,11 @@ def lib():
     from paper_2012_02430_amd import _lib
 
     return _lib.load()
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name the case on stdout (flushed) before a GPU test touches the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield

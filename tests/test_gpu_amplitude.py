@@ -1,0 +1,212 @@
+"""Parity of the HIP amplitude path with the oracle (through the C-ABI).
+
+Tolerances (relative): 1e-12 for the complex128 path, 1e-5 for complex64
+with power-of-two scaling.  Per-slice values are compared one by one.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_02430_amd import _lib as L
+from paper_2012_02430_amd import api
+from paper_2012_02430_amd import network as N
+from workloads import generate_regular_graph, qaoa_params, random_bitstring, regular_graph
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def slice_err(got, want):
+    """Max over slices of |got - want| relative to the largest slice value."""
+    return np.abs(np.asarray(got) - np.asarray(want)).max() / np.abs(want).max()
+
+
+def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batch=0, step=None):
+    spec = N.amplitude_network(n, edges, p, z)
+    net = api.Network(spec)
+    if k == 0:
+        order, _ = net.order_greedy(algo)
+        groups = []
+    else:
+        sch = net.plan_slicing(k, algo=algo)
+        order, groups = sch.order, sch.groups
+        if step is not None:
+            # force the slice step: prefix = first `step` of the unsliced
+            # order, the rest reordered on the sliced graph
+            full, _ = net.order_greedy(algo)
+            sl = sch.slice_vars
+            pre = [v for v in full if v not in sl][:step]
+            rest, _ = net.order_greedy(algo, exclude=sl + pre)
+            order, groups = pre + rest, [(step, sl)]
+    return net, api.Plan(net, order, groups, precision=precision, slice_batch=slice_batch)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_c1_amplitude(precision):
+    # n=16, p=1, min-fill order, no slicing
+    n, p = 16, 1
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 4, seed=1)
+    for i in range(4):
+        z = random_bitstring(n, i) if i else None
+        net, plan = build(n, p, edges, z, precision=precision)
+        got = plan.contract_amplitude(gs[i], bs[i])
+        want = oracle.amplitude(n, edges, gs[i], bs[i], z)
+        assert rel(got, want) < TOL[precision], (i, got, want)
+        assert rel(got, oracle.amplitude_sv(n, edges, gs[i], bs[i], z)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_c2_per_slice_parity(precision):
+    # n=60, p=2, k=8 slice variables (256 slices), min-fill plan
+    n, p, k = 60, 2, 8
+    edges = regular_graph(n, 3, 0)
+    g, b = qaoa_params(p, 1, seed=1)
+    net, plan = build(n, p, edges, k=k, precision=precision)
+    sch_order, groups = plan.order, plan.groups
+    total, per = plan.contract_batch(g, b, per_slice=True)
+    T = oracle.amplitude_network(n, edges, g[0], b[0])
+    want = oracle.sliced_values(T, sch_order, groups)
+    assert per.shape == (1, 256)
+    assert slice_err(per[0], want) < TOL[precision]
+    assert rel(total[0], want.sum()) < TOL[precision]
+    assert rel(plan.contract_amplitude(g[0], b[0]), want.sum()) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("k,step,slice_batch", [(1, None, 0), (3, 0, 0), (3, 10, 2), (5, "end", 0), (6, None, 1),
+                                                (6, None, 16)])
+def test_slicing_variants(precision, k, step, slice_batch):
+    n, p = 20, 2
+    edges = regular_graph(n, 3, 1)
+    z = random_bitstring(n, 5)
+    g, b = qaoa_params(p, 1, seed=k)
+    spec = N.amplitude_network(n, edges, p, z)
+    if step == "end":
+        step = len(spec.variables()) - k
+    net, plan = build(n, p, edges, z, k=k, precision=precision, slice_batch=slice_batch, step=step)
+    total, per = plan.contract_batch(g, b, per_slice=True)
+    want = oracle.sliced_values(oracle.amplitude_network(n, edges, g[0], b[0], z), plan.order, plan.groups)
+    assert slice_err(per[0], want) < TOL[precision]
+    assert rel(total[0], oracle.amplitude_sv(n, edges, g[0], b[0], z)) < TOL[precision]
+    # a sub-range of slices sums to the oracle's partial sum
+    if 2 ** k >= 4:
+        lo, hi = 1, 2 ** k - 1
+        part, per2 = plan.contract_batch(g, b, lo, hi, per_slice=True)
+        assert rel(part[0], want[lo:hi].sum()) < TOL[precision]
+        assert slice_err(per2[0], want[lo:hi]) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_many_points_batched(precision):
+    n, p, k = 14, 3, 4
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 5, seed=9)
+    net, plan = build(n, p, edges, k=k, precision=precision)
+    vals, per = plan.contract_batch(gs, bs, per_slice=True)
+    for i in range(5):
+        assert rel(vals[i], oracle.amplitude_sv(n, edges, gs[i], bs[i])) < TOL[precision]
+
+
+def _random_dense_network(rng, n_vars, n_tensors, max_rank, hub=None):
+    spec = N.NetworkSpec(n_vars=n_vars, p=0)
+    T = []
+    for t in range(n_tensors):
+        r = int(rng.integers(1, max_rank + 1))
+        va = list(rng.choice(n_vars, r, replace=False))
+        if hub is not None and t < 11 and hub not in va:
+            va[0] = hub
+        vals = (rng.standard_normal((2,) * len(va)) + 1j * rng.standard_normal((2,) * len(va))) * 0.7
+        spec.tensors.append((L.QT_T_DENSE, 0, tuple(int(v) for v in va), vals))
+        T.append((vals, tuple(int(v) for v in va)))
+    used = set(v for _, va in T for v in va)
+    return spec, T, used
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dense_networks(precision, seed):
+    # arbitrary dense tensors, a variable shared by 11 tensors (bucket split
+    # into product steps), and possibly disconnected pieces
+    rng = np.random.default_rng(seed)
+    spec, T, used = _random_dense_network(rng, 16, 24, 4, hub=3)
+    net = api.Network(spec)
+    order, _ = net.order_greedy("min_fill")
+    want = oracle.contract(T, order)
+    plan = api.Plan(net, order, precision=precision)
+    assert rel(plan.contract_amplitude([], []), want) < TOL[precision]
+    sch = net.plan_slicing(3, algo="min_degree")
+    plan = api.Plan(net, sch.order, sch.groups, precision=precision, slice_batch=2)
+    tot, per = plan.contract_batch([], [], per_slice=True)
+    assert rel(tot, want) < TOL[precision]
+    assert slice_err(per[0], oracle.sliced_values(T, sch.order, sch.groups)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_disconnected_graph(precision):
+    # two disjoint K4s: the amplitude factorises; buckets close to scalars
+    k4 = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    edges = k4 + [(a + 4, b + 4) for a, b in k4]
+    g, b = [0.3, 1.2], [0.7, 0.1]
+    want = oracle.amplitude_sv(8, edges, g, b)
+    net, plan = build(8, 2, edges, precision=precision)
+    assert rel(plan.contract_amplitude(g, b), want) < TOL[precision]
+    net, plan = build(8, 2, edges, k=2, precision=precision)
+    assert rel(plan.contract_amplitude(g, b), want) < TOL[precision]
+
+
+def test_bitwise_reproducible():
+    n, p = 60, 2
+    edges = regular_graph(n, 3, 0)
+    g, b = qaoa_params(p, 1, seed=1)
+    net, plan = build(n, p, edges, k=8, precision="c64")
+    a1, s1 = plan.contract_batch(g, b, per_slice=True)
+    a2, s2 = plan.contract_batch(g, b, per_slice=True)
+    assert a1[0] == a2[0] and np.array_equal(s1, s2)
+
+
+def test_fault_injection_and_resume(monkeypatch):
+    n, p = 20, 2
+    edges = regular_graph(n, 3, 0)
+    g, b = qaoa_params(p, 1, seed=2)
+    net, plan = build(n, p, edges, k=4, precision="c64", slice_batch=4)
+    full, per_full = plan.contract_batch(g, b, per_slice=True)
+    monkeypatch.setenv("QT_FAULT_AFTER_SLICE", "6")
+    with pytest.raises(L.QTError) as e:
+        plan.contract_batch(g, b, per_slice=True)
+    assert e.value.status == L.QT_EFAULT_INJECTED
+    monkeypatch.delenv("QT_FAULT_AFTER_SLICE")
+    # resume the missing range and combine the journal in slice order
+    rest, per_rest = plan.contract_batch(g, b, 6, 16, per_slice=True)
+    assert np.array_equal(per_rest[0], per_full[0][6:])
+
+
+def test_invalid_slice_range():
+    n, p = 10, 1
+    edges = regular_graph(n, 3, 0)
+    net, plan = build(n, p, edges, k=2, precision="c64")
+    for lo, hi in [(0, 5), (3, 3), (-1, 2)]:
+        with pytest.raises(L.QTError) as e:
+            plan.contract_batch([0.1], [0.2], lo, hi)
+        assert e.value.status == L.QT_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["c64"])
+def test_invariants_210_qubits_full_size(precision):
+    # configuration of the 210-qubit p=1 amplitude: min-degree plan, 8 slice
+    # variables (256 slices).  beta = 0 gives exactly 2^{-105}; gamma = 0
+    # gives e^{-i n beta} 2^{-105}.
+    n, p = 210, 1
+    edges = regular_graph(n, 3, 0)
+    net, plan = build(n, p, edges, k=8, algo="min_degree", precision=precision)
+    a = plan.contract_amplitude([0.83], [0.0])
+    assert rel(a, 2.0 ** -105) < TOL[precision]
+    a = plan.contract_amplitude([0.0], [0.41])
+    assert rel(a, np.exp(-1j * n * 0.41) * 2.0 ** -105) < TOL[precision]

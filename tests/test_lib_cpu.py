@@ -1,0 +1,159 @@
+"""Host-only checks of the C-ABI library (no GPU): exports, planner, plan validation."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2012_02430_amd import _lib as L
+from paper_2012_02430_amd import api
+from paper_2012_02430_amd import network as N
+from workloads import regular_graph
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    names = set()
+    for h in (ROOT / "include").glob("*.h"):
+        text = re.sub(r"/\*.*?\*/", "", h.read_text(), flags=re.S)
+        names.update(re.findall(r"\b(qt_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "qt_contract_amplitude" in names and "qt_plan_slicing" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(L.SIGNATURES)
+
+
+def _width_of(spec, order, removed=()):
+    """Contraction width of an order by plain vertex elimination (Section IV-B)."""
+    removed = set(removed)
+    adj = {v: set() for v in spec.variables() if v not in removed}
+    for _, _, va in spec.tensors:
+        va = [x for x in va if x not in removed]
+        for a in va:
+            adj[a].update(x for x in va if x != a)
+    w = 0
+    for v in order:
+        nb = adj.pop(v)
+        w = max(w, len(nb))
+        for a in nb:
+            adj[a].discard(v)
+            adj[a].update(x for x in nb if x != a)
+    assert not adj
+    return w
+
+
+@pytest.mark.parametrize("algo", ["min_degree", "min_fill", "rgreedy"])
+def test_greedy_order_width(algo):
+    n, p = 30, 2
+    spec = N.amplitude_network(n, regular_graph(n, 3, 0) if n in (4, 6, 8, 10, 12, 14, 16, 18, 20) else
+                               __import__("workloads").generate_regular_graph(n, 3, 0), p)
+    net = api.Network(spec)
+    order, w = net.order_greedy(algo, tau=0.5, repeats=4, seed=3)
+    assert sorted(order) == sorted(spec.variables())
+    assert w == _width_of(spec, order)
+
+
+def test_greedy_tie_break_smallest_id():
+    # a 4-cycle of ZZ-like rank-2 tensors: every vertex has degree 2; the
+    # smallest id goes first
+    spec = N.NetworkSpec(n_vars=4, p=1)
+    for a, b in [(0, 1), (1, 2), (2, 3), (3, 0)]:
+        spec.add(L.QT_T_ZZ, 1, a, b)
+    order, w = api.Network(spec).order_greedy("min_degree")
+    assert order[0] == 0 and w == 2
+
+
+@pytest.mark.parametrize("algo", ["min_degree", "min_fill"])
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_step_dependent_slicing(algo, k):
+    n, p = 60, 2
+    spec = N.amplitude_network(n, regular_graph(n, 3, 0), p)
+    net = api.Network(spec)
+    sch = net.plan_slicing(k, algo=algo)
+    assert len(sch.slice_vars) == k and not set(sch.slice_vars) & set(sch.order)
+    assert sorted(sch.order + sch.slice_vars) == sorted(spec.variables())
+    assert sch.width == max(sch.prefix_width, sch.slice_width)
+    assert sch.width <= sch.unsliced_width
+    assert 0 <= sch.step <= sch.peak_step
+    # widths recomputed independently: prefix on the full graph, the rest on
+    # the graph with the slice variables deleted after the prefix
+    assert sch.width_by_step[sch.step] == sch.width
+    assert min(sch.width_by_step.values()) == sch.width
+    # the symbolic compile of the plan reaches the same widths
+    pl = api.Plan(net, sch.order, sch.groups, precision="c64")
+    inf = pl.info()
+    assert (inf.prefix_width, inf.slice_width) == (sch.prefix_width, sch.slice_width)
+    assert inf.n_slices == 2 ** k
+
+
+def test_slicing_reduces_width_on_210_qubits():
+    # Section VIII: greedy width about 44 on the 210-qubit p=1 circuit, and
+    # slicing lowers it; here min-degree on the seeded instance
+    spec = N.amplitude_network(210, regular_graph(210, 3, 0), 1)
+    net = api.Network(spec)
+    one = net.plan_slicing(1, algo="min_degree")
+    eight = net.plan_slicing(8, algo="min_degree")
+    assert 40 <= one.unsliced_width <= 46
+    assert one.width <= one.unsliced_width - 1
+    assert eight.width <= one.width - 4
+
+
+def _plan_status(net, order, groups=(), precision="c64"):
+    try:
+        api.Plan(net, order, groups, precision=precision)
+        return L.QT_OK
+    except L.QTError as e:
+        return e.status
+
+
+def test_plan_validation():
+    spec = N.amplitude_network(8, regular_graph(8, 3, 0), 1)
+    net = api.Network(spec)
+    order, _ = net.order_greedy("min_fill")
+    assert _plan_status(net, order) == L.QT_OK
+    assert _plan_status(net, order[:-1]) == L.QT_EPLAN                 # a variable left out
+    assert _plan_status(net, order + [order[0]]) == L.QT_EPLAN         # repeated
+    assert _plan_status(net, order[1:], [(0, [order[0], order[0]])]) == L.QT_EPLAN
+    assert _plan_status(net, order, [(0, [order[0]])]) == L.QT_EPLAN    # sliced and ordered
+    assert _plan_status(net, order[1:], [(len(order), [order[0]])]) == L.QT_EPLAN  # step > n_order
+    assert _plan_status(net, order[2:], [(0, [order[0]]), (1, [order[1]])]) == L.QT_EUNSUPPORTED
+    assert _plan_status(net, order + [999]) == L.QT_EPLAN
+    assert _plan_status(net, order[1:], [(3, [order[0]])]) == L.QT_OK
+
+
+def test_network_validation():
+    lib = L.load()
+    spec = N.NetworkSpec(n_vars=4, p=1)
+    spec.add(L.QT_T_ZZ, 2, 0, 1)  # layer > p
+    with pytest.raises(L.QTError) as e:
+        api.Network(spec)
+    assert e.value.status == L.QT_EINVAL
+    spec = N.NetworkSpec(n_vars=4, p=1)
+    spec.add(L.QT_T_RX, 1, 0, 0)  # repeated variable
+    with pytest.raises(L.QTError):
+        api.Network(spec)
+    spec = N.NetworkSpec(n_vars=4, p=1)
+    spec.add(L.QT_T_VEC_PLUS, 0, 7)  # out of range
+    with pytest.raises(L.QTError):
+        api.Network(spec)
+    assert lib.qt_load_network(None, ctypes.byref(ctypes.c_void_p())) == L.QT_EINVAL
+
+
+def test_energy_network_matches_lightcone_convention():
+    # same variables and tensor count as the oracle's independent builder
+    import oracle
+
+    n, p = 60, 2
+    edges = regular_graph(n, 3, 0)
+    for u, v in edges[:5]:
+        spec = N.energy_network(n, edges, p, u, v)
+        T = oracle.energy_network(n, edges, np.zeros(p), np.zeros(p), u, v)
+        assert sorted(tuple(sorted(t[2])) for t in spec.tensors) == sorted(tuple(sorted(t[1])) for t in T)

@@ -120,7 +120,13 @@ typedef struct {
   const int32_t* slice_vars;
   int32_t precision;    /* qt_precision */
   int64_t slice_batch;  /* slices processed per launch; 0 = as many as fit the workspace budget */
+  int32_t flags;        /* QT_PLAN_* bits */
 } qt_plan_desc;
+
+/* Plan flags.  QT_PLAN_PLAIN: one launch per bucket step (no fusion of small
+ * steps into LDS-resident segments); with slice_batch = 1 this is the plain
+ * path, one launch per step per slice. */
+enum { QT_PLAN_PLAIN = 1 };
 
 typedef struct {
   double re, im;        /* mantissa */

@@ -60,7 +60,11 @@ class qt_network_desc(ctypes.Structure):
 class qt_plan_desc(ctypes.Structure):
     _fields_ = [("order", POINTER(c_int32)), ("n_order", c_int32), ("n_groups", c_int32),
                 ("group_step", POINTER(c_int32)), ("group_len", POINTER(c_int32)),
-                ("slice_vars", POINTER(c_int32)), ("precision", c_int32), ("slice_batch", c_int64)]
+                ("slice_vars", POINTER(c_int32)), ("precision", c_int32), ("slice_batch", c_int64),
+                ("flags", c_int32)]
+
+
+QT_PLAN_PLAIN = 1
 
 
 class qt_amp(ctypes.Structure):

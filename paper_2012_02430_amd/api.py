@@ -118,7 +118,7 @@ class SlicingSchedule:
 class Plan:
     """A compiled plan (``qt_load_plan``) over a loaded network."""
 
-    def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0):
+    def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False):
         lib = L.load()
         self.network = network
         groups = list(groups)
@@ -133,7 +133,7 @@ class Plan:
                            ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(lens, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(sv, ctypes.POINTER(ctypes.c_int32)),
-                           PRECISIONS[precision], int(slice_batch))
+                           PRECISIONS[precision], int(slice_batch), L.QT_PLAN_PLAIN if plain else 0)
         h = ctypes.c_void_p()
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h

@@ -93,8 +93,13 @@ __device__ __forceinline__ float abs_max(E v) {
 __device__ __forceinline__ float abs_max(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
 
 // BIG mode: each workgroup covers one tile of kWG*kEPT outputs of one batch
-// item, so every per-item quantity (input bases, scale factors) is uniform.
-template <typename E, bool SCALED>
+// item, so every per-item quantity (input bases, scale factors) is uniform
+// and the part of each input index that depends on the tile is computed on
+// the scalar unit.  All loads of a thread (kEPT elements x NIN inputs x the
+// two values of v) are issued before any arithmetic.  An input without the
+// summed variable is read twice at the same index, so the two products
+// t0 (v = 0) and t1 (v = 1) need no branch.
+template <typename E, bool SCALED, int NIN>
 __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restrict__ exps,
                                                   uint32_t* __restrict__ maxbits) {
   using R = typename Cx<E>::R;
@@ -105,57 +110,57 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   const uint64_t sid = (uint64_t)s.chunk_base + sb;
   const uint32_t tid = threadIdx.x;
 
-  int64_t base[kMaxIn];
-  uint32_t lanep[kMaxIn];
-  R scale[kMaxIn];
+  const E* src[NIN];
+  uint32_t lanep[NIN];
+  R scale[NIN];
   int eacc = 0;
 #pragma unroll
-  for (int j = 0; j < kMaxIn; ++j) {
-    base[j] = 0;
-    lanep[j] = 0;
+  for (int j = 0; j < NIN; ++j) {
+    const DevIn& in = s.in[j];
+    src[j] = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+             ((int64_t)pext_bits(sid, in.smask) << in.slow);
+    lanep[j] = pext_runs(tid, in);
     scale[j] = (R)1;
-    if (j < s.n_in) {
-      const DevIn& in = s.in[j];
-      base[j] = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-                ((int64_t)pext_bits(sid, in.smask) << in.slow);
-      lanep[j] = pext_runs(tid, in);
-      if (SCALED && in.exp_base >= 0) {
-        const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
-        const int sh = scale_shift(maxbits[slot]);
-        scale[j] = (R)ldexp(1.0, -sh);
-        eacc += exps[slot] + sh;
-      }
+    if (SCALED && in.exp_base >= 0) {
+      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+      const int sh = scale_shift(maxbits[slot]);
+      scale[j] = (R)ldexp(1.0, -sh);
+      eacc += exps[slot] + sh;
+    }
+  }
+  E a0[kEPT][NIN], a1[kEPT][NIN];
+#pragma unroll
+  for (int e = 0; e < kEPT; ++e) {
+    const uint32_t hi = (tile << kLgTile) | ((uint32_t)e << 8);
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const int hv = s.in[j].has_v;
+      const int64_t idx = (int64_t)(pext_runs(hi, s.in[j]) + lanep[j]) << hv;
+      a0[e][j] = src[j][idx];
+      a1[e][j] = src[j][idx + hv];
     }
   }
   E* out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
   float mx = 0.f;
 #pragma unroll
   for (int e = 0; e < kEPT; ++e) {
-    const uint32_t hi = (tile << kLgTile) | ((uint32_t)e << 8);
-    E common = Cx<E>::one(), t0 = Cx<E>::one(), t1 = Cx<E>::one();
-#pragma unroll
-    for (int j = 0; j < kMaxIn; ++j) {
-      if (j < s.n_in) {
-        const DevIn& in = s.in[j];
-        const int64_t idx = base[j] + ((int64_t)(pext_runs(hi, in) + lanep[j]) << in.has_v);
-        if (in.has_v) {
-          E a0, a1;
-          Cx<E>::load_pair(in.ptr, idx, a0, a1);
-          if (SCALED) {
-            a0 = cscale(a0, scale[j]);
-            a1 = cscale(a1, scale[j]);
-          }
-          t0 = cmul(t0, a0);
-          t1 = cmul(t1, a1);
-        } else {
-          E a = reinterpret_cast<const E*>(in.ptr)[idx];
-          if (SCALED) a = cscale(a, scale[j]);
-          common = cmul(common, a);
-        }
-      }
+    E t0 = a0[e][0], t1 = a1[e][0];
+    if (SCALED) {
+      t0 = cscale(t0, scale[0]);
+      t1 = cscale(t1, scale[0]);
     }
-    const E res = s.sum ? cmul(common, cadd(t0, t1)) : common;
-    out[hi | tid] = res;
+#pragma unroll
+    for (int j = 1; j < NIN; ++j) {
+      E x0 = a0[e][j], x1 = a1[e][j];
+      if (SCALED) {
+        x0 = cscale(x0, scale[j]);
+        x1 = cscale(x1, scale[j]);
+      }
+      t0 = cmul(t0, x0);
+      t1 = cmul(t1, x1);
+    }
+    const E res = s.sum ? cadd(t0, t1) : t0;
+    out[(tile << kLgTile) | ((uint32_t)e << 8) | tid] = res;
     if (SCALED) mx = fmaxf(mx, abs_max(res));
   }
   if (SCALED) {
@@ -176,48 +181,46 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
 
 // SMALL mode: one output element per thread over the flattened
 // (point, slice item, x) space; outputs smaller than a tile.
-template <typename E, bool SCALED>
+template <typename E, bool SCALED, int NIN>
 __global__ __launch_bounds__(kWG) void k_step_small(const DevStep s, int* __restrict__ exps,
                                                     uint32_t* __restrict__ maxbits, int64_t n_elems) {
   using R = typename Cx<E>::R;
-  const int64_t g = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  const bool valid = g < n_elems;
+  const int64_t g0 = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const bool valid = g0 < n_elems;
+  const int64_t g = valid ? g0 : 0;
   const uint32_t x = (uint32_t)(g & ((1ll << s.r) - 1));
   const uint32_t item = (uint32_t)(g >> s.r);
   const uint32_t sb = item & ((1u << s.lg_nsb) - 1u);
   const uint32_t pt = item >> s.lg_nsb;
   const uint64_t sid = (uint64_t)s.chunk_base + sb;
-  E res = Cx<E>::one();
+  E a0[NIN], a1[NIN];
+  R scale[NIN];
   int eacc = 0;
-  if (valid) {
-    E common = Cx<E>::one(), t0 = Cx<E>::one(), t1 = Cx<E>::one();
 #pragma unroll
-    for (int j = 0; j < kMaxIn; ++j) {
-      if (j < s.n_in) {
-        const DevIn& in = s.in[j];
-        R sc = (R)1;
-        if (SCALED && in.exp_base >= 0) {
-          const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
-          const int sh = scale_shift(maxbits[slot]);
-          sc = (R)ldexp(1.0, -sh);
-          eacc += exps[slot] + sh;
-        }
-        const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-                            ((int64_t)pext_bits(sid, in.smask) << in.slow) +
-                            ((int64_t)pext_runs(x, in) << in.has_v);
-        if (in.has_v) {
-          E a0, a1;
-          Cx<E>::load_pair(in.ptr, idx, a0, a1);
-          t0 = cmul(t0, cscale(a0, sc));
-          t1 = cmul(t1, cscale(a1, sc));
-        } else {
-          common = cmul(common, cscale(reinterpret_cast<const E*>(in.ptr)[idx], sc));
-        }
-      }
+  for (int j = 0; j < NIN; ++j) {
+    const DevIn& in = s.in[j];
+    const int hv = in.has_v;
+    const E* src = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                   ((int64_t)pext_bits(sid, in.smask) << in.slow);
+    const int64_t idx = (int64_t)pext_runs(x, in) << hv;
+    a0[j] = src[idx];
+    a1[j] = src[idx + hv];
+    scale[j] = (R)1;
+    if (SCALED && in.exp_base >= 0) {
+      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+      const int sh = scale_shift(maxbits[slot]);
+      scale[j] = (R)ldexp(1.0, -sh);
+      eacc += exps[slot] + sh;
     }
-    res = s.sum ? cmul(common, cadd(t0, t1)) : common;
-    reinterpret_cast<E*>(s.out)[g] = res;
   }
+  E t0 = cscale(a0[0], scale[0]), t1 = cscale(a1[0], scale[0]);
+#pragma unroll
+  for (int j = 1; j < NIN; ++j) {
+    t0 = cmul(t0, cscale(a0[j], scale[j]));
+    t1 = cmul(t1, cscale(a1[j], scale[j]));
+  }
+  const E res = s.sum ? cadd(t0, t1) : t0;
+  if (valid) reinterpret_cast<E*>(s.out)[g] = res;
   if (SCALED) {
     float m = valid ? abs_max(res) : 0.f;
     const int seg = s.r < 6 ? s.r : 6;
@@ -393,30 +396,49 @@ hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, co
   return hipGetLastError();
 }
 
-hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits, int64_t n_elems,
-                       hipStream_t stream, int* n_launches, int* kclass) {
-  if (n_elems == 0) return hipSuccess;
-  if (n_launches) ++*n_launches;
-  if (kclass) *kclass = s.r >= kLgTile ? QT_KCLASS_STEP_STREAM : QT_KCLASS_STEP_SMALL;
+namespace {
+
+template <typename E, bool SCALED, int NIN>
+void launch_step_t(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_elems, hipStream_t stream) {
   if (s.r >= kLgTile) {
     DevStep t = s;
     t.lg_tiles = s.r - kLgTile;
-    const dim3 grid((unsigned)(n_elems >> kLgTile)), block(kWG);
-    if (c128)
-      hipLaunchKernelGGL((k_step_big<double2, false>), grid, block, 0, stream, t, exps, maxbits);
-    else if (scaled)
-      hipLaunchKernelGGL((k_step_big<float2, true>), grid, block, 0, stream, t, exps, maxbits);
-    else
-      hipLaunchKernelGGL((k_step_big<float2, false>), grid, block, 0, stream, t, exps, maxbits);
+    hipLaunchKernelGGL((k_step_big<E, SCALED, NIN>), dim3((unsigned)(n_elems >> kLgTile)), dim3(kWG), 0, stream, t,
+                       exps, maxbits);
   } else {
-    const dim3 grid((unsigned)((n_elems + kWG - 1) / kWG)), block(kWG);
-    if (c128)
-      hipLaunchKernelGGL((k_step_small<double2, false>), grid, block, 0, stream, s, exps, maxbits, n_elems);
-    else if (scaled)
-      hipLaunchKernelGGL((k_step_small<float2, true>), grid, block, 0, stream, s, exps, maxbits, n_elems);
-    else
-      hipLaunchKernelGGL((k_step_small<float2, false>), grid, block, 0, stream, s, exps, maxbits, n_elems);
+    hipLaunchKernelGGL((k_step_small<E, SCALED, NIN>), dim3((unsigned)((n_elems + kWG - 1) / kWG)), dim3(kWG), 0,
+                       stream, s, exps, maxbits, n_elems);
   }
+}
+
+template <typename E, bool SCALED>
+void launch_step_n(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_elems, hipStream_t stream) {
+  switch (s.n_in) {
+    case 1: launch_step_t<E, SCALED, 1>(s, exps, maxbits, n_elems, stream); break;
+    case 2: launch_step_t<E, SCALED, 2>(s, exps, maxbits, n_elems, stream); break;
+    case 3: launch_step_t<E, SCALED, 3>(s, exps, maxbits, n_elems, stream); break;
+    case 4: launch_step_t<E, SCALED, 4>(s, exps, maxbits, n_elems, stream); break;
+    case 5: launch_step_t<E, SCALED, 5>(s, exps, maxbits, n_elems, stream); break;
+    case 6: launch_step_t<E, SCALED, 6>(s, exps, maxbits, n_elems, stream); break;
+    case 7: launch_step_t<E, SCALED, 7>(s, exps, maxbits, n_elems, stream); break;
+    default: launch_step_t<E, SCALED, 8>(s, exps, maxbits, n_elems, stream); break;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits, int64_t n_elems,
+                       hipStream_t stream, int* n_launches, int* kclass) {
+  if (n_elems == 0) return hipSuccess;
+  if (s.n_in < 1 || s.n_in > kMaxIn) return hipErrorInvalidValue;
+  if (n_launches) ++*n_launches;
+  if (kclass) *kclass = s.r >= kLgTile ? QT_KCLASS_STEP_STREAM : QT_KCLASS_STEP_SMALL;
+  if (c128)
+    launch_step_n<double2, false>(s, exps, maxbits, n_elems, stream);
+  else if (scaled)
+    launch_step_n<float2, true>(s, exps, maxbits, n_elems, stream);
+  else
+    launch_step_n<float2, false>(s, exps, maxbits, n_elems, stream);
   return hipGetLastError();
 }
 

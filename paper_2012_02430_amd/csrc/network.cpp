@@ -56,19 +56,12 @@ int expected_rank(int kind) {
 }
 
 constexpr int kMaxDenseRank = 24;
-constexpr int64_t kUnitAlign = 64;  // arena offsets in multiples of 64 elements
 
-int64_t align_units(int64_t n) { return (n + kUnitAlign - 1) / kUnitAlign * kUnitAlign; }
+}  // namespace
 
-struct Interval {
-  int32_t t;
-  int64_t size;
-  int32_t start, end;  // closed step interval
-};
-
-// Offline first-fit placement of tensors that are live over step intervals:
+// Offline first-fit placement of buffers live over closed time intervals:
 // largest first, each at the lowest offset free over its whole interval.
-int64_t place_intervals(std::vector<Interval>& iv, std::vector<qt::SymTensor>& tensors) {
+int64_t place_intervals(std::vector<Interval>& iv, std::vector<int64_t>& off_out) {
   std::sort(iv.begin(), iv.end(), [](const Interval& a, const Interval& b) {
     if (a.size != b.size) return a.size > b.size;
     return a.start < b.start;
@@ -91,13 +84,12 @@ int64_t place_intervals(std::vector<Interval>& iv, std::vector<qt::SymTensor>& t
       off = std::max(off, b.second);
     }
     placed.push_back({off, it.size, it.start, it.end});
-    tensors[it.t].unit_off = off;
+    off_out[it.t] = off;
     total = std::max(total, off + it.size);
   }
   return total;
 }
 
-}  // namespace
 }  // namespace qt
 
 using namespace qt;
@@ -178,6 +170,7 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     plan->net = *net;
     plan->precision = d->precision;
     plan->slice_batch_req = d->slice_batch;
+    plan->flags = d->flags;
     const int V = net->n_vars();
     std::vector<int> role(V, -1);
     auto internal = [&](int ext, int& iv) -> bool {
@@ -394,26 +387,13 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     plan->leaf_block = (off + 1) & ~1;
     if (plan->dense_table.empty()) plan->dense_table.push_back(0.0);
 
-    // Arenas: level 0 (per point) and level 1 (per point x slice item).
-    const int INF = INT_MAX / 2;
-    std::vector<Interval> iv0, iv1;
-    for (int t = 0; t < (int)T.size(); ++t) {
-      SymTensor& st = T[t];
+    // Exponent slots of intermediates: per point (level 0) or per point and
+    // slice item (level 1).  Device arenas are laid out at run time, once
+    // the launch schedule is known.
+    for (auto& st : T) {
       if (st.leaf >= 0) continue;
-      const int64_t size = align_units(1ll << st.rank);
-      int end = st.consumer;
-      if (end == -2) end = INF;
-      if (st.level == 0) {
-        if (end != INF && steps[end].level == 1) end = INF;
-        iv0.push_back({t, size, st.producer, end});
-        st.exp_slot = plan->n_exp0++;
-      } else {
-        iv1.push_back({t, size, st.producer, end});
-        st.exp_slot = plan->n_exp1++;
-      }
+      st.exp_slot = st.level == 0 ? plan->n_exp0++ : plan->n_exp1++;
     }
-    plan->arena0_units = place_intervals(iv0, T);
-    plan->arena1_units = place_intervals(iv1, T);
 
     qt_plan_info& in = plan->info;
     in.n_steps = (int)steps.size();

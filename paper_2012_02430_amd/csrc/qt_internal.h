@@ -93,6 +93,59 @@ struct DevStep {
   DevIn in[kMaxIn];
 };
 
+// ------------------------------------------------- LDS executor descriptors
+// Operand (or output) of a step run by the LDS executor: in LDS when ptr is
+// null (element offset lds_off inside the workgroup's tensor area), else in
+// global memory at ptr + pt*pt_stride + sb*sb_stride + (pext(sid, smask) << slow).
+constexpr int kXRuns = 8;   // executor steps have outputs of rank <= 16
+// Work unit of the executor: steps of rank >= kXBigRank are cut into units
+// of kXEpu * 64 outputs (kXEpu per lane), smaller steps into 64-output units.
+// (complex128 uses kXEpu / 2 per lane and units of half the size).
+constexpr int kXBigRank = 8;
+constexpr int kXEpu = 4;
+constexpr int kXMaxThreads = 512;
+inline int64_t x_unit_elems(int rank, int elt) { return rank >= kXBigRank ? 64 * (elt == 8 ? kXEpu : kXEpu / 2) : 64; }
+struct XIn {
+  const void* ptr;
+  int64_t pt_stride;
+  int64_t sb_stride;
+  uint32_t lds_off;
+  uint32_t smask;
+  int32_t slow;
+  int32_t has_v;
+  int32_t nruns;
+  int32_t slot_kind;  // 0: unscaled; 1: LDS slot; 2: global slot
+  int32_t slot;       // LDS slot index, or global slot base
+  int32_t exp_pt;
+  int32_t exp_sb;
+  int32_t pad;
+  uint8_t run_lo[kXRuns];
+  uint8_t run_len[kXRuns];
+  uint8_t run_dst[kXRuns];
+};
+
+struct XStep {
+  XIn out;   // output location and scale slot (runs unused)
+  int32_t r;
+  int32_t sum;
+  int32_t n_in;
+  int32_t pad;
+  XIn in[kMaxIn];
+};
+
+// One launch of the executor: every workgroup runs the same level schedule
+// for its batch item (pt, sb).
+struct XLaunch {
+  const XStep* steps;
+  const uint2* units;      // (step, 64-element chunk) work units, level by level
+  const int32_t* level_off;  // n_levels + 1 offsets into units
+  int32_t n_levels;
+  int32_t lg_nsb;
+  int64_t chunk_base;
+  int32_t n_slots;         // LDS scale slots
+  int32_t lds_elems;       // tensor area, elements
+};
+
 // Leaf (gate) tensor materialisation record.
 struct DevLeaf {
   int32_t kind;
@@ -141,9 +194,16 @@ struct SymTensor {
   int32_t producer = -1;      // step id
   int32_t consumer = -1;      // step id, or -2 for final scalar factors
   int32_t rank = 0;           // stored rank (= vars.size())
-  int64_t unit_off = 0;       // arena offset in units of elements per (point x batch item)
   int32_t exp_slot = -1;      // scalar slot base for exponents
 };
+
+// Buffers live over closed time intervals, packed first-fit, largest first.
+struct Interval {
+  int32_t t;
+  int64_t size;
+  int32_t start, end;
+};
+int64_t place_intervals(std::vector<Interval>& iv, std::vector<int64_t>& off_out);
 
 }  // namespace qt
 
@@ -165,10 +225,9 @@ struct qt_plan {
   int32_t leaf_block = 0;           // elements of one point's leaves
   std::vector<qt::DevLeaf> dev_leaves;
   std::vector<double> dense_table;  // interleaved, permuted to key order
-  int64_t arena0_units = 0;         // level-0 arena (units: elements per point)
-  int64_t arena1_units = 0;         // level-1 arena (units: elements per point x batch item)
   int32_t n_exp0 = 0, n_exp1 = 0;   // exponent slots per point / per (point x item)
   int64_t slice_batch_req = 0;
+  int32_t flags = 0;
   qt_plan_info info{};
   // HIP-event profiling of launches (qt_profile_enable / qt_profile_read)
   struct Profile;
@@ -193,6 +252,9 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items,
                         bool c128, bool scaled, const int* exps, const uint32_t* maxbits,
                         double* per_slice, int64_t slice_end, hipStream_t stream);
+hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c128, bool scaled, int* exps,
+                           uint32_t* maxbits, hipStream_t stream);
+size_t lds_exec_smem_bytes(int n_slots, int lds_elems, bool c128);
 hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,
                             hipStream_t stream);
 

@@ -4,7 +4,9 @@
 // batch dimension), per-slice scalars, and the FP64 sum over slices.
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 
 #include "qt_internal.h"
 
@@ -54,11 +56,42 @@ struct qt_plan::Workspace {
   std::vector<DevStep> steps;
   std::vector<int64_t> step_elems;
   std::vector<DevIn> finals;
+  // Launch sequence: a streaming step (seg < 0, index `step`) or an LDS
+  // segment (index `seg`), separately for the prefix and the per-slice part.
+  struct Op {
+    int step;
+    int seg;
+  };
+  struct Segment {
+    int level = 0;
+    std::vector<int> steps;  // plan step ids, in plan order
+    int n_levels = 0;
+    int n_slots = 0;
+    int lds_elems = 0;
+    double bytes_c64 = 0, flops = 0;  // per item
+    std::vector<XStep> xsteps;
+    std::vector<uint2> units;
+    std::vector<int32_t> level_off;
+    XLaunch launch{};
+  };
+  std::vector<Op> prefix_ops, slice_ops;
+  std::vector<Segment> segs;
+  void* seg_tables = nullptr;
+  int waves = 8;
+  // schedule (independent of batch size): per step its segment and level,
+  // per tensor its LDS offset/slot (-1: global) and global arena offset
+  bool planned = false;
+  std::vector<int> seg_of, depth;
+  std::vector<int64_t> lds_off;
+  std::vector<int> lds_slot;
+  std::vector<int64_t> unit_off;
+  int64_t arena0_units = 0, arena1_units = 0;
 
   void release() {
     for (void* p : {leaves, arena0, arena1, (void*)exps, (void*)maxbits, (void*)params, (void*)dleaves,
-                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums})
+                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums, seg_tables})
       if (p) (void)hipFree(p);
+    seg_tables = nullptr;
     leaves = arena0 = arena1 = nullptr;
     exps = nullptr;
     maxbits = nullptr;
@@ -163,6 +196,35 @@ qt_status dev_alloc(T** p, int64_t count, int64_t& bytes) {
     if (_s != QT_OK) return _s; \
   } while (0)
 
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
+constexpr int64_t kUnitAlign = 64;  // arena offsets in multiples of 64 elements
+int64_t align_units(int64_t n) { return (n + kUnitAlign - 1) / kUnitAlign * kUnitAlign; }
+
+bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns) {
+  int n = 0, d = 0;
+  for (int b = 0; b < 32;) {
+    if (!((mask >> b) & 1u)) {
+      ++b;
+      continue;
+    }
+    int e = b;
+    while (e < 32 && ((mask >> e) & 1u)) ++e;
+    if (n == max_runs) return false;
+    lo[n] = (uint8_t)b;
+    len[n] = (uint8_t)(e - b);
+    dst[n] = (uint8_t)d;
+    d += e - b;
+    ++n;
+    b = e;
+  }
+  nruns = n;
+  return true;
+}
+
 bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t mask, int has_v, uint32_t smask,
               int slow, int elt, DevIn& d) {
   const SymTensor& st = plan.tensors[t];
@@ -173,14 +235,14 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
     d.sb_stride = 0;
     d.exp_base = -1;
   } else if (st.level == 0) {
-    d.ptr = (const char*)ws.arena0 + st.unit_off * ws.np * elt;
+    d.ptr = (const char*)ws.arena0 + ws.unit_off[t] * ws.np * elt;
     d.pt_stride = 1ll << st.rank;
     d.sb_stride = 0;
     d.exp_base = st.exp_slot;
     d.exp_pt = plan.n_exp0;
     d.exp_sb = 0;
   } else {
-    d.ptr = (const char*)ws.arena1 + st.unit_off * ws.np * ws.chunk * elt;
+    d.ptr = (const char*)ws.arena1 + ws.unit_off[t] * ws.np * ws.chunk * elt;
     d.pt_stride = ws.chunk << st.rank;
     d.sb_stride = 1ll << st.rank;
     d.exp_base = (int32_t)(ws.exp1_base + st.exp_slot);
@@ -190,31 +252,276 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
   d.smask = smask;
   d.slow = slow;
   d.has_v = has_v;
-  // runs of contiguous set bits of the mask: (source bit, length, destination bit)
-  int n = 0, dst = 0;
-  for (int b = 0; b < 32;) {
-    if (!((mask >> b) & 1u)) {
-      ++b;
+  return make_runs(mask, kMaxRuns, d.run_lo, d.run_len, d.run_dst, d.nruns);
+}
+
+// Launch schedule, independent of batch size and pointers:
+//  * cuts the step list into LDS segments (maximal runs of consecutive steps
+//    of one level whose outputs have rank <= max_rank) and streaming steps;
+//  * groups each segment's steps into dependency levels;
+//  * places every tensor produced and consumed inside a segment in LDS when
+//    it fits (first-fit over level intervals, largest first);
+//  * lays out the global arenas over schedule time (a streaming step is one
+//    tick, a segment's level L is tick start + L), so buffers of steps that
+//    run concurrently inside a segment never share memory.
+qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
+  ws.prefix_ops.clear();
+  ws.slice_ops.clear();
+  ws.segs.clear();
+  const bool plain = (plan.flags & QT_PLAN_PLAIN) != 0;
+  const int max_rank = std::min(16, env_int("QT_LDS_MAX_RANK", 14));
+  ws.waves = std::max(1, std::min(kXMaxThreads / 64, env_int("QT_LDS_WAVES", 8)));
+  const int64_t lds_bytes = std::min(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
+  const int nsteps = (int)plan.steps.size();
+  const int ntens = (int)plan.tensors.size();
+  ws.seg_of.assign(nsteps, -1);
+  ws.depth.assign(nsteps, 0);
+  ws.lds_off.assign(ntens, -1);
+  ws.lds_slot.assign(ntens, -1);
+  // Depth and LDS placement of a candidate segment (steps in plan order).
+  // Returns false when some tensor produced and consumed inside does not
+  // fit: a global buffer must never be written and read in the same launch
+  // (the reader's vector L1 may hold the line from before the write).
+  auto place = [&](const std::vector<int>& steps, qt_plan::Workspace::Segment& S, bool commit) -> bool {
+    std::vector<char> in_seg(nsteps, 0);
+    for (int i : steps) in_seg[i] = 1;
+    std::vector<int> dep(nsteps, 0);
+    int n_levels = 0;
+    for (int i : steps) {
+      for (const SymIn& in : plan.steps[i].ins) {
+        const int pr = plan.tensors[in.tensor].producer;
+        if (pr >= 0 && in_seg[pr]) dep[i] = std::max(dep[i], dep[pr] + 1);
+      }
+      n_levels = std::max(n_levels, dep[i] + 1);
+    }
+    std::vector<Interval> cands;
+    for (int i : steps) {
+      const int t = plan.steps[i].out;
+      const int c = plan.tensors[t].consumer;
+      if (c >= 0 && in_seg[c]) cands.push_back({t, std::max<int64_t>(2, 1ll << plan.tensors[t].rank), dep[i], dep[c]});
+    }
+    std::sort(cands.begin(), cands.end(), [](const Interval& x, const Interval& y) {
+      return x.size != y.size ? x.size > y.size : x.start < y.start;
+    });
+    const int64_t cap = (lds_bytes - 8 * (int64_t)(cands.size() + 4)) / elt;
+    struct Placed {
+      int64_t off, size;
+      int start, end;
+    };
+    std::vector<Placed> placed;
+    std::vector<std::pair<int64_t, int64_t>> busy;
+    std::vector<std::pair<int, int64_t>> where;
+    int64_t top = 0;
+    for (const Interval& c : cands) {
+      busy.clear();
+      for (const auto& p : placed)
+        if (p.start <= c.end && c.start <= p.end) busy.emplace_back(p.off, p.off + p.size);
+      std::sort(busy.begin(), busy.end());
+      int64_t off = 0;
+      for (const auto& b : busy) {
+        if (b.first >= off + c.size) break;
+        off = std::max(off, b.second);
+      }
+      if (off + c.size > cap) return false;
+      placed.push_back({off, c.size, c.start, c.end});
+      where.emplace_back(c.t, off);
+      top = std::max(top, off + c.size);
+    }
+    if (!commit) return true;
+    S.steps = steps;
+    S.n_levels = n_levels;
+    S.lds_elems = (int)top;
+    for (int i : steps) {
+      ws.depth[i] = dep[i];
+      S.bytes_c64 += plan.steps[i].bytes_c64;
+      S.flops += plan.steps[i].flops;
+    }
+    for (const auto& w : where) {
+      ws.lds_off[w.first] = w.second;
+      ws.lds_slot[w.first] = S.n_slots++;
+    }
+    return true;
+  };
+  // Recursive halving until every piece keeps its internal tensors in LDS.
+  std::function<void(const std::vector<int>&, int, std::vector<qt_plan::Workspace::Op>&)> emit_run =
+      [&](const std::vector<int>& steps, int level, std::vector<qt_plan::Workspace::Op>& ops) {
+        qt_plan::Workspace::Segment S;
+        S.level = level;
+        if (steps.size() == 1 || place(steps, S, false)) {
+          place(steps, S, true);
+          ws.segs.push_back(std::move(S));
+          const int si = (int)ws.segs.size() - 1;
+          for (int i : ws.segs[si].steps) ws.seg_of[i] = si;
+          ops.push_back({-1, si});
+          return;
+        }
+        const size_t h = steps.size() / 2;
+        emit_run(std::vector<int>(steps.begin(), steps.begin() + h), level, ops);
+        emit_run(std::vector<int>(steps.begin() + h, steps.end()), level, ops);
+      };
+  std::vector<int> run;
+  int run_level = -1;
+  auto flush = [&]() {
+    if (run.empty()) return;
+    emit_run(run, run_level, run_level == 0 ? ws.prefix_ops : ws.slice_ops);
+    run.clear();
+  };
+  for (int i = 0; i < nsteps; ++i) {
+    const SymStep& st = plan.steps[i];
+    if (plain || st.rank > max_rank) {
+      flush();
+      (st.level == 0 ? ws.prefix_ops : ws.slice_ops).push_back({i, -1});
       continue;
     }
-    int e = b;
-    while (e < 32 && ((mask >> e) & 1u)) ++e;
-    if (n == kMaxRuns) return false;
-    d.run_lo[n] = (uint8_t)b;
-    d.run_len[n] = (uint8_t)(e - b);
-    d.run_dst[n] = (uint8_t)dst;
-    dst += e - b;
-    ++n;
-    b = e;
+    if (st.level != run_level) flush();
+    run_level = st.level;
+    run.push_back(i);
   }
-  d.nruns = n;
-  return true;
+  flush();
+  for (int t = 0; t < ntens; ++t) {
+    const SymTensor& st = plan.tensors[t];
+    if (st.leaf < 0 && ws.lds_off[t] < 0 && st.consumer >= 0 && ws.seg_of[st.producer] >= 0 &&
+        ws.seg_of[st.producer] == ws.seg_of[st.consumer])
+      return fail(QT_EPLAN, "internal: a global tensor is written and read inside one launch");
+  }
+  // schedule time of every step
+  std::vector<int> when(nsteps, 0);
+  int clock = 0;
+  for (auto* ops : {&ws.prefix_ops, &ws.slice_ops}) {
+    for (const auto& op : *ops) {
+      if (op.seg < 0) {
+        when[op.step] = clock++;
+      } else {
+        for (int i : ws.segs[op.seg].steps) when[i] = clock + ws.depth[i];
+        clock += ws.segs[op.seg].n_levels;
+      }
+    }
+  }
+  const int INF = 1 << 30;
+  std::vector<Interval> iv0, iv1;
+  for (int t = 0; t < ntens; ++t) {
+    const SymTensor& st = plan.tensors[t];
+    if (st.leaf >= 0 || ws.lds_off[t] >= 0) continue;
+    int end = st.consumer < 0 ? INF : when[st.consumer];
+    if (st.level == 0 && st.consumer >= 0 && plan.steps[st.consumer].level == 1) end = INF;  // kept for every chunk
+    Interval it{t, align_units(1ll << st.rank), when[st.producer], end};
+    (st.level == 0 ? iv0 : iv1).push_back(it);
+  }
+  ws.unit_off.assign(ntens, 0);
+  ws.arena0_units = place_intervals(iv0, ws.unit_off);
+  ws.arena1_units = place_intervals(iv1, ws.unit_off);
+  ws.planned = true;
+  if (env_int("QT_DEBUG_SCHEDULE", 0)) {
+    for (size_t si = 0; si < ws.segs.size(); ++si) {
+      const auto& S = ws.segs[si];
+      std::fprintf(stderr, "segment %zu level %d: %zu steps, %d levels, %d LDS slots, %d LDS elems\n", si, S.level,
+                   S.steps.size(), S.n_levels, S.n_slots, S.lds_elems);
+      for (int i : S.steps) {
+        const SymStep& st = plan.steps[i];
+        std::fprintf(stderr, "  step %d depth %d rank %d sum %d out t%d %s%lld", i, ws.depth[i], st.rank, st.sum, st.out,
+                     ws.lds_off[st.out] >= 0 ? "lds@" : "glob@",
+                     (long long)(ws.lds_off[st.out] >= 0 ? ws.lds_off[st.out] : ws.unit_off[st.out]));
+        for (const SymIn& in : st.ins)
+          std::fprintf(stderr, " | t%d r%d %s%lld m%x v%d s%x", in.tensor, plan.tensors[in.tensor].rank,
+                       plan.tensors[in.tensor].leaf >= 0 ? "leaf" : (ws.lds_off[in.tensor] >= 0 ? "lds@" : "glob@"),
+                       (long long)(ws.lds_off[in.tensor] >= 0 ? ws.lds_off[in.tensor] : ws.unit_off[in.tensor]),
+                       in.mask, in.has_v, in.smask);
+        std::fprintf(stderr, "\n");
+      }
+    }
+  }
+  return QT_OK;
+}
+
+// Device descriptors of the segments (needs the allocated buffers).
+qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
+  auto to_x = [&](int t, const SymIn* si, XIn& x) -> bool {
+    std::memset(&x, 0, sizeof(x));
+    if (ws.lds_off[t] >= 0) {
+      x.ptr = nullptr;
+      x.lds_off = (uint32_t)ws.lds_off[t];
+      x.slot_kind = 1;
+      x.slot = ws.lds_slot[t];
+    } else {
+      DevIn d;
+      build_in(plan, ws, t, 0, 0, si ? si->smask : 0, si ? si->slow : 0, elt, d);
+      x.ptr = d.ptr;
+      x.pt_stride = d.pt_stride;
+      x.sb_stride = d.sb_stride;
+      x.smask = d.smask;
+      x.slow = d.slow;
+      x.slot_kind = d.exp_base >= 0 ? 2 : 0;
+      x.slot = d.exp_base;
+      x.exp_pt = d.exp_pt;
+      x.exp_sb = d.exp_sb;
+    }
+    if (!si) return true;
+    x.has_v = si->has_v;
+    return make_runs(si->mask, kXRuns, x.run_lo, x.run_len, x.run_dst, x.nruns);
+  };
+  size_t total = 0;
+  for (auto& S : ws.segs) {
+    S.xsteps.assign(S.steps.size(), XStep{});
+    std::vector<int> local(plan.steps.size(), -1);
+    for (size_t a = 0; a < S.steps.size(); ++a) local[S.steps[a]] = (int)a;
+    for (size_t a = 0; a < S.steps.size(); ++a) {
+      const SymStep& st = plan.steps[S.steps[a]];
+      XStep& xs = S.xsteps[a];
+      std::memset(&xs, 0, sizeof(xs));
+      to_x(st.out, nullptr, xs.out);
+      xs.r = st.rank;
+      xs.sum = st.sum;
+      xs.n_in = (int)st.ins.size();
+      for (size_t j = 0; j < st.ins.size(); ++j)
+        if (!to_x(st.ins[j].tensor, &st.ins[j], xs.in[j]))
+          return fail(QT_EUNSUPPORTED, "LDS segment input index map has more than 8 runs of bits");
+    }
+    S.units.clear();
+    S.level_off.clear();
+    for (int L = 0; L < S.n_levels; ++L) {
+      S.level_off.push_back((int32_t)S.units.size());
+      for (size_t a = 0; a < S.steps.size(); ++a)
+        if (ws.depth[S.steps[a]] == L) {
+          const int r = plan.steps[S.steps[a]].rank;
+          const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, elt));
+          for (int64_t c = 0; c < chunks; ++c) S.units.push_back(make_uint2((uint32_t)a, (uint32_t)c));
+        }
+    }
+    S.level_off.push_back((int32_t)S.units.size());
+    total += ((S.xsteps.size() * sizeof(XStep) + 255) & ~(size_t)255) +
+             ((S.units.size() * sizeof(uint2) + 255) & ~(size_t)255) +
+             ((S.level_off.size() * sizeof(int32_t) + 255) & ~(size_t)255);
+  }
+  if (!total) return QT_OK;
+  QT_TRY(dev_alloc((char**)&ws.seg_tables, (int64_t)total, ws.bytes));
+  std::vector<char> host(total);
+  size_t off = 0;
+  char* base = (char*)ws.seg_tables;
+  auto put = [&](const void* src, size_t bytes) {
+    std::memcpy(host.data() + off, src, bytes);
+    const char* at = base + off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  for (auto& S : ws.segs) {
+    S.launch.steps = (const XStep*)put(S.xsteps.data(), S.xsteps.size() * sizeof(XStep));
+    S.launch.units = (const uint2*)put(S.units.data(), S.units.size() * sizeof(uint2));
+    S.launch.level_off = (const int32_t*)put(S.level_off.data(), S.level_off.size() * sizeof(int32_t));
+    S.launch.n_levels = S.n_levels;
+    S.launch.n_slots = S.n_slots;
+    S.launch.lds_elems = S.lds_elems;
+  }
+  QT_HIP_CHECK(hipMemcpy(ws.seg_tables, host.data(), total, hipMemcpyHostToDevice));
+  return QT_OK;
 }
 
 qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
   const bool c128 = plan.precision == QT_C128;
   const int elt = c128 ? 16 : 8;
   const int k = (int)plan.slice_vars.size();
+  if (!plan.ws) plan.ws = std::make_unique<qt_plan::Workspace>();
+  auto& ws = *plan.ws;
+  if (!ws.planned) QT_TRY(plan_schedule(plan, ws, elt));
   int64_t chunk = 1;
   if (k > 0) {
     const int64_t n_slices = 1ll << k;
@@ -224,21 +531,19 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     } else {
       int64_t budget = kDefaultBudget;
       if (const char* e = std::getenv("QT_WORKSPACE_BUDGET")) budget = std::max<int64_t>(1, std::atoll(e));
-      const int64_t per = std::max<int64_t>(1, plan.arena1_units * np * elt);
+      const int64_t per = std::max<int64_t>(1, ws.arena1_units * np * elt);
       chunk = 1;
       while (chunk * 2 <= n_slices && chunk * 2 * per <= budget) chunk *= 2;
     }
   }
-  if (!plan.ws) plan.ws = std::make_unique<qt_plan::Workspace>();
-  auto& ws = *plan.ws;
   if (ws.np != np || ws.chunk != chunk) {
     ws.release();
     ws.np = np;
     ws.chunk = chunk;
     int64_t& b = ws.bytes;
     QT_TRY(dev_alloc((char**)&ws.leaves, (int64_t)plan.leaf_block * np * elt, b));
-    QT_TRY(dev_alloc((char**)&ws.arena0, std::max<int64_t>(1, plan.arena0_units) * np * elt, b));
-    QT_TRY(dev_alloc((char**)&ws.arena1, std::max<int64_t>(1, plan.arena1_units) * np * chunk * elt, b));
+    QT_TRY(dev_alloc((char**)&ws.arena0, std::max<int64_t>(1, ws.arena0_units) * np * elt, b));
+    QT_TRY(dev_alloc((char**)&ws.arena1, std::max<int64_t>(1, ws.arena1_units) * np * chunk * elt, b));
     ws.exp1_base = (int64_t)np * plan.n_exp0;
     ws.exp1_count = (int64_t)np * chunk * plan.n_exp1;
     ws.n_exp = ws.exp1_base + ws.exp1_count;
@@ -253,13 +558,18 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
                            hipMemcpyHostToDevice));
     QT_HIP_CHECK(hipMemcpy(ws.ddense, plan.dense_table.data(), plan.dense_table.size() * sizeof(double),
                            hipMemcpyHostToDevice));
-    // step descriptors
+    // streaming step descriptors
     ws.steps.clear();
     ws.step_elems.clear();
     for (const SymStep& st : plan.steps) {
       DevStep d;
       std::memset(&d, 0, sizeof(d));
       const SymTensor& ot = plan.tensors[st.out];
+      ws.step_elems.push_back((int64_t)np * (st.level == 1 ? chunk : 1) << ot.rank);
+      if (ws.lds_off[st.out] >= 0 || ws.seg_of[&st - plan.steps.data()] >= 0) {
+        ws.steps.push_back(d);  // runs inside an LDS segment
+        continue;
+      }
       DevIn od;
       build_in(plan, ws, st.out, 0, 0, 0, 0, elt, od);
       d.out = const_cast<void*>(od.ptr);
@@ -272,11 +582,11 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
       d.out_exp_sb = od.exp_sb;
       for (size_t j = 0; j < st.ins.size(); ++j) {
         const SymIn& si = st.ins[j];
+        if (ws.lds_off[si.tensor] >= 0) return fail(QT_EPLAN, "internal: streaming step reads an LDS tensor");
         if (!build_in(plan, ws, si.tensor, si.mask, si.has_v, si.smask, si.slow, elt, d.in[j]))
-          return fail(QT_EUNSUPPORTED, "input index map has more than 8 runs of bits");
+          return fail(QT_EUNSUPPORTED, "input index map has more than 16 runs of bits");
       }
       ws.steps.push_back(d);
-      ws.step_elems.push_back((int64_t)np * (st.level == 1 ? chunk : 1) << ot.rank);
     }
     ws.finals.clear();
     for (int t : plan.finals) {
@@ -292,6 +602,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     }
     if (!ws.finals.empty())
       QT_HIP_CHECK(hipMemcpy(ws.dfinal, ws.finals.data(), ws.finals.size() * sizeof(DevIn), hipMemcpyHostToDevice));
+    QT_TRY(build_segment_tables(plan, ws, elt));
     plan.info.slice_batch = chunk;
   }
   if (ws.per_slice_cap < (int64_t)np * n_range) {
@@ -349,7 +660,23 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
       return launch_step(d, c128, scaled, ws.exps, ws.maxbits, ws.step_elems[i], stream, &launches, nullptr);
     });
   };
-  for (int i = 0; i < plan.n_prefix_steps; ++i) QT_HIP_CHECK(step(ws.steps[i], i));
+  auto run_op = [&](const qt_plan::Workspace::Op& op, int64_t cb) -> hipError_t {
+    if (op.seg < 0) {
+      DevStep d = ws.steps[op.step];
+      d.chunk_base = cb;
+      return step(d, op.step);
+    }
+    auto& S = ws.segs[op.seg];
+    XLaunch x = S.launch;
+    x.chunk_base = cb;
+    x.lg_nsb = S.level == 1 ? ilog2(ws.chunk) : 0;
+    const int64_t items = (int64_t)np * (S.level == 1 ? ws.chunk : 1);
+    ++launches;
+    return timed(plan, stream, QT_KCLASS_LDS, S.bytes_c64 * eb * items, S.flops * items, [&] {
+      return launch_lds_exec(x, items, ws.waves, c128, scaled, ws.exps, ws.maxbits, stream);
+    });
+  };
+  for (const auto& op : ws.prefix_ops) QT_HIP_CHECK(run_op(op, 0));
   DevFinal f{};
   f.n_factors = (int)ws.finals.size();
   f.slice_begin = begin;
@@ -371,11 +698,7 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
         }));
         ++launches;
       }
-      for (size_t i = plan.n_prefix_steps; i < ws.steps.size(); ++i) {
-        DevStep d = ws.steps[i];
-        d.chunk_base = cb;
-        QT_HIP_CHECK(step(d, (int)i));
-      }
+      for (const auto& op : ws.slice_ops) QT_HIP_CHECK(run_op(op, cb));
       f.lg_nsb = ilog2(C);
       f.chunk_base = cb;
       QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {

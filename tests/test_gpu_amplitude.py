@@ -28,7 +28,7 @@ def slice_err(got, want):
     return np.abs(np.asarray(got) - np.asarray(want)).max() / np.abs(want).max()
 
 
-def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batch=0, step=None):
+def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batch=0, step=None, plain=False):
     spec = N.amplitude_network(n, edges, p, z)
     net = api.Network(spec)
     if k == 0:
@@ -45,7 +45,7 @@ def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batc
             pre = [v for v in full if v not in sl][:step]
             rest, _ = net.order_greedy(algo, exclude=sl + pre)
             order, groups = pre + rest, [(step, sl)]
-    return net, api.Plan(net, order, groups, precision=precision, slice_batch=slice_batch)
+    return net, api.Plan(net, order, groups, precision=precision, slice_batch=slice_batch, plain=plain)
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
@@ -160,6 +160,35 @@ def test_disconnected_graph(precision):
     assert rel(plan.contract_amplitude(g, b), want) < TOL[precision]
     net, plan = build(8, 2, edges, k=2, precision=precision)
     assert rel(plan.contract_amplitude(g, b), want) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("max_rank", ["4", "14"])
+def test_fused_segments_match_streaming(precision, max_rank, monkeypatch):
+    # LDS segments (steps up to the rank limit fused) against one launch per
+    # step; both against the oracle per slice.  A low limit mixes segments
+    # and streaming steps; a small LDS budget forces spills to global memory.
+    n, p, k = 24, 3, 5
+    edges = generate_regular_graph(n, 3, 2)
+    g, b = qaoa_params(p, 1, seed=4)
+    want = oracle.sliced_values(oracle.amplitude_network(n, edges, g[0], b[0]), *_plan_of(n, p, edges, k))
+    monkeypatch.setenv("QT_LDS_MAX_RANK", max_rank)
+    for budget in ("163840", "65536", "32768", "4096"):
+        monkeypatch.setenv("QT_LDS_BYTES", budget)
+        net, plan = build(n, p, edges, k=k, precision=precision)
+        _, per = plan.contract_batch(g, b, per_slice=True)
+        assert slice_err(per[0], want) < TOL[precision], budget
+        _, again = plan.contract_batch(g, b, per_slice=True)
+        assert np.array_equal(per, again), budget
+    net, plain = build(n, p, edges, k=k, precision=precision, plain=True, slice_batch=1)
+    _, per = plain.contract_batch(g, b, per_slice=True)
+    assert slice_err(per[0], want) < TOL[precision]
+
+
+def _plan_of(n, p, edges, k):
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(k, algo="min_fill")
+    return sch.order, sch.groups
 
 
 def test_bitwise_reproducible():

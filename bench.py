@@ -27,7 +27,7 @@ METRIC = "QAOA amplitudes/s and edge-energies/s vs plain complex128 path at stat
 HBM_PEAK_GBS = 8000.0
 
 
-def build_plan(precision, slice_batch=0, plain=False):
+def build_plan(precision, slice_batch=0, plain=False, fold=False):
     from paper_2012_02430_amd import api
     from paper_2012_02430_amd import network as N
     from workloads import regular_graph
@@ -36,7 +36,8 @@ def build_plan(precision, slice_batch=0, plain=False):
     edges = regular_graph(n, 3, 0)
     net = api.Network(N.amplitude_network(n, edges, p))
     sch = net.plan_slicing(k, algo="min_fill")
-    plan = api.Plan(net, sch.order, sch.groups, precision=precision, slice_batch=slice_batch, plain=plain)
+    plan = api.Plan(net, sch.order, sch.groups, precision=precision, slice_batch=slice_batch, plain=plain,
+                    fold_prefix=fold)
     return net, sch, plan, edges
 
 
@@ -100,7 +101,7 @@ def main():
     g, b = qaoa_params(2, 1, seed=1)
     g, b = g[0], b[0]
 
-    net, sch, plan, edges = build_plan("c64")
+    net, sch, plan, edges = build_plan("c64", fold=True)
     _, _, plain, _ = build_plan("c128", slice_batch=1, plain=True)
     print(f"[bench] plan: width {sch.width} (prefix {sch.prefix_width}, slice {sch.slice_width}), "
           f"unsliced {sch.unsliced_width}, step {sch.step}, 256 slices", flush=True)

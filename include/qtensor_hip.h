@@ -123,10 +123,14 @@ typedef struct {
   int32_t flags;        /* QT_PLAN_* bits */
 } qt_plan_desc;
 
-/* Plan flags.  QT_PLAN_PLAIN: one launch per bucket step (no fusion of small
- * steps into LDS-resident segments); with slice_batch = 1 this is the plain
- * path, one launch per step per slice. */
-enum { QT_PLAN_PLAIN = 1 };
+/* Plan flags.
+ *   QT_PLAN_PLAIN: one launch per bucket step (no fusion of small steps into
+ *     LDS-resident segments); with slice_batch = 1 this is the plain path,
+ *     one launch per step per slice.
+ *   QT_PLAN_FOLD_PREFIX: run the serial prefix inside every slice with the
+ *     slice variables already fixed (same order, same per-slice values),
+ *     instead of once before the slices. */
+enum { QT_PLAN_PLAIN = 1, QT_PLAN_FOLD_PREFIX = 2 };
 
 typedef struct {
   double re, im;        /* mantissa */
@@ -230,6 +234,13 @@ qt_status qt_profile_enable(qt_plan* plan, int32_t enable);
  * out[QT_KCLASS_COUNT]; with `reset` != 0 the accumulated statistics are
  * cleared afterwards. */
 qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_t reset);
+
+/* Host-only description of the launch schedule the plan would run with the
+ * current environment: LDS-executor segments (steps, dependency levels,
+ * LDS bytes, staged inputs) and streaming steps, as JSON.  Writes at most
+ * `cap` bytes (NUL-terminated) to `buf` and the full length to *needed;
+ * QT_EINVAL if `buf` is too small.  Touches no GPU. */
+qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t cap, int64_t* needed);
 
 void qt_free_plan(qt_plan* plan);
 void qt_free_network(qt_network* net);

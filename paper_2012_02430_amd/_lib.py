@@ -65,6 +65,7 @@ class qt_plan_desc(ctypes.Structure):
 
 
 QT_PLAN_PLAIN = 1
+QT_PLAN_FOLD_PREFIX = 2
 
 
 class qt_amp(ctypes.Structure):
@@ -109,6 +110,7 @@ SIGNATURES = {
     "qt_plan_get_info": (c_int32, [c_void_p, POINTER(qt_plan_info)]),
     "qt_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qt_profile_read": (c_int32, [c_void_p, POINTER(qt_kernel_stats), c_int32]),
+    "qt_plan_describe": (c_int32, [c_void_p, ctypes.c_char_p, c_int64, POINTER(c_int64)]),
     "qt_free_plan": (None, [c_void_p]),
     "qt_free_network": (None, [c_void_p]),
     "qt_last_error": (ctypes.c_char_p, []),

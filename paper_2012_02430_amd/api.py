@@ -56,8 +56,8 @@ class Network:
         self._keep = None
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            L.load().qt_free_network(self.handle)
+        if getattr(self, "handle", None) and L is not None and L._LIB is not None:
+            L._LIB.qt_free_network(self.handle)
             self.handle = None
 
     # ---- planning (host only, Section V-A / VI-C / VI-D)
@@ -118,7 +118,8 @@ class SlicingSchedule:
 class Plan:
     """A compiled plan (``qt_load_plan``) over a loaded network."""
 
-    def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False):
+    def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False,
+                 fold_prefix=False):
         lib = L.load()
         self.network = network
         groups = list(groups)
@@ -133,15 +134,16 @@ class Plan:
                            ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(lens, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(sv, ctypes.POINTER(ctypes.c_int32)),
-                           PRECISIONS[precision], int(slice_batch), L.QT_PLAN_PLAIN if plain else 0)
+                           PRECISIONS[precision], int(slice_batch),
+                           (L.QT_PLAN_PLAIN if plain else 0) | (L.QT_PLAN_FOLD_PREFIX if fold_prefix else 0))
         h = ctypes.c_void_p()
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
         self.p = network.spec.p
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            L.load().qt_free_plan(self.handle)
+        if getattr(self, "handle", None) and L is not None and L._LIB is not None:
+            L._LIB.qt_free_plan(self.handle)
             self.handle = None
 
     def info(self) -> L.qt_plan_info:
@@ -152,6 +154,16 @@ class Plan:
     @property
     def n_slices(self) -> int:
         return self.info().n_slices
+
+    def describe(self) -> dict:
+        """Launch schedule (segments, levels, LDS bytes, streaming steps); host only."""
+        import json
+
+        need = ctypes.c_int64()
+        L.load().qt_plan_describe(self.handle, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(need.value)
+        L.check(L.load().qt_plan_describe(self.handle, buf, need.value, ctypes.byref(need)))
+        return json.loads(buf.value.decode())
 
     def profile_enable(self, on=True):
         L.check(L.load().qt_profile_enable(self.handle, 1 if on else 0))

@@ -1,19 +1,21 @@
-// LDS executor: one workgroup per batch item runs a segment of bucket steps
-// whose tensors are small enough to live in the workgroup's LDS.
+// LDS executor: one workgroup per batch item (point, slice) runs a segment
+// of bucket steps whose tensors are small enough to live in its LDS.
 //
-// The steps of a segment are grouped into dependency levels (a step's level
-// is one more than the deepest step of the segment that produced one of its
-// inputs), and all steps of a level run concurrently: the level's work is
-// cut into 64-element units of one step each, handed round-robin to the
-// workgroup's wavefronts, with a single barrier between levels.  A unit is
-// uniform over its wavefront, so its descriptors are read with scalar loads.
-// Each element computes, like the streaming kernels,
-//   out[x] = prod_{j without v} T_j[x] * sum_{v} prod_{j with v} T_j[x, v],
-// reading operands from LDS or global memory (results of earlier launches,
-// gate tensors) and writing the output to LDS or global memory.
+// At the start the workgroup materialises its point's gate table and copies
+// the segment's external inputs (results of earlier launches) into LDS; from
+// then on every operand is read from LDS.  The steps are grouped into
+// dependency levels (a step's level is one more than the deepest step of
+// the segment that produced one of its inputs) and all steps of a level run
+// concurrently: the level's work is cut into units of 64 x EPU outputs of
+// one step, handed round-robin to the wavefronts, with one barrier between
+// levels.  A unit is uniform over its wavefront, so its descriptor is read
+// with scalar loads.  Each output element computes, like the streaming
+// kernels,
+//   out[x] = prod_{j} T_j[x, v=0] + prod_{j} T_j[x, v=1]
+// (an input without the summed variable contributes the same value to both
+// products), and is written to LDS or, when it leaves the segment, to
+// global memory.
 #include <hip/hip_runtime.h>
-
-#include <type_traits>
 
 #include "qt_internal.h"
 
@@ -30,15 +32,27 @@ __device__ __forceinline__ float2 xadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ double2 xadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 xscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ double2 xscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-template <typename E> __device__ __forceinline__ E xone();
-template <> __device__ __forceinline__ float2 xone<float2>() { return make_float2(1.f, 0.f); }
-template <> __device__ __forceinline__ double2 xone<double2>() { return make_double2(1.0, 0.0); }
 
-__device__ __forceinline__ uint32_t xpext_runs(uint32_t x, const XIn& in) {
+template <typename E> struct XReal;
+template <> struct XReal<float2> { using R = float; };
+template <> struct XReal<double2> { using R = double; };
+
+template <typename E> struct XRaw;
+template <> struct alignas(8) XRaw<float2> { float x, y; };
+template <> struct alignas(16) XRaw<double2> { double x, y; };
+// Global pointers typed in the global address space so that they are never
+// merged with LDS pointers into generic (flat) accesses.
+template <typename E>
+using gconst_t = const __attribute__((address_space(1))) XRaw<E>*;
+template <typename E>
+using gmut_t = __attribute__((address_space(1))) XRaw<E>*;
+
+template <int N>
+__device__ __forceinline__ uint32_t xpext_all(uint32_t x, const uint8_t (&lo)[N], const uint8_t (&len)[N],
+                                              const uint8_t (&dst)[N]) {
   uint32_t r = 0;
 #pragma unroll
-  for (int i = 0; i < kXRuns; ++i)
-    if (i < in.nruns) r |= ((x >> in.run_lo[i]) & ((1u << in.run_len[i]) - 1u)) << in.run_dst[i];
+  for (int i = 0; i < N; ++i) r |= ((x >> lo[i]) & ((1u << len[i]) - 1u)) << dst[i];
   return r;
 }
 
@@ -54,14 +68,14 @@ __device__ __forceinline__ uint32_t xpext_bits(uint64_t x, uint32_t m) {
   return r;
 }
 
+// Power of two that brings max|x| into [0.5, 1), clamped so that 2^-shift is
+// a normal float.
 __device__ __forceinline__ int xshift(uint32_t maxbits) {
   if (maxbits == 0) return 0;
-  return ilogbf(__uint_as_float(maxbits)) + 1;
+  const int s = ilogbf(__uint_as_float(maxbits)) + 1;
+  return s < -126 ? -126 : (s > 127 ? 127 : s);
 }
-
-template <typename E> struct XReal;
-template <> struct XReal<float2> { using R = float; };
-template <> struct XReal<double2> { using R = double; };
+__device__ __forceinline__ float xpow2neg(int sh) { return __int_as_float((127 - sh) << 23); }
 
 struct XCtx {
   uint32_t pt, sb;
@@ -69,73 +83,79 @@ struct XCtx {
   uint32_t lane;
 };
 
-// One work unit: EPU x 64 consecutive outputs of one step.  Every load of
-// the unit is issued before any arithmetic; inputs without the summed
-// variable are read twice at the same index (no branch between the two
-// products).
 template <typename E, bool SCALED, int NIN, int EPU>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,
                                        uint32_t* __restrict__ gmax) {
   using R = typename XReal<E>::R;
-  const E* src[NIN];
+  const uint32_t cx = chunk * EPU * 64u;
+  uint32_t base[NIN], lp[NIN];
   R sc[NIN];
   int eacc = 0;
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {
-    const XIn& in = st.in[j];
-    if (in.ptr == nullptr)
-      src[j] = lds + in.lds_off;
-    else
-      src[j] = reinterpret_cast<const E*>(in.ptr) + (int64_t)c.pt * in.pt_stride + (int64_t)c.sb * in.sb_stride +
-               ((int64_t)xpext_bits(c.sid, in.smask) << in.slow);
+    const XOp& in = st.in[j];
+    base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
+    const uint32_t pc = xpext_all(cx, in.run_lo, in.run_len, in.run_dst);
+    lp[j] = xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc;
     sc[j] = (R)1;
-    if (SCALED && in.slot_kind != 0) {
-      int sh, ex;
-      if (in.slot_kind == 1) {
-        sh = xshift(smax[in.slot]);
-        ex = sexp[in.slot];
-      } else {
-        const int g = in.slot + (int)c.pt * in.exp_pt + (int)c.sb * in.exp_sb;
-        sh = xshift(gmax[g]);
-        ex = gexps[g];
-      }
-      sc[j] = (R)ldexp(1.0, -sh);
-      eacc += ex + sh;
+    if (SCALED && in.slot >= 0) {
+      const int sh = xshift(smax[in.slot]);
+      sc[j] = (R)xpow2neg(sh);
+      eacc += sexp[in.slot] + sh;
     }
   }
-  const uint32_t n = 1u << st.r;
   E a0[EPU][NIN], a1[EPU][NIN];
 #pragma unroll
   for (int e = 0; e < EPU; ++e) {
-    uint32_t x = (chunk * EPU + e) * 64u + c.lane;
-    x = x < n ? x : 0u;
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
-      const int hv = st.in[j].has_v;
-      const uint32_t idx = xpext_runs(x, st.in[j]) << hv;
-      a0[e][j] = src[j][idx];
-      a1[e][j] = src[j][idx + hv];
+      const uint32_t hv = (uint32_t)st.in[j].has_v;
+      const uint32_t i = base[j] + ((lp[j] + st.in[j].ep[e]) << hv);
+      a0[e][j] = lds[i];
+      a1[e][j] = lds[i + hv];
     }
   }
-  const XIn& o = st.out;
-  E* dst = o.ptr == nullptr
-               ? lds + o.lds_off
-               : reinterpret_cast<E*>(const_cast<void*>(o.ptr)) + (int64_t)c.pt * o.pt_stride + (int64_t)c.sb * o.sb_stride;
+  const XOut& o = st.out;
+  const uint32_t n = 1u << st.r;
   float m = 0.f;
+  E res[EPU];
 #pragma unroll
   for (int e = 0; e < EPU; ++e) {
-    const uint32_t x = (chunk * EPU + e) * 64u + c.lane;
-    E t0 = xscale(a0[e][0], sc[0]), t1 = xscale(a1[e][0], sc[0]);
+    E t0 = a0[e][0], t1 = a1[e][0];
+    if (SCALED) {
+      t0 = xscale(t0, sc[0]);
+      t1 = xscale(t1, sc[0]);
+    }
 #pragma unroll
     for (int j = 1; j < NIN; ++j) {
-      t0 = xmul(t0, xscale(a0[e][j], sc[j]));
-      t1 = xmul(t1, xscale(a1[e][j], sc[j]));
+      E x0 = a0[e][j], x1 = a1[e][j];
+      if (SCALED) {
+        x0 = xscale(x0, sc[j]);
+        x1 = xscale(x1, sc[j]);
+      }
+      t0 = xmul(t0, x0);
+      t1 = xmul(t1, x1);
     }
-    const E res = st.sum ? xadd(t0, t1) : t0;
-    if (x < n) {
-      dst[x] = res;
-      if (SCALED) m = fmaxf(m, fmaxf(fabsf((float)res.x), fabsf((float)res.y)));
+    res[e] = st.sum ? xadd(t0, t1) : t0;
+    const uint32_t x = cx + e * 64u + c.lane;
+    if (SCALED && x < n) m = fmaxf(m, fmaxf(fabsf((float)res[e].x), fabsf((float)res[e].y)));
+  }
+  if (o.ptr == nullptr) {
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) {
+      const uint32_t x = cx + e * 64u + c.lane;
+      if (x < n) lds[o.lds_off + x] = res[e];
+    }
+  } else {
+    gmut_t<E> g = (gmut_t<E>)(reinterpret_cast<E*>(o.ptr) + (int64_t)c.pt * o.pt_stride + (int64_t)c.sb * o.sb_stride);
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) {
+      const uint32_t x = cx + e * 64u + c.lane;
+      if (x < n) {
+        g[x].x = res[e].x;
+        g[x].y = res[e].y;
+      }
     }
   }
   if (SCALED) {
@@ -154,23 +174,48 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
   }
 }
 
-template <typename E, bool SCALED, int EPU>
-__device__ __forceinline__ void x_dispatch(const XStep& st, uint32_t chunk, const XCtx& c, E* lds, uint32_t* smax,
-                                           int* sexp, int* gexps, uint32_t* gmax) {
-  switch (st.n_in) {
-    case 1: x_unit<E, SCALED, 1, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 2: x_unit<E, SCALED, 2, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 3: x_unit<E, SCALED, 3, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 4: x_unit<E, SCALED, 4, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 5: x_unit<E, SCALED, 5, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 6: x_unit<E, SCALED, 6, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    case 7: x_unit<E, SCALED, 7, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
-    default: x_unit<E, SCALED, 8, EPU>(st, chunk, c, lds, smax, sexp, gexps, gmax); break;
+// Gate table entry t of the workgroup's point (layout: x_gate_off), FP64
+// trigonometry rounded to the element type (Section III-A conventions).
+template <typename E>
+__device__ __forceinline__ E x_gate(int t, const double* prm, int p) {
+  using R = typename XReal<E>::R;
+  E v;
+  double re = 0.0, im = 0.0;
+  if (t < 10) {
+    const int a = t >> 1, i = t & 1;  // |+>, <0|, <1|, observable (two pairs)
+    if (a == 0) re = 1.0;
+    else if (a == 1) re = i == 0 ? 1.0 : 0.0;
+    else if (a == 2) re = i == 0 ? 0.0 : 1.0;
+    else if (a == 3) re = i == 0 ? 0.0 : 1.0;
+    else re = i == 0 ? 1.0 : 0.0;
+  } else {
+    const int u = t - 10, k = u >> 4, g = (u >> 2) & 3, i = u & 3;
+    double sn, cs;
+    const bool diag = i == 0 || i == 3;
+    if (g < 2) {
+      sincos(prm[k], &sn, &cs);
+      re = diag ? 1.0 : cs;
+      im = diag ? 0.0 : (g == 0 ? -sn : sn);
+    } else {
+      sincos(prm[p + k], &sn, &cs);
+      re = diag ? cs : 0.0;
+      im = diag ? 0.0 : (g == 2 ? -sn : sn);
+    }
   }
+  v.x = (R)re;
+  v.y = (R)im;
+  return v;
 }
 
+// The step, unit, level and copy tables are separate read-only, non-aliasing
+// arguments so that their (wavefront-uniform) reads become scalar loads.
 template <typename E, bool SCALED>
-__global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, int* __restrict__ gexps, uint32_t* __restrict__ gmax) {
+__global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, const XStep* __restrict__ steps,
+                                                           const uint2* __restrict__ units,
+                                                           const int32_t* __restrict__ level_off,
+                                                           const XCopy* __restrict__ copies,
+                                                           int* __restrict__ gexps, uint32_t* __restrict__ gmax,
+                                                           uint64_t* __restrict__ trace) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int slots16 = (X.n_slots + 3) & ~3;
   uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
@@ -191,19 +236,62 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, int*
     smax[i] = 0u;
     sexp[i] = 0;
   }
+  if (tid < 2) {
+    lds[tid].x = 1;
+    lds[tid].y = 0;
+  }
+  if (tid < x_gate_elems(X.p)) lds[kXGate + tid] = x_gate<E>(tid, X.params + (int64_t)c.pt * 2 * X.p, X.p);
+  // stage the segment's external inputs (with their scale slots)
+  for (int e = wave; e < X.n_copies; e += nw) {
+    const XCopy& cp = copies[e];
+    gconst_t<E> src = (gconst_t<E>)(reinterpret_cast<const E*>(cp.ptr) + (int64_t)c.pt * cp.pt_stride +
+                                     (int64_t)c.sb * cp.sb_stride + ((int64_t)xpext_bits(c.sid, cp.smask) << cp.slow));
+    for (uint32_t i0 = 0; i0 < cp.n; i0 += 256) {
+      E v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * 64 + c.lane;
+        if (i < cp.n) {
+          v[q].x = src[i].x;
+          v[q].y = src[i].y;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * 64 + c.lane;
+        if (i < cp.n) lds[cp.lds_off + i] = v[q];
+      }
+    }
+    if (SCALED && c.lane == 0 && cp.gslot >= 0) {
+      const int g = cp.gslot + (int)c.pt * cp.exp_pt + (int)c.sb * cp.exp_sb;
+      smax[cp.lslot] = gmax[g];
+      sexp[cp.lslot] = gexps[g];
+    }
+  }
   __syncthreads();
 
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  const bool tracing = trace != nullptr && blockIdx.x == 0 && tid == 0;
+  if (tracing) trace[0] = wall_clock64();
   for (int L = 0; L < X.n_levels; ++L) {
-    const int u_end = X.level_off[L + 1];
-    for (int u = X.level_off[L] + wave; u < u_end; u += nw) {
-      const uint2 un = X.units[u];
-      const XStep& st = X.steps[un.x];
-      if (st.r >= kXBigRank)
-        x_dispatch<E, SCALED, (sizeof(E) == 8 ? kXEpu : kXEpu / 2)>(st, un.y, c, lds, smax, sexp, gexps, gmax);
-      else
-        x_dispatch<E, SCALED, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+    const int u_end = level_off[L + 1];
+    for (int u = level_off[L] + wave; u < u_end; u += nw) {
+      const uint2 un = units[u];
+      const XStep& st = steps[un.x];
+      const bool big = st.r >= kXBigRank;
+      if (st.n_in <= 2) {
+        if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+      } else if (st.n_in <= 4) {
+        if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+      } else {
+        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+      }
     }
     __syncthreads();
+    if (tracing) trace[L + 1] = wall_clock64();
   }
 }
 
@@ -219,23 +307,20 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
   if (n_items == 0 || x.n_levels == 0) return hipSuccess;
   const size_t smem = lds_exec_smem_bytes(x.n_slots, x.lds_elems, c128);
   const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
-  hipError_t e;
-  if (c128) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_exec<double2, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lds_exec<double2, false>), grid, block, smem, stream, x, exps, maxbits);
-  } else if (scaled) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_exec<float2, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lds_exec<float2, true>), grid, block, smem, stream, x, exps, maxbits);
-  } else {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_exec<float2, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lds_exec<float2, false>), grid, block, smem, stream, x, exps, maxbits);
-  }
+  const void* fn = c128 ? reinterpret_cast<const void*>(&k_lds_exec<double2, false>)
+                        : (scaled ? reinterpret_cast<const void*>(&k_lds_exec<float2, true>)
+                                  : reinterpret_cast<const void*>(&k_lds_exec<float2, false>));
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  if (c128)
+    hipLaunchKernelGGL((k_lds_exec<double2, false>), grid, block, smem, stream, x, x.steps, x.units, x.level_off,
+                       x.copies, exps, maxbits, x.trace);
+  else if (scaled)
+    hipLaunchKernelGGL((k_lds_exec<float2, true>), grid, block, smem, stream, x, x.steps, x.units, x.level_off,
+                       x.copies, exps, maxbits, x.trace);
+  else
+    hipLaunchKernelGGL((k_lds_exec<float2, false>), grid, block, smem, stream, x, x.steps, x.units, x.level_off,
+                       x.copies, exps, maxbits, x.trace);
   return hipGetLastError();
 }
 

@@ -316,8 +316,11 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       return QT_OK;
     };
 
+    // With QT_PLAN_FOLD_PREFIX every step runs per slice (slice variables
+    // fixed from the start).
+    const int s_exec = (k > 0 && (d->flags & QT_PLAN_FOLD_PREFIX)) ? 0 : s;
     for (int i = 0; i < n_order; ++i) {
-      const bool post = k > 0 && i >= s;
+      const bool post = k > 0 && i >= s_exec;
       const int v = plan->order[i];
       std::vector<int> ins = std::move(buckets[i]);
       if (ins.empty()) continue;

@@ -94,44 +94,100 @@ struct DevStep {
 };
 
 // ------------------------------------------------- LDS executor descriptors
-// Operand (or output) of a step run by the LDS executor: in LDS when ptr is
-// null (element offset lds_off inside the workgroup's tensor area), else in
-// global memory at ptr + pt*pt_stride + sb*sb_stride + (pext(sid, smask) << slow).
+// Operand of a step run by the LDS executor; always in LDS (gate table,
+// staged input or internal tensor).  Element index for output x:
+//   lds_off + (pext(sid, smask) << slow) + (pext(x, mask) << has_v) + v
+// with pext(x) split as pext(unit base) + ep[e] + pext(lane) for
+// x = unit base + 64 e + lane.
 constexpr int kXRuns = 8;   // executor steps have outputs of rank <= 16
-// Work unit of the executor: steps of rank >= kXBigRank are cut into units
-// of kXEpu * 64 outputs (kXEpu per lane), smaller steps into 64-output units.
-// (complex128 uses kXEpu / 2 per lane and units of half the size).
-constexpr int kXBigRank = 8;
-constexpr int kXEpu = 4;
-constexpr int kXMaxThreads = 512;
-inline int64_t x_unit_elems(int rank, int elt) { return rank >= kXBigRank ? 64 * (elt == 8 ? kXEpu : kXEpu / 2) : 64; }
-struct XIn {
-  const void* ptr;
-  int64_t pt_stride;
-  int64_t sb_stride;
+struct XOp {  // 32-bit fields only: they are read with scalar loads
   uint32_t lds_off;
-  uint32_t smask;
+  uint32_t smask;   // slice-id bits (gate operands on slice variables)
   int32_t slow;
   int32_t has_v;
-  int32_t nruns;
-  int32_t slot_kind;  // 0: unscaled; 1: LDS slot; 2: global slot
-  int32_t slot;       // LDS slot index, or global slot base
-  int32_t exp_pt;
-  int32_t exp_sb;
+  int32_t slot;     // LDS scale slot, -1: unscaled
   int32_t pad;
+  uint32_t ep[4];   // pext(64 e) for the unit's elements e
   uint8_t run_lo[kXRuns];
   uint8_t run_len[kXRuns];
   uint8_t run_dst[kXRuns];
 };
 
+// Output of an executor step: LDS (ptr null) or global memory.
+struct XOut {
+  void* ptr;
+  int64_t pt_stride;
+  int64_t sb_stride;
+  uint32_t lds_off;
+  int32_t slot_kind;  // 0: unscaled; 1: LDS slot; 2: global slot
+  int32_t slot;
+  int32_t exp_pt;
+  int32_t exp_sb;
+  int32_t pad;
+};
+
 struct XStep {
-  XIn out;   // output location and scale slot (runs unused)
+  XOut out;
   int32_t r;
   int32_t sum;
   int32_t n_in;
   int32_t pad;
-  XIn in[kMaxIn];
+  XOp in[kMaxIn];
 };
+
+// Work unit of the executor: steps of rank >= kXBigRank are cut into units
+// of kXEpu * 64 outputs (kXEpu per lane), smaller steps into 64-output units
+// (complex128 uses kXEpu / 2 per lane; steps with more than 4 inputs use
+// half as many again).  Steps are padded to 2, 4 or 8 inputs.
+constexpr int kXBigRank = 8;
+constexpr int kXEpu = 4;
+constexpr int kXMaxThreads = 1024;
+inline int x_nin_class(int n_in) { return n_in <= 2 ? 2 : (n_in <= 4 ? 4 : 8); }
+inline int x_epu(int rank, int n_in, int elt) {
+  if (rank < kXBigRank) return 1;
+  int epu = elt == 8 ? kXEpu : kXEpu / 2;
+  if (x_nin_class(n_in) == 8) epu = epu > 1 ? epu / 2 : 1;
+  return epu;
+}
+inline int64_t x_unit_elems(int rank, int n_in, int elt) { return 64 * x_epu(rank, n_in, elt); }
+
+// Global tensor copied into LDS at the start of an executor launch (the
+// block of one batch item: 2^rank elements, or the slice-selected block of a
+// prefix tensor).
+struct XCopy {
+  const void* ptr;
+  int64_t pt_stride;
+  int64_t sb_stride;
+  uint32_t smask;
+  int32_t slow;
+  uint32_t lds_off;
+  uint32_t n;
+  int32_t gslot;  // global scale slot base (-1: unscaled)
+  int32_t exp_pt;
+  int32_t exp_sb;
+  int32_t lslot;  // LDS scale slot
+};
+
+// LDS element area of an executor workgroup: element 0-1 the identity
+// operand (1 + 0i), then the gate table of the workgroup's point, then
+// staged and internal tensors.  Gate table (element offsets): |+> (1, 1) at
+// 2, <0| at 4, <1| at 6, the edge observable at 8, and for layer k (0-based)
+// ZZ, ZZ^dagger, RX, RX^dagger at 12 + 16k + {0, 4, 8, 12} (10 + 16p entries).
+constexpr int kXGate = 2;
+__host__ __device__ inline int x_gate_elems(int p) { return 10 + 16 * p; }
+__host__ __device__ inline int x_tensor_base(int p) { return (kXGate + x_gate_elems(p) + 1) & ~1; }
+inline int x_gate_off(int kind, int layer) {
+  switch (kind) {
+    case QT_T_VEC_PLUS: return kXGate + 0;
+    case QT_T_BRA_BIT: return kXGate + (layer ? 4 : 2);
+    case QT_T_OBS_CUT: return kXGate + 6;
+    case QT_T_ZZ: return kXGate + 10 + 16 * (layer - 1);
+    case QT_T_ZZ_DAG: return kXGate + 14 + 16 * (layer - 1);
+    case QT_T_RX: return kXGate + 18 + 16 * (layer - 1);
+    case QT_T_RX_DAG: return kXGate + 22 + 16 * (layer - 1);
+    default: return -1;
+  }
+}
 
 // One launch of the executor: every workgroup runs the same level schedule
 // for its batch item (pt, sb).
@@ -139,11 +195,16 @@ struct XLaunch {
   const XStep* steps;
   const uint2* units;      // (step, 64-element chunk) work units, level by level
   const int32_t* level_off;  // n_levels + 1 offsets into units
+  const XCopy* copies;     // inputs staged into LDS at the start
+  const double* params;    // [points][2p]: gammas then betas
   int32_t n_levels;
   int32_t lg_nsb;
   int64_t chunk_base;
   int32_t n_slots;         // LDS scale slots
-  int32_t lds_elems;       // tensor area, elements
+  int32_t lds_elems;       // LDS element area, elements
+  int32_t n_copies;
+  int32_t p;
+  uint64_t* trace;         // optional: workgroup 0 stores wall_clock64() after each level
 };
 
 // Leaf (gate) tensor materialisation record.

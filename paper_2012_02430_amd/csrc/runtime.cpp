@@ -70,6 +70,7 @@ struct qt_plan::Workspace {
     int lds_elems = 0;
     double bytes_c64 = 0, flops = 0;  // per item
     std::vector<XStep> xsteps;
+    std::vector<XCopy> copies;
     std::vector<uint2> units;
     std::vector<int32_t> level_off;
     XLaunch launch{};
@@ -84,14 +85,19 @@ struct qt_plan::Workspace {
   std::vector<int> seg_of, depth;
   std::vector<int64_t> lds_off;
   std::vector<int> lds_slot;
+  std::vector<int> staged_in;  // segment that stages the tensor into LDS, -1: none
   std::vector<int64_t> unit_off;
   int64_t arena0_units = 0, arena1_units = 0;
+  // QT_DEBUG_LEVEL_TRACE: per-level clock of workgroup 0 of each segment launch
+  bool trace_on = false;
+  uint64_t* trace_buf = nullptr;
 
   void release() {
     for (void* p : {leaves, arena0, arena1, (void*)exps, (void*)maxbits, (void*)params, (void*)dleaves,
-                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums, seg_tables})
+                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums, seg_tables, (void*)trace_buf})
       if (p) (void)hipFree(p);
     seg_tables = nullptr;
+    trace_buf = nullptr;
     leaves = arena0 = arena1 = nullptr;
     exps = nullptr;
     maxbits = nullptr;
@@ -270,7 +276,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   ws.segs.clear();
   const bool plain = (plan.flags & QT_PLAN_PLAIN) != 0;
   const int max_rank = std::min(16, env_int("QT_LDS_MAX_RANK", 14));
-  ws.waves = std::max(1, std::min(kXMaxThreads / 64, env_int("QT_LDS_WAVES", 8)));
+  ws.waves = std::max(1, std::min(kXMaxThreads / 64, env_int("QT_LDS_WAVES", 16)));
   const int64_t lds_bytes = std::min(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
   const int nsteps = (int)plan.steps.size();
   const int ntens = (int)plan.tensors.size();
@@ -278,6 +284,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   ws.depth.assign(nsteps, 0);
   ws.lds_off.assign(ntens, -1);
   ws.lds_slot.assign(ntens, -1);
+  ws.staged_in.assign(ntens, -1);
   // Depth and LDS placement of a candidate segment (steps in plan order).
   // Returns false when some tensor produced and consumed inside does not
   // fit: a global buffer must never be written and read in the same launch
@@ -294,16 +301,26 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       }
       n_levels = std::max(n_levels, dep[i] + 1);
     }
-    std::vector<Interval> cands;
+    std::vector<Interval> cands, ext;
     for (int i : steps) {
       const int t = plan.steps[i].out;
       const int c = plan.tensors[t].consumer;
       if (c >= 0 && in_seg[c]) cands.push_back({t, std::max<int64_t>(2, 1ll << plan.tensors[t].rank), dep[i], dep[c]});
+      for (const SymIn& in : plan.steps[i].ins) {
+        const SymTensor& T = plan.tensors[in.tensor];
+        if (T.leaf >= 0 && x_gate_off(plan.net.leaves[T.leaf].kind, plan.net.leaves[T.leaf].layer) >= 0) continue;
+        if (T.producer >= 0 && in_seg[T.producer]) continue;
+        const int eff = in.smask ? in.slow : T.rank;
+        ext.push_back({in.tensor, std::max<int64_t>(2, 1ll << eff), -1, dep[i]});
+      }
     }
-    std::sort(cands.begin(), cands.end(), [](const Interval& x, const Interval& y) {
+    auto by_size = [](const Interval& x, const Interval& y) {
       return x.size != y.size ? x.size > y.size : x.start < y.start;
-    });
-    const int64_t cap = (lds_bytes - 8 * (int64_t)(cands.size() + 4)) / elt;
+    };
+    std::sort(cands.begin(), cands.end(), by_size);
+    std::sort(ext.begin(), ext.end(), by_size);
+    cands.insert(cands.end(), ext.begin(), ext.end());
+    const int64_t cap = (lds_bytes - 8 * (int64_t)(cands.size() + 4)) / elt - x_tensor_base(plan.net.p);
     struct Placed {
       int64_t off, size;
       int start, end;
@@ -312,7 +329,8 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     std::vector<std::pair<int64_t, int64_t>> busy;
     std::vector<std::pair<int, int64_t>> where;
     int64_t top = 0;
-    for (const Interval& c : cands) {
+    for (int ci = 0; ci < (int)cands.size(); ++ci) {
+      const Interval& c = cands[ci];
       busy.clear();
       for (const auto& p : placed)
         if (p.start <= c.end && c.start <= p.end) busy.emplace_back(p.off, p.off + p.size);
@@ -322,7 +340,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
         if (b.first >= off + c.size) break;
         off = std::max(off, b.second);
       }
-      if (off + c.size > cap) return false;
+      if (off + c.size > cap) return false;  // every operand of a segment lives in LDS
       placed.push_back({off, c.size, c.start, c.end});
       where.emplace_back(c.t, off);
       top = std::max(top, off + c.size);
@@ -330,7 +348,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     if (!commit) return true;
     S.steps = steps;
     S.n_levels = n_levels;
-    S.lds_elems = (int)top;
+    S.lds_elems = (int)top + x_tensor_base(plan.net.p);
     for (int i : steps) {
       ws.depth[i] = dep[i];
       S.bytes_c64 += plan.steps[i].bytes_c64;
@@ -338,7 +356,9 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     }
     for (const auto& w : where) {
       ws.lds_off[w.first] = w.second;
-      ws.lds_slot[w.first] = S.n_slots++;
+      if (plan.tensors[w.first].leaf < 0) ws.lds_slot[w.first] = S.n_slots++;
+      const int pr = plan.tensors[w.first].producer;
+      if (pr < 0 || !in_seg[pr]) ws.staged_in[w.first] = (int)ws.segs.size();  // copied in at launch start
     }
     return true;
   };
@@ -347,12 +367,16 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       [&](const std::vector<int>& steps, int level, std::vector<qt_plan::Workspace::Op>& ops) {
         qt_plan::Workspace::Segment S;
         S.level = level;
-        if (steps.size() == 1 || place(steps, S, false)) {
+        if (place(steps, S, false)) {
           place(steps, S, true);
           ws.segs.push_back(std::move(S));
           const int si = (int)ws.segs.size() - 1;
           for (int i : ws.segs[si].steps) ws.seg_of[i] = si;
           ops.push_back({-1, si});
+          return;
+        }
+        if (steps.size() == 1) {  // its operands do not fit: one streaming launch
+          ops.push_back({steps[0], -1});
           return;
         }
         const size_t h = steps.size() / 2;
@@ -380,7 +404,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   flush();
   for (int t = 0; t < ntens; ++t) {
     const SymTensor& st = plan.tensors[t];
-    if (st.leaf < 0 && ws.lds_off[t] < 0 && st.consumer >= 0 && ws.seg_of[st.producer] >= 0 &&
+    if (st.leaf < 0 && (ws.lds_off[t] < 0 || ws.staged_in[t] >= 0) && st.consumer >= 0 && ws.seg_of[st.producer] >= 0 &&
         ws.seg_of[st.producer] == ws.seg_of[st.consumer])
       return fail(QT_EPLAN, "internal: a global tensor is written and read inside one launch");
   }
@@ -401,7 +425,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   std::vector<Interval> iv0, iv1;
   for (int t = 0; t < ntens; ++t) {
     const SymTensor& st = plan.tensors[t];
-    if (st.leaf >= 0 || ws.lds_off[t] >= 0) continue;
+    if (st.leaf >= 0 || (ws.lds_off[t] >= 0 && ws.staged_in[t] < 0)) continue;
     int end = st.consumer < 0 ? INF : when[st.consumer];
     if (st.level == 0 && st.consumer >= 0 && plan.steps[st.consumer].level == 1) end = INF;  // kept for every chunk
     Interval it{t, align_units(1ll << st.rank), when[st.producer], end};
@@ -435,29 +459,53 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
 
 // Device descriptors of the segments (needs the allocated buffers).
 qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
-  auto to_x = [&](int t, const SymIn* si, XIn& x) -> bool {
+  const int tbase = x_tensor_base(plan.net.p);
+  // Operand: the gate table, a staged input or an internal tensor.
+  auto to_op = [&](int t, const SymIn& si, int epu, XOp& x) -> bool {
     std::memset(&x, 0, sizeof(x));
-    if (ws.lds_off[t] >= 0) {
-      x.ptr = nullptr;
-      x.lds_off = (uint32_t)ws.lds_off[t];
-      x.slot_kind = 1;
+    const SymTensor& T = plan.tensors[t];
+    const int gate = T.leaf >= 0 ? x_gate_off(plan.net.leaves[T.leaf].kind, plan.net.leaves[T.leaf].layer) : -1;
+    x.slot = -1;
+    if (gate >= 0) {
+      x.lds_off = (uint32_t)gate;
+      x.smask = si.smask;  // a gate on a slice variable is read at the slice's bit
+      x.slow = si.slow;
+    } else if (ws.lds_off[t] >= 0) {
+      x.lds_off = (uint32_t)(ws.lds_off[t] + tbase);  // staged inputs arrive with the slice already selected
       x.slot = ws.lds_slot[t];
     } else {
-      DevIn d;
-      build_in(plan, ws, t, 0, 0, si ? si->smask : 0, si ? si->slow : 0, elt, d);
-      x.ptr = d.ptr;
-      x.pt_stride = d.pt_stride;
-      x.sb_stride = d.sb_stride;
-      x.smask = d.smask;
-      x.slow = d.slow;
-      x.slot_kind = d.exp_base >= 0 ? 2 : 0;
-      x.slot = d.exp_base;
-      x.exp_pt = d.exp_pt;
-      x.exp_sb = d.exp_sb;
+      return false;
     }
-    if (!si) return true;
-    x.has_v = si->has_v;
-    return make_runs(si->mask, kXRuns, x.run_lo, x.run_len, x.run_dst, x.nruns);
+    x.has_v = si.has_v;
+    int32_t nr = 0;
+    if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr)) return false;
+    for (int e = 0; e < 4; ++e) {
+      uint32_t r = 0;
+      if (e < epu)
+        for (int i = 0; i < nr; ++i)
+          r |= (((uint32_t)(64 * e) >> x.run_lo[i]) & ((1u << x.run_len[i]) - 1u)) << x.run_dst[i];
+      x.ep[e] = r;
+    }
+    return true;
+  };
+  auto to_out = [&](int t, XOut& x) {
+    std::memset(&x, 0, sizeof(x));
+    if (ws.lds_off[t] >= 0 && ws.staged_in[t] < 0) {  // internal: stays in LDS
+      x.ptr = nullptr;
+      x.lds_off = (uint32_t)(ws.lds_off[t] + tbase);
+      x.slot_kind = 1;
+      x.slot = ws.lds_slot[t];
+      return;
+    }
+    DevIn d;
+    build_in(plan, ws, t, 0, 0, 0, 0, elt, d);
+    x.ptr = const_cast<void*>(d.ptr);
+    x.pt_stride = d.pt_stride;
+    x.sb_stride = d.sb_stride;
+    x.slot_kind = d.exp_base >= 0 ? 2 : 0;
+    x.slot = d.exp_base;
+    x.exp_pt = d.exp_pt;
+    x.exp_sb = d.exp_sb;
   };
   size_t total = 0;
   for (auto& S : ws.segs) {
@@ -468,13 +516,20 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       const SymStep& st = plan.steps[S.steps[a]];
       XStep& xs = S.xsteps[a];
       std::memset(&xs, 0, sizeof(xs));
-      to_x(st.out, nullptr, xs.out);
+      to_out(st.out, xs.out);
       xs.r = st.rank;
       xs.sum = st.sum;
-      xs.n_in = (int)st.ins.size();
+      xs.n_in = x_nin_class((int)st.ins.size());
+      const int epu = x_epu(st.rank, (int)st.ins.size(), elt);
       for (size_t j = 0; j < st.ins.size(); ++j)
-        if (!to_x(st.ins[j].tensor, &st.ins[j], xs.in[j]))
-          return fail(QT_EUNSUPPORTED, "LDS segment input index map has more than 8 runs of bits");
+        if (!to_op(st.ins[j].tensor, st.ins[j], epu, xs.in[j]))
+          return fail(QT_EPLAN, "internal: LDS segment operand not in LDS or index map too fragmented");
+      for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {
+        XOp& id = xs.in[j];  // identity operand: LDS elements 0 and 1 (1 + 0i), index 0
+        std::memset(&id, 0, sizeof(id));
+        id.has_v = 1;
+        id.slot = -1;
+      }
     }
     S.units.clear();
     S.level_off.clear();
@@ -483,12 +538,36 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       for (size_t a = 0; a < S.steps.size(); ++a)
         if (ws.depth[S.steps[a]] == L) {
           const int r = plan.steps[S.steps[a]].rank;
-          const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, elt));
+          const int nin = (int)plan.steps[S.steps[a]].ins.size();
+          const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, nin, elt));
           for (int64_t c = 0; c < chunks; ++c) S.units.push_back(make_uint2((uint32_t)a, (uint32_t)c));
         }
     }
     S.level_off.push_back((int32_t)S.units.size());
+    // staging copies of external inputs
+    S.copies.clear();
+    for (int i : S.steps)
+      for (const SymIn& in : plan.steps[i].ins) {
+        const int t = in.tensor;
+        if (ws.staged_in[t] < 0 || ws.seg_of[i] != ws.staged_in[t]) continue;
+        DevIn d;
+        build_in(plan, ws, t, 0, 0, in.smask, in.slow, elt, d);
+        XCopy cp{};
+        cp.ptr = d.ptr;
+        cp.pt_stride = d.pt_stride;
+        cp.sb_stride = d.sb_stride;
+        cp.smask = d.smask;
+        cp.slow = d.slow;
+        cp.lds_off = (uint32_t)(ws.lds_off[t] + tbase);
+        cp.n = 1u << (in.smask ? in.slow : plan.tensors[t].rank);
+        cp.gslot = d.exp_base;
+        cp.exp_pt = d.exp_pt;
+        cp.exp_sb = d.exp_sb;
+        cp.lslot = ws.lds_slot[t];
+        S.copies.push_back(cp);
+      }
     total += ((S.xsteps.size() * sizeof(XStep) + 255) & ~(size_t)255) +
+             ((S.copies.size() * sizeof(XCopy) + 255) & ~(size_t)255) +
              ((S.units.size() * sizeof(uint2) + 255) & ~(size_t)255) +
              ((S.level_off.size() * sizeof(int32_t) + 255) & ~(size_t)255);
   }
@@ -507,6 +586,10 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     S.launch.steps = (const XStep*)put(S.xsteps.data(), S.xsteps.size() * sizeof(XStep));
     S.launch.units = (const uint2*)put(S.units.data(), S.units.size() * sizeof(uint2));
     S.launch.level_off = (const int32_t*)put(S.level_off.data(), S.level_off.size() * sizeof(int32_t));
+    S.launch.copies = (const XCopy*)put(S.copies.data(), S.copies.size() * sizeof(XCopy));
+    S.launch.n_copies = (int)S.copies.size();
+    S.launch.params = ws.params;
+    S.launch.p = plan.net.p;
     S.launch.n_levels = S.n_levels;
     S.launch.n_slots = S.n_slots;
     S.launch.lds_elems = S.lds_elems;
@@ -566,7 +649,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
       std::memset(&d, 0, sizeof(d));
       const SymTensor& ot = plan.tensors[st.out];
       ws.step_elems.push_back((int64_t)np * (st.level == 1 ? chunk : 1) << ot.rank);
-      if (ws.lds_off[st.out] >= 0 || ws.seg_of[&st - plan.steps.data()] >= 0) {
+      if (ws.seg_of[&st - plan.steps.data()] >= 0) {
         ws.steps.push_back(d);  // runs inside an LDS segment
         continue;
       }
@@ -582,7 +665,8 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
       d.out_exp_sb = od.exp_sb;
       for (size_t j = 0; j < st.ins.size(); ++j) {
         const SymIn& si = st.ins[j];
-        if (ws.lds_off[si.tensor] >= 0) return fail(QT_EPLAN, "internal: streaming step reads an LDS tensor");
+        if (ws.lds_off[si.tensor] >= 0 && ws.staged_in[si.tensor] < 0)
+          return fail(QT_EPLAN, "internal: streaming step reads an LDS tensor");
         if (!build_in(plan, ws, si.tensor, si.mask, si.has_v, si.smask, si.slow, elt, d.in[j]))
           return fail(QT_EUNSUPPORTED, "input index map has more than 16 runs of bits");
       }
@@ -603,6 +687,12 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     if (!ws.finals.empty())
       QT_HIP_CHECK(hipMemcpy(ws.dfinal, ws.finals.data(), ws.finals.size() * sizeof(DevIn), hipMemcpyHostToDevice));
     QT_TRY(build_segment_tables(plan, ws, elt));
+    ws.trace_on = env_int("QT_DEBUG_LEVEL_TRACE", 0) != 0;
+    if (ws.trace_on) {
+      int max_levels = 1;
+      for (auto& S : ws.segs) max_levels = std::max(max_levels, S.n_levels + 1);
+      QT_TRY(dev_alloc(&ws.trace_buf, (int64_t)max_levels * (int64_t)ws.segs.size(), b));
+    }
     plan.info.slice_batch = chunk;
   }
   if (ws.per_slice_cap < (int64_t)np * n_range) {
@@ -669,6 +759,9 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
     auto& S = ws.segs[op.seg];
     XLaunch x = S.launch;
     x.chunk_base = cb;
+    int max_levels = 1;
+    for (auto& T : ws.segs) max_levels = std::max(max_levels, T.n_levels + 1);
+    x.trace = ws.trace_on ? ws.trace_buf + (int64_t)op.seg * max_levels : nullptr;
     x.lg_nsb = S.level == 1 ? ilog2(ws.chunk) : 0;
     const int64_t items = (int64_t)np * (S.level == 1 ? ws.chunk : 1);
     ++launches;
@@ -711,6 +804,32 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
   QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0,
                      [&] { return launch_slice_sum(ws.per_slice, np, n_range, ws.sums, stream); }));
   ++launches;
+  if (ws.trace_on) {
+    QT_HIP_CHECK(hipStreamSynchronize(stream));
+    int max_levels = 1;
+    for (auto& T : ws.segs) max_levels = std::max(max_levels, T.n_levels + 1);
+    std::vector<uint64_t> tr((size_t)max_levels * ws.segs.size());
+    QT_HIP_CHECK(hipMemcpy(tr.data(), ws.trace_buf, tr.size() * 8, hipMemcpyDeviceToHost));
+    int rate_khz = 100000;
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, 0);
+    for (size_t si = 0; si < ws.segs.size(); ++si) {
+      const auto& S = ws.segs[si];
+      const uint64_t* t = tr.data() + si * max_levels;
+      std::fprintf(stderr, "segment %zu (level %d, %zu steps): total %.1f us\n", si, S.level, S.steps.size(),
+                   (double)(t[S.n_levels] - t[0]) * 1e3 / rate_khz);
+      for (int L = 0; L < S.n_levels; ++L) {
+        int nu = S.level_off[L + 1] - S.level_off[L];
+        int maxr = 0, nst = 0;
+        for (size_t a = 0; a < S.steps.size(); ++a)
+          if (ws.depth[S.steps[a]] == L) {
+            maxr = std::max(maxr, plan.steps[S.steps[a]].rank);
+            ++nst;
+          }
+        std::fprintf(stderr, "  level %2d: %6.2f us  steps %2d units %4d max rank %2d\n", L,
+                     (double)(t[L + 1] - t[L]) * 1e3 / rate_khz, nst, nu, maxr);
+      }
+    }
+  }
   plan.info.n_launches = launches;
   return QT_OK;
 }
@@ -779,6 +898,50 @@ extern "C" qt_status qt_contract_amplitude(qt_plan* plan, const double* gammas, 
 }
 
 extern "C" void qt_free_plan(qt_plan* plan) { delete plan; }
+
+extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t cap, int64_t* needed) {
+  try {
+    if (!plan || !needed) return fail(QT_EINVAL, "qt_plan_describe: null argument");
+    qt_plan::Workspace ws;
+    const int elt = plan->precision == QT_C128 ? 16 : 8;
+    QT_TRY(plan_schedule(const_cast<qt_plan&>(*plan), ws, elt));
+    std::string j = "{\"element_bytes\":" + std::to_string(elt) + ",\"segments\":[";
+    for (size_t si = 0; si < ws.segs.size(); ++si) {
+      const auto& S = ws.segs[si];
+      int staged = 0, internal = 0;
+      for (size_t t = 0; t < plan->tensors.size(); ++t) {
+        if (ws.staged_in[t] == (int)si) ++staged;
+        else if (ws.lds_off[t] >= 0 && ws.staged_in[t] < 0 && plan->tensors[t].producer >= 0 &&
+                 ws.seg_of[plan->tensors[t].producer] == (int)si)
+          ++internal;
+      }
+      const size_t smem = lds_exec_smem_bytes(S.n_slots, S.lds_elems, elt == 16);
+      j += std::string(si ? "," : "") + "{\"level\":" + std::to_string(S.level) + ",\"steps\":" +
+           std::to_string(S.steps.size()) + ",\"first_step\":" + std::to_string(S.steps.front()) +
+           ",\"levels\":" + std::to_string(S.n_levels) + ",\"lds_bytes\":" + std::to_string(smem) +
+           ",\"slots\":" + std::to_string(S.n_slots) + ",\"internal\":" + std::to_string(internal) +
+           ",\"staged\":" + std::to_string(staged) + "}";
+    }
+    j += "],\"stream_steps\":[";
+    bool first = true;
+    for (auto* ops : {&ws.prefix_ops, &ws.slice_ops})
+      for (const auto& op : *ops)
+        if (op.seg < 0) {
+          j += std::string(first ? "" : ",") + "{\"step\":" + std::to_string(op.step) + ",\"rank\":" +
+               std::to_string(plan->steps[op.step].rank) + ",\"inputs\":" +
+               std::to_string(plan->steps[op.step].ins.size()) + "}";
+          first = false;
+        }
+    j += "],\"arena0_units\":" + std::to_string(ws.arena0_units) + ",\"arena1_units\":" +
+         std::to_string(ws.arena1_units) + "}";
+    *needed = (int64_t)j.size() + 1;
+    if (!buf || cap < *needed) return fail(QT_EINVAL, "qt_plan_describe: buffer too small");
+    std::memcpy(buf, j.c_str(), j.size() + 1);
+    return QT_OK;
+  } catch (const std::exception& ex) {
+    return fail(QT_ENOMEM, std::string("qt_plan_describe: ") + ex.what());
+  }
+}
 
 extern "C" qt_status qt_profile_enable(qt_plan* plan, int32_t enable) {
   if (!plan) return fail(QT_EINVAL, "qt_profile_enable: null plan");

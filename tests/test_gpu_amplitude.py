@@ -28,7 +28,8 @@ def slice_err(got, want):
     return np.abs(np.asarray(got) - np.asarray(want)).max() / np.abs(want).max()
 
 
-def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batch=0, step=None, plain=False):
+def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batch=0, step=None, plain=False,
+          fold=False):
     spec = N.amplitude_network(n, edges, p, z)
     net = api.Network(spec)
     if k == 0:
@@ -45,7 +46,8 @@ def build(n, p, edges, z=None, k=0, algo="min_fill", precision="c64", slice_batc
             pre = [v for v in full if v not in sl][:step]
             rest, _ = net.order_greedy(algo, exclude=sl + pre)
             order, groups = pre + rest, [(step, sl)]
-    return net, api.Plan(net, order, groups, precision=precision, slice_batch=slice_batch, plain=plain)
+    return net, api.Plan(net, order, groups, precision=precision, slice_batch=slice_batch, plain=plain,
+                         fold_prefix=fold)
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
@@ -189,6 +191,27 @@ def _plan_of(n, p, edges, k):
     net = api.Network(N.amplitude_network(n, edges, p))
     sch = net.plan_slicing(k, algo="min_fill")
     return sch.order, sch.groups
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_fold_prefix(precision):
+    # the prefix run inside every slice with the slice variables fixed gives
+    # the same per-slice values as the prefix run once
+    n, p, k = 60, 2, 8
+    edges = regular_graph(n, 3, 0)
+    g, b = qaoa_params(p, 1, seed=1)
+    net, plan = build(n, p, edges, k=k, precision=precision, fold=True)
+    _, per = plan.contract_batch(g, b, per_slice=True)
+    want = oracle.sliced_values(oracle.amplitude_network(n, edges, g[0], b[0]), plan.order, plan.groups)
+    assert slice_err(per[0], want) < TOL[precision]
+    n, p = 20, 3
+    edges = regular_graph(n, 3, 1)
+    z = random_bitstring(n, 7)
+    gs, bs = qaoa_params(p, 3, seed=2)
+    net, plan = build(n, p, edges, z, k=4, precision=precision, fold=True, slice_batch=4)
+    vals, _ = plan.contract_batch(gs, bs)
+    for i in range(3):
+        assert rel(vals[i], oracle.amplitude_sv(n, edges, gs[i], bs[i], z)) < TOL[precision]
 
 
 def test_bitwise_reproducible():

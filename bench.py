@@ -75,6 +75,83 @@ def cpu_baseline(edges, g, b, sch, budget_s):
     return reps / el, reps, el
 
 
+def energy_bench(steps, warmup, cpu_seconds):
+    """Edge-energies/s on n=1000, p=3: 1500 lightcones x 32 points per evaluation."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2012_02430_amd import _lib as L
+    from paper_2012_02430_amd import api
+    from workloads import qaoa_params, regular_graph
+
+    n, p, npt = 1000, 3, 32
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, npt, seed=1)
+    model = api.EnergyModel(n, edges, p, precision="c64")
+    lib = L.load()
+    stream = torch.cuda.current_stream()
+    gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
+    bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
+    Ed = torch.zeros(npt, dtype=torch.float64, device="cuda")
+
+    def call():
+        L.check(lib.qt_energy_grad(model._arr, len(edges), npt, gd.data_ptr(), bd.data_ptr(), Ed.data_ptr(), None,
+                                   None, None, stream.cuda_stream))
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    rate = len(edges) * npt / el
+    # accuracy on sampled edges against the oracle
+    E, pe = model.energy(gs, bs, per_edge=True)
+    rng = np.random.default_rng(0)
+    err = 0.0
+    for i in (0, 31):
+        for e in rng.choice(len(edges), 4, replace=False):
+            u, v = edges[e]
+            err = max(err, abs(pe[i, e] - oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real))
+    # plain complex128 path on a sample of lightcones: one launch per bucket step
+    sample = list(rng.choice(len(edges), 8, replace=False))
+    plain = [api.Plan(model.networks[e], model.plans[e].order, precision="c128", plain=True, slice_batch=1)
+             for e in sample]
+    for pl in plain:
+        pl.contract_amplitude(gs[0], bs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl in plain:
+        pl.contract_amplitude(gs[0], bs[0])
+    plain_rate = len(plain) / (time.perf_counter() - t0)
+    # the oracle on the host, same sample of lightcones
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < cpu_seconds:
+        u, v = edges[sample[done % len(sample)]]
+        oracle.edge_energy(n, edges, gs[0], bs[0], u, v)
+        done += 1
+    cpu_rate = done / (time.perf_counter() - t0)
+    return {
+        "metric": "edge-energies/s",
+        "workload": "QAOA p=3 MaxCut energy, seeded random 3-regular graph n=1000: 1500 per-edge lightcone "
+                    "networks x 32 seeded points per evaluation, one batched launch, complex64, FP64 edge sums",
+        "value": rate,
+        "ms_per_evaluation": 1e3 * el,
+        "max_abs_err_vs_oracle_sampled": err,
+        "plain_c128": {"value": plain_rate, "unit": "edge-energies/s",
+                       "sample": f"{len(plain)} lightcones, one launch per bucket step"},
+        "speedup_vs_plain_c128": rate / plain_rate,
+        "cpu_oracle": {"value": cpu_rate, "unit": "edge-energies/s", "cores": 1,
+                       "sample": f"{done} lightcone contractions in {cpu_seconds:.0f} s"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +160,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
@@ -149,6 +227,13 @@ def main():
                          "numpy complex128, single thread"}
         print(f"[bench] oracle on host: {rate:.3f} amplitudes/s", flush=True)
 
+    energy = None
+    if not args.no_energy:
+        energy = energy_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5)
+        print(f"[bench] energy: {energy['value']:.3e} edge-energies/s ({energy['ms_per_evaluation']:.2f} ms per "
+              f"1500x32 evaluation), plain c128 {energy['plain_c128']['value']:.1f}/s, "
+              f"max abs err {energy['max_abs_err_vs_oracle_sampled']:.1e}", flush=True)
+
     inf = plan.info()
     line = {
         "metric": METRIC,
@@ -180,6 +265,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
+        "energy": energy,
     }
     print(json.dumps(line), flush=True)
 

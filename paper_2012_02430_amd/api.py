@@ -216,3 +216,41 @@ def contract_batch(plans, gammas, betas, slice_begin=0, slice_end=None, per_slic
     if len(plans) == 1:
         return vals[0], (slices[0] if per_slice else None)
     return vals, slices
+
+
+class EnergyModel:
+    """QAOA MaxCut energy from per-edge lightcone networks (``qt_energy_grad``).
+
+    One network and one plan per edge (greedy order, no slicing); every edge
+    and point runs in one batched launch.
+    """
+
+    def __init__(self, n, edges, p, precision="c64", algo="min_fill"):
+        from paper_2012_02430_amd import network as N
+
+        self.n, self.p = n, p
+        self.edges = [tuple(e) for e in edges]
+        self.networks = [Network(N.energy_network(n, self.edges, p, u, v)) for u, v in self.edges]
+        self.plans = [Plan(net, net.order_greedy(algo)[0], precision=precision) for net in self.networks]
+        self._arr = (ctypes.c_void_p * len(self.plans))(*[pl.handle.value for pl in self.plans])
+
+    def energy(self, gammas, betas, per_edge=False, grad=False, stream=None):
+        """E per point (and per-edge values [n_points, n_edges], and (dE/dgamma, dE/dbeta))."""
+        lib = L.load()
+        p = self.p
+        g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1, p)
+        b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1, p)
+        npt = g.shape[0]
+        E = np.zeros(npt)
+        pe = np.zeros((npt, len(self.plans))) if per_edge else None
+        dg = np.zeros((npt, p)) if grad else None
+        db = np.zeros((npt, p)) if grad else None
+        L.check(lib.qt_energy_grad(self._arr, len(self.plans), npt, g.ctypes.data, b.ctypes.data, E.ctypes.data,
+                                   dg.ctypes.data if grad else None, db.ctypes.data if grad else None,
+                                   pe.ctypes.data if per_edge else None, stream or 0))
+        out = [E]
+        if per_edge:
+            out.append(pe)
+        if grad:
+            out += [dg, db]
+        return out[0] if len(out) == 1 else tuple(out)

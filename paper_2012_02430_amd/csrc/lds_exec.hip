@@ -325,3 +325,128 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
 }
 
 }  // namespace qt
+
+namespace qt {
+namespace {
+
+// Multi-program executor: one workgroup per (program, point) item runs a
+// whole network (a per-edge lightcone) in LDS, then forms its scalar
+// result: the product of the network's closing scalars in FP64 with the
+// accumulated power-of-two exponent.
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, const XProg* __restrict__ progs,
+                                                            const XStep* __restrict__ steps,
+                                                            const uint2* __restrict__ units,
+                                                            const int32_t* __restrict__ level_off,
+                                                            const XFinal* __restrict__ finals,
+                                                            const int32_t* __restrict__ item_prog) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int slots16 = (M.n_slots + 3) & ~3;
+  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
+  int* sexp = reinterpret_cast<int*>(smem + 4 * slots16);
+  E* lds = reinterpret_cast<E*>(smem + 8 * slots16);
+
+  const uint32_t item = blockIdx.x;
+  const int prog_id = item_prog[item / (uint32_t)M.n_points];
+  const XProg& P = progs[prog_id];
+  XCtx c;
+  c.pt = item % (uint32_t)M.n_points;
+  c.sb = 0;
+  c.sid = 0;
+  const int tid = threadIdx.x;
+  c.lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nw = blockDim.x >> 6;
+
+  for (int i = tid; i < P.n_slots; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  if (tid < 2) {
+    lds[tid].x = 1;
+    lds[tid].y = 0;
+  }
+  if (tid < x_gate_elems(M.p)) lds[kXGate + tid] = x_gate<E>(tid, M.params + (int64_t)c.pt * 2 * M.p, M.p);
+  __syncthreads();
+
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  const XStep* psteps = steps + P.steps_off;
+  const uint2* punits = units + P.units_off;
+  const int32_t* plev = level_off + P.levels_off;
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw) {
+      const uint2 un = punits[u];
+      const XStep& st = psteps[un.x];
+      const bool big = st.r >= kXBigRank;
+      if (st.n_in <= 2) {
+        if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      } else if (st.n_in <= 4) {
+        if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      } else {
+        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double re = 1.0, im = 0.0, ex = P.log2_const;
+    for (int f = 0; f < P.n_finals; ++f) {
+      const XFinal& F = finals[P.finals_off + f];
+      const E a = lds[F.lds_off];
+      const double ar = (double)a.x, ai = (double)a.y;
+      if (SCALED && F.slot >= 0) ex += sexp[F.slot];
+      const double nr = re * ar - im * ai;
+      im = re * ai + im * ar;
+      re = nr;
+    }
+    double* o = M.out + 3 * ((int64_t)c.pt * M.n_progs + prog_id);
+    o[0] = re;
+    o[1] = im;
+    o[2] = ex;
+  }
+}
+
+__global__ void k_amp_to_real(const double* __restrict__ amp, int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double e = amp[3 * i + 2];
+    const double fl = floor(e);
+    out[i] = ldexp(amp[3 * i] * exp2(e - fl), (int)fl);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled, hipStream_t stream) {
+  const int64_t n_items = (int64_t)n_item_progs * m.n_points;
+  if (n_items == 0) return hipSuccess;
+  const size_t smem = lds_exec_smem_bytes(m.n_slots, m.lds_elems, c128);
+  const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
+  const void* fn = c128 ? reinterpret_cast<const void*>(&k_lds_multi<double2, false>)
+                        : (scaled ? reinterpret_cast<const void*>(&k_lds_multi<float2, true>)
+                                  : reinterpret_cast<const void*>(&k_lds_multi<float2, false>));
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  if (c128)
+    hipLaunchKernelGGL((k_lds_multi<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
+                       m.level_off, m.finals, m.item_prog);
+  else if (scaled)
+    hipLaunchKernelGGL((k_lds_multi<float2, true>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
+                       m.level_off, m.finals, m.item_prog);
+  else
+    hipLaunchKernelGGL((k_lds_multi<float2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
+                       m.level_off, m.finals, m.item_prog);
+  return hipGetLastError();
+}
+
+hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_amp_to_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, amp, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace qt

@@ -21,6 +21,7 @@
 //   * slice variables are the top bits, so fixing them picks a contiguous
 //     block of a prefix tensor.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 #include <numeric>
@@ -167,6 +168,8 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     if (d->slice_batch < 0) return fail(QT_EINVAL, "qt_load_plan: negative slice_batch");
 
     auto plan = std::make_unique<qt_plan>();
+    static std::atomic<uint64_t> next_serial{1};
+    plan->serial = next_serial++;
     plan->net = *net;
     plan->precision = d->precision;
     plan->slice_batch_req = d->slice_batch;

@@ -207,6 +207,41 @@ struct XLaunch {
   uint64_t* trace;         // optional: workgroup 0 stores wall_clock64() after each level
 };
 
+// Multi-program launch (per-edge lightcone networks): item i runs program
+// item_prog[i / n_points] at point i % n_points; every tensor of a program
+// lives in LDS and its scalar result is formed in an FP64 epilogue.
+struct XFinal {
+  uint32_t lds_off;
+  int32_t slot;
+};
+struct XProg {
+  int32_t steps_off;   // first XStep of the program
+  int32_t units_off;   // first unit (units name steps relative to steps_off)
+  int32_t levels_off;  // first of its n_levels + 1 level offsets (relative to units_off)
+  int32_t n_levels;
+  int32_t n_slots;
+  int32_t finals_off;
+  int32_t n_finals;
+  int32_t pad;
+  double log2_const;   // exponent of the |+> normalisations
+};
+struct XMulti {
+  const XProg* progs;
+  const XStep* steps;
+  const uint2* units;
+  const int32_t* level_off;
+  const XFinal* finals;
+  const int32_t* item_prog;
+  const double* params;    // [points][2p]
+  double* out;             // [points][programs][3]: re, im, log2 scale
+  int32_t n_points;
+  int32_t n_progs;
+  int32_t p;
+  int32_t lds_elems;       // max over programs
+  int32_t n_slots;         // max over programs
+  int32_t pad;
+};
+
 // Leaf (gate) tensor materialisation record.
 struct DevLeaf {
   int32_t kind;
@@ -258,6 +293,14 @@ struct SymTensor {
   int32_t exp_slot = -1;      // scalar slot base for exponents
 };
 
+int env_int(const char* name, int dflt);
+void energy_forget(uint64_t serial);  // drops cached energy jobs that use the plan
+// Full contraction of a plan at np points through the general schedule;
+// *sums receives the device address of its [np][3] (re, im, log2) results.
+qt_status run_plan_points(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream,
+                          const double** sums);
+bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns);
+
 // Buffers live over closed time intervals, packed first-fit, largest first.
 struct Interval {
   int32_t t;
@@ -289,6 +332,7 @@ struct qt_plan {
   int32_t n_exp0 = 0, n_exp1 = 0;   // exponent slots per point / per (point x item)
   int64_t slice_batch_req = 0;
   int32_t flags = 0;
+  uint64_t serial = 0;  // unique per plan, never reused (cache keys)
   qt_plan_info info{};
   // HIP-event profiling of launches (qt_profile_enable / qt_profile_read)
   struct Profile;
@@ -315,6 +359,9 @@ hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, i
                         double* per_slice, int64_t slice_end, hipStream_t stream);
 hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c128, bool scaled, int* exps,
                            uint32_t* maxbits, hipStream_t stream);
+hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
+                            hipStream_t stream);
+hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream);
 size_t lds_exec_smem_bytes(int n_slots, int lds_elems, bool c128);
 hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,
                             hipStream_t stream);

@@ -36,6 +36,35 @@ int ilog2(int64_t x) {
 
 using namespace qt;
 
+namespace qt {
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
+bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns) {
+  int n = 0, d = 0;
+  for (int b = 0; b < 32;) {
+    if (!((mask >> b) & 1u)) {
+      ++b;
+      continue;
+    }
+    int e = b;
+    while (e < 32 && ((mask >> e) & 1u)) ++e;
+    if (n == max_runs) return false;
+    lo[n] = (uint8_t)b;
+    len[n] = (uint8_t)(e - b);
+    dst[n] = (uint8_t)d;
+    d += e - b;
+    ++n;
+    b = e;
+  }
+  nruns = n;
+  return true;
+}
+
+}  // namespace qt
+
 struct qt_plan::Workspace {
   int np = 0;
   int64_t chunk = 0;
@@ -202,34 +231,9 @@ qt_status dev_alloc(T** p, int64_t count, int64_t& bytes) {
     if (_s != QT_OK) return _s; \
   } while (0)
 
-int env_int(const char* name, int dflt) {
-  const char* e = std::getenv(name);
-  return e ? std::atoi(e) : dflt;
-}
 
 constexpr int64_t kUnitAlign = 64;  // arena offsets in multiples of 64 elements
 int64_t align_units(int64_t n) { return (n + kUnitAlign - 1) / kUnitAlign * kUnitAlign; }
-
-bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns) {
-  int n = 0, d = 0;
-  for (int b = 0; b < 32;) {
-    if (!((mask >> b) & 1u)) {
-      ++b;
-      continue;
-    }
-    int e = b;
-    while (e < 32 && ((mask >> e) & 1u)) ++e;
-    if (n == max_runs) return false;
-    lo[n] = (uint8_t)b;
-    len[n] = (uint8_t)(e - b);
-    dst[n] = (uint8_t)d;
-    d += e - b;
-    ++n;
-    b = e;
-  }
-  nruns = n;
-  return true;
-}
 
 bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t mask, int has_v, uint32_t smask,
               int slow, int elt, DevIn& d) {
@@ -837,6 +841,15 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
 }  // namespace
 }  // namespace qt
 
+namespace qt {
+qt_status run_plan_points(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream,
+                          const double** sums) {
+  QT_TRY(run_plan(plan, np, gammas, betas, 0, 1ll << plan.slice_vars.size(), 1ll << plan.slice_vars.size(), stream));
+  *sums = plan.ws->sums;
+  return QT_OK;
+}
+}  // namespace qt
+
 extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_points,
                                        const double* gammas, const double* betas, int64_t slice_begin,
                                        int64_t slice_end, qt_amp* out, double* per_slice_out, void* hip_stream) {
@@ -897,7 +910,11 @@ extern "C" qt_status qt_contract_amplitude(qt_plan* plan, const double* gammas, 
   return qt_contract_batch(&plan, 1, 1, gammas, betas, 0, ns, out, nullptr, hip_stream);
 }
 
-extern "C" void qt_free_plan(qt_plan* plan) { delete plan; }
+extern "C" void qt_free_plan(qt_plan* plan) {
+  if (!plan) return;
+  energy_forget(plan->serial);
+  delete plan;
+}
 
 extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t cap, int64_t* needed) {
   try {
@@ -960,18 +977,4 @@ extern "C" qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_
   return QT_OK;
 }
 
-extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
-                                    const double* gammas, const double* betas, double* energy, double* dE_dgamma,
-                                    double* dE_dbeta, double* per_edge, void* hip_stream) {
-  (void)lightcones;
-  (void)n_edges;
-  (void)n_points;
-  (void)gammas;
-  (void)betas;
-  (void)energy;
-  (void)dE_dgamma;
-  (void)dE_dbeta;
-  (void)per_edge;
-  (void)hip_stream;
-  return fail(QT_EUNSUPPORTED, "qt_energy_grad: not built yet");
-}
+

@@ -1,0 +1,93 @@
+"""Parity of the HIP energy path (per-edge lightcones, one batched launch).
+
+Per-edge values <C_e> lie in [0, 1]; they are compared with an absolute
+tolerance equal to the relative one (1e-12 for complex128, 1e-5 for
+complex64), and the energy with a relative tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.statevector import edge_energy_sv
+from paper_2012_02430_amd import _lib as L
+from paper_2012_02430_amd import api
+from workloads import qaoa_params, regular_graph
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("n,p", [(10, 1), (12, 2), (14, 3), (8, 3)])
+def test_energy_vs_statevector(precision, n, p):
+    edges = regular_graph(n, 3, 1)
+    gs, bs = qaoa_params(p, 3, seed=n + p)
+    model = api.EnergyModel(n, edges, p, precision=precision)
+    E, pe = model.energy(gs, bs, per_edge=True)
+    for i in range(3):
+        want = oracle.energy_sv(n, edges, gs[i], bs[i])
+        assert abs(E[i] - want) / abs(want) < TOL[precision]
+        for e, (u, v) in enumerate(edges):
+            assert abs(pe[i, e] - edge_energy_sv(n, edges, gs[i], bs[i], u, v)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c64"])
+def test_energy_p1_closed_form_n1000(precision):
+    n = 1000
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(1, 4, seed=2)
+    model = api.EnergyModel(n, edges, 1, precision=precision)
+    E, pe = model.energy(gs, bs, per_edge=True)
+    for i in range(4):
+        want = np.array([oracle.edge_energy_p1(edges, u, v, gs[i, 0], bs[i, 0]).real for u, v in edges])
+        assert np.abs(pe[i] - want).max() < TOL[precision]
+        assert abs(E[i] - want.sum()) / want.sum() < TOL[precision]
+
+
+def test_energy_p3_n1000_sampled_and_symmetries():
+    # the configuration of the headline energy workload: n=1000, p=3,
+    # 1500 lightcones, 32 seeded points
+    n, p = 1000, 3
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 32, seed=1)
+    model = api.EnergyModel(n, edges, p, precision="c64")
+    E, pe = model.energy(gs, bs, per_edge=True)
+    assert pe.shape == (32, 1500)
+    rng = np.random.default_rng(0)
+    for i in (0, 17, 31):
+        for e in rng.choice(len(edges), 6, replace=False):
+            u, v = edges[e]
+            want = oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real
+            assert abs(pe[i, e] - want) < TOL["c64"], (i, e)
+        assert abs(E[i] - pe[i].sum()) < 1e-9 * abs(E[i])
+    # exact identities at full size: gamma = 0 or beta = 0 gives |E|/2
+    z = np.zeros((2, p))
+    E0 = model.energy(z, bs[:2])
+    E1 = model.energy(gs[:2], z)
+    assert np.abs(E0 - 750.0).max() < 1e-5 * 750 and np.abs(E1 - 750.0).max() < 1e-5 * 750
+    # E(-gamma, -beta) = E(gamma, beta)
+    Em = model.energy(-gs[:4], -bs[:4])
+    assert np.abs(Em - E[:4]).max() < 1e-5 * np.abs(E[:4]).max()
+
+
+def test_energy_reproducible_and_errors():
+    n, p = 20, 2
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 5, seed=3)
+    model = api.EnergyModel(n, edges, p)
+    a = model.energy(gs, bs, per_edge=True)
+    b = model.energy(gs, bs, per_edge=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a plan with slicing is not a lightcone plan
+    net = model.networks[0]
+    sch = net.plan_slicing(1)
+    bad = api.Plan(net, sch.order, sch.groups)
+    arr = (L.ctypes.c_void_p * 1)(bad.handle.value) if hasattr(L, "ctypes") else None
+    import ctypes
+
+    arr = (ctypes.c_void_p * 1)(bad.handle.value)
+    E = np.zeros(1)
+    st = L.load().qt_energy_grad(arr, 1, 1, gs[:1].ctypes.data, bs[:1].ctypes.data, E.ctypes.data, None, None,
+                                 None, 0)
+    assert st == L.QT_EINVAL

@@ -136,6 +136,14 @@ def load():
     if _LIB is None:
         if not LIB_PATH.exists():
             raise ImportError(f"{LIB_PATH} is not built: run python -m paper_2012_02430_amd.build")
+        # torch ships its own HIP runtime under the same soname as the
+        # system one this library links; loading torch first makes the
+        # library bind to that copy, so the process holds one HIP runtime
+        # and device pointers and streams are shared with torch.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(str(LIB_PATH))
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -254,3 +254,69 @@ class EnergyModel:
         if grad:
             out += [dg, db]
         return out[0] if len(out) == 1 else tuple(out)
+
+    def energy_device(self, gammas, betas, grad=False, per_edge=False, stream=None):
+        """Device-resident call: gammas/betas are float64 torch tensors [n_points, p] on the GPU.
+
+        Returns torch tensors (E, and per-edge values, and dE/dgamma, dE/dbeta)
+        written by the library on ``stream`` (default: torch's current stream).
+        """
+        import torch
+
+        lib = L.load()
+        g = gammas.detach().to(torch.float64).contiguous()
+        b = betas.detach().to(torch.float64).contiguous()
+        npt = g.shape[0]
+        dev = g.device
+        E = torch.empty(npt, dtype=torch.float64, device=dev)
+        pe = torch.empty(npt, len(self.plans), dtype=torch.float64, device=dev) if per_edge else None
+        dg = torch.empty(npt, self.p, dtype=torch.float64, device=dev) if grad else None
+        db = torch.empty(npt, self.p, dtype=torch.float64, device=dev) if grad else None
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        L.check(lib.qt_energy_grad(self._arr, len(self.plans), npt, g.data_ptr(), b.data_ptr(), E.data_ptr(),
+                                   dg.data_ptr() if grad else None, db.data_ptr() if grad else None,
+                                   pe.data_ptr() if per_edge else None, s))
+        out = [E]
+        if per_edge:
+            out.append(pe)
+        if grad:
+            out += [dg, db]
+        return out[0] if len(out) == 1 else tuple(out)
+
+
+def _energy_function():
+    import torch
+
+    class QAOAEnergy(torch.autograd.Function):
+        """E(gamma, beta) per point; backward uses the adjoint gradient that
+        the same ``qt_energy_grad`` launch computes (reverse bucket
+        elimination), so no second contraction runs."""
+
+        @staticmethod
+        def forward(ctx, model, gammas, betas):
+            need = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+            if need:
+                E, dg, db = model.energy_device(gammas, betas, grad=True)
+                ctx.save_for_backward(dg, db)
+            else:
+                E = model.energy_device(gammas, betas)
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            dg, db = ctx.saved_tensors
+            w = gE.to(torch.float64).unsqueeze(1)
+            return None, w * dg, w * db
+
+    return QAOAEnergy
+
+
+_QAOA_ENERGY = None
+
+
+def qaoa_energy(model: EnergyModel, gammas, betas):
+    """Differentiable E per point: gammas, betas are float64 GPU tensors [n_points, p]."""
+    global _QAOA_ENERGY
+    if _QAOA_ENERGY is None:
+        _QAOA_ENERGY = _energy_function()
+    return _QAOA_ENERGY.apply(model, gammas, betas)

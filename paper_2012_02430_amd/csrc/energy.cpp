@@ -10,7 +10,9 @@
 // numbers and dropped when a plan is freed.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 
 #include "qt_internal.h"
@@ -18,17 +20,100 @@
 namespace qt {
 namespace {
 
+#define QT_TRY(expr)            \
+  do {                          \
+    qt_status _s = (expr);      \
+    if (_s != QT_OK) return _s; \
+  } while (0)
+
+
 struct Program {
   bool fits = true;
+  bool global = false;  // gradient schedule run level by level from global scratch
   std::vector<XStep> steps;
+  std::vector<XRev> revs;
   std::vector<uint2> units;
   std::vector<int32_t> levels;
   std::vector<XFinal> finals;
-  int n_levels = 0, n_slots = 0, lds_elems = 0;
+  std::vector<int32_t> rec_off;  // gradient programs: 2p + 1 record offsets
+  int n_levels = 0, n_slots = 0, n_recs = 0, lds_elems = 0;
+  int dropped = 0, recomputed = 0;
   double log2_const = 0, cost = 0, bytes_c64 = 0, flops = 0;
 };
 
-qt_status build_program(const qt_plan& plan, int elt, int64_t lds_bytes, Program& pg) {
+// Operand location of a tensor for one use: LDS element offset and scale slot.
+struct Loc {
+  uint32_t off;
+  int32_t slot;
+};
+
+int gate_offset(const qt_plan& plan, int t) {
+  const Leaf& L = plan.net.leaves[plan.tensors[t].leaf];
+  return x_gate_off(L.kind, L.layer);
+}
+
+// Descriptor of bucket step s writing (out) and reading its inputs where
+// loc(tensor) says (gate leaves read the gate table).
+template <class LocFn>
+qt_status fill_xstep(const qt_plan& plan, int s, int elt, Loc out, LocFn loc, XStep& xs) {
+  const SymStep& st = plan.steps[s];
+  std::memset(&xs, 0, sizeof(xs));
+  xs.out.ptr = nullptr;
+  xs.out.lds_off = out.off;
+  xs.out.slot_kind = 1;
+  xs.out.slot = out.slot;
+  xs.r = st.rank;
+  xs.sum = st.sum;
+  xs.n_in = x_nin_class((int)st.ins.size());
+  const int epu = x_epu(st.rank, (int)st.ins.size(), elt);
+  for (size_t j = 0; j < st.ins.size(); ++j) {
+    const SymIn& si = st.ins[j];
+    XOp& x = xs.in[j];
+    x.slot = -1;
+    if (plan.tensors[si.tensor].leaf >= 0) {
+      const int g = gate_offset(plan, si.tensor);
+      if (g < 0) return fail(QT_EUNSUPPORTED, "qt_energy_grad: dense tensors are not supported in lightcones");
+      x.lds_off = (uint32_t)g;
+    } else {
+      const Loc l = loc(si.tensor);
+      x.lds_off = l.off;
+      x.slot = l.slot;
+    }
+    x.has_v = si.has_v;
+    int32_t nr = 0;
+    if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr))
+      return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
+    for (int e = 0; e < 4; ++e) {
+      uint32_t r = 0;
+      if (e < epu)
+        for (int q = 0; q < nr; ++q)
+          r |= (((uint32_t)(64 * e) >> x.run_lo[q]) & ((1u << x.run_len[q]) - 1u)) << x.run_dst[q];
+      x.ep[e] = r;
+    }
+  }
+  for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {
+    XOp& id = xs.in[j];  // identity operand
+    std::memset(&id, 0, sizeof(id));
+    id.has_v = 1;
+    id.slot = -1;
+  }
+  return QT_OK;
+}
+
+void push_step_units(const qt_plan& plan, int s, int xs_index, int elt, std::vector<uint2>& units) {
+  const int r = plan.steps[s].rank;
+  const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, (int)plan.steps[s].ins.size(), elt));
+  for (int64_t c = 0; c < chunks; ++c) units.push_back(make_uint2((uint32_t)xs_index, (uint32_t)c));
+}
+
+int count_intermediates(const qt_plan& plan) {
+  int n = 0;
+  for (const SymTensor& T : plan.tensors) n += T.leaf < 0;
+  return n;
+}
+
+// Forward-only program: every intermediate in LDS over its level interval.
+qt_status build_program(const qt_plan& plan, int elt, int64_t cap_elems, Program& pg) {
   if (!plan.slice_vars.empty()) return fail(QT_EINVAL, "qt_energy_grad: lightcone plans take no slicing");
   const int nsteps = (int)plan.steps.size();
   const int ntens = (int)plan.tensors.size();
@@ -49,62 +134,20 @@ qt_status build_program(const qt_plan& plan, int elt, int64_t lds_bytes, Program
   }
   std::vector<int64_t> off(ntens, -1);
   const int64_t top = place_intervals(iv, off);
-  const int tbase = x_tensor_base(plan.net.p);
-  const int64_t cap = (lds_bytes - 8 * (int64_t)(iv.size() + 4)) / elt - tbase;
-  if (top > cap) {
+  if (top > cap_elems) {
     pg.fits = false;  // contracted through the general schedule instead
     return QT_OK;
   }
   std::vector<int> slot(ntens, -1);
   for (const Interval& it : iv) slot[it.t] = pg.n_slots++;
+  const int tbase = x_tensor_base(plan.net.p);
   pg.lds_elems = (int)top + tbase;
   pg.log2_const = plan.log2_const;
-
+  auto loc = [&](int t) { return Loc{(uint32_t)(off[t] + tbase), slot[t]}; };
   pg.steps.assign(nsteps, XStep{});
   for (int i = 0; i < nsteps; ++i) {
     const SymStep& st = plan.steps[i];
-    XStep& xs = pg.steps[i];
-    std::memset(&xs, 0, sizeof(xs));
-    xs.out.ptr = nullptr;
-    xs.out.lds_off = (uint32_t)(off[st.out] + tbase);
-    xs.out.slot_kind = 1;
-    xs.out.slot = slot[st.out];
-    xs.r = st.rank;
-    xs.sum = st.sum;
-    xs.n_in = x_nin_class((int)st.ins.size());
-    const int epu = x_epu(st.rank, (int)st.ins.size(), elt);
-    for (size_t j = 0; j < st.ins.size(); ++j) {
-      const SymIn& si = st.ins[j];
-      const SymTensor& T = plan.tensors[si.tensor];
-      XOp& x = xs.in[j];
-      x.slot = -1;
-      if (T.leaf >= 0) {
-        const Leaf& L = plan.net.leaves[T.leaf];
-        const int g = x_gate_off(L.kind, L.layer);
-        if (g < 0) return fail(QT_EUNSUPPORTED, "qt_energy_grad: dense tensors are not supported in lightcones");
-        x.lds_off = (uint32_t)g;
-      } else {
-        x.lds_off = (uint32_t)(off[si.tensor] + tbase);
-        x.slot = slot[si.tensor];
-      }
-      x.has_v = si.has_v;
-      int32_t nr = 0;
-      if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr))
-        return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
-      for (int e = 0; e < 4; ++e) {
-        uint32_t r = 0;
-        if (e < epu)
-          for (int q = 0; q < nr; ++q)
-            r |= (((uint32_t)(64 * e) >> x.run_lo[q]) & ((1u << x.run_len[q]) - 1u)) << x.run_dst[q];
-        x.ep[e] = r;
-      }
-    }
-    for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {
-      XOp& id = xs.in[j];  // identity operand
-      std::memset(&id, 0, sizeof(id));
-      id.has_v = 1;
-      id.slot = -1;
-    }
+    QT_TRY(fill_xstep(plan, i, elt, loc(st.out), loc, pg.steps[i]));
     pg.cost += std::ldexp(1.0, st.rank) * (double)st.ins.size();
     pg.bytes_c64 += st.bytes_c64;
     pg.flops += st.flops;
@@ -112,35 +155,402 @@ qt_status build_program(const qt_plan& plan, int elt, int64_t lds_bytes, Program
   for (int L = 0; L < pg.n_levels; ++L) {
     pg.levels.push_back((int32_t)pg.units.size());
     for (int i = 0; i < nsteps; ++i)
-      if (depth[i] == L) {
-        const int r = plan.steps[i].rank;
-        const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, (int)plan.steps[i].ins.size(), elt));
-        for (int64_t c = 0; c < chunks; ++c) pg.units.push_back(make_uint2((uint32_t)i, (uint32_t)c));
-      }
+      if (depth[i] == L) push_step_units(plan, i, i, elt, pg.units);
   }
   pg.levels.push_back((int32_t)pg.units.size());
   for (int t : plan.finals) {
     if (plan.tensors[t].leaf >= 0) return fail(QT_EPLAN, "qt_energy_grad: internal: leaf as closing scalar");
-    pg.finals.push_back({(uint32_t)(off[t] + tbase), slot[t]});
+    pg.finals.push_back({loc(t).off, loc(t).slot});
   }
   return QT_OK;
 }
 
+// ---------------------------------------------------------------- adjoint
+// Reverse bucket elimination.  Every tensor of a bucket-elimination plan has
+// exactly one consumer (a step, or the closing product), so the reverse
+// pass visits the steps in reverse order and each input's adjoint is formed
+// once, by its consumer's reverse operation; no accumulation is needed.
+//
+// Checkpointing: a subset C of the intermediates keeps its forward value
+// until its consumer's reverse operation; the others are dropped after
+// their forward use and recomputed, by their step re-run in the reverse
+// schedule once the adjoint of their nearest kept ancestor exists.  The
+// schedule (forward levels, the closing adjoints, recomputation and reverse
+// levels) and the LDS intervals follow from C; C starts as every
+// intermediate and loses one tensor at a time, the one whose loss gives the
+// smallest LDS peak, until the program fits.
+struct GradSched {
+  std::vector<int> lf, lr, lb;  // forward, recompute (-1: none), reverse level per step
+  int lfa = 0, n_levels = 0;
+  std::vector<Interval> iv;     // interval ids 3 t + {0: value, 1: recomputed value, 2: adjoint}
+  std::vector<int64_t> off;
+  int64_t top = 0;
+  double recompute = 0;
+};
+
+void grad_schedule(const qt_plan& plan, const std::vector<char>& keep, GradSched& g) {
+  const auto& T = plan.tensors;
+  const auto& S = plan.steps;
+  const int ns = (int)S.size(), nt = (int)T.size();
+  g.lf.assign(ns, 0);
+  g.lr.assign(ns, -1);
+  g.lb.assign(ns, -1);
+  for (int s = 0; s < ns; ++s)
+    for (const SymIn& in : S[s].ins)
+      if (T[in.tensor].leaf < 0) g.lf[s] = std::max(g.lf[s], g.lf[T[in.tensor].producer] + 1);
+  g.lfa = 0;
+  for (int t : plan.finals) g.lfa = std::max(g.lfa, g.lf[T[t].producer] + 1);
+  auto radj = [&](int t) { return T[t].consumer == -2 ? g.lfa : g.lb[T[t].consumer]; };
+  // level at which intermediate t's value is available to the reverse pass
+  std::function<int(int)> avail = [&](int t) -> int {
+    const int q = T[t].producer;
+    if (keep[t]) return g.lf[q];
+    if (g.lr[q] < 0) {
+      int u = t;
+      while (!keep[u]) u = S[T[u].consumer].out;
+      int l = radj(u);
+      for (const SymIn& in : S[q].ins)
+        if (T[in.tensor].leaf < 0) l = std::max(l, avail(in.tensor) + 1);
+      g.lr[q] = l;
+    }
+    return g.lr[q];
+  };
+  for (int s = ns - 1; s >= 0; --s) {
+    int l = radj(S[s].out);
+    for (const SymIn& in : S[s].ins)
+      if (T[in.tensor].leaf < 0) l = std::max(l, avail(in.tensor));
+    g.lb[s] = l + 1;
+  }
+  g.n_levels = g.lfa + 1;
+  g.recompute = 0;
+  for (int s = 0; s < ns; ++s) {
+    g.n_levels = std::max({g.n_levels, g.lf[s] + 1, g.lr[s] + 1, g.lb[s] + 1});
+    if (g.lr[s] >= 0) g.recompute += std::ldexp(1.0, S[s].rank) * (double)S[s].ins.size();
+  }
+  g.iv.clear();
+  for (int t = 0; t < nt; ++t) {
+    if (T[t].leaf >= 0) continue;
+    const int64_t size = std::max<int64_t>(2, 1ll << T[t].rank);
+    const int q = T[t].producer, c = T[t].consumer;
+    int end;
+    if (c == -2) end = g.n_levels - 1;
+    else if (keep[t]) end = std::max({g.lf[c], g.lr[c], g.lb[c]});
+    else end = g.lf[c];
+    g.iv.push_back({3 * t, size, g.lf[q], end});
+    if (!keep[t]) g.iv.push_back({3 * t + 1, size, g.lr[q], std::max(g.lr[c], g.lb[c])});
+    g.iv.push_back({3 * t + 2, size, radj(t), g.lb[q]});
+  }
+  g.off.assign(3 * (size_t)nt, -1);
+  std::vector<Interval> iv = g.iv;
+  g.top = place_intervals(iv, g.off);
+}
+
+bool add_run_pairs(const std::vector<std::pair<int, int>>& pairs, uint8_t* lo, uint8_t* len, uint8_t* dst) {
+  int n = 0;
+  for (size_t i = 0; i < pairs.size();) {
+    size_t e = i + 1;
+    while (e < pairs.size() && pairs[e].first == pairs[e - 1].first + 1 && pairs[e].second == pairs[e - 1].second + 1)
+      ++e;
+    if (n == kXRuns) return false;
+    lo[n] = (uint8_t)pairs[i].first;
+    len[n] = (uint8_t)(e - i);
+    dst[n] = (uint8_t)pairs[i].second;
+    ++n;
+    i = e;
+  }
+  return true;
+}
+
+// Maps the y (bits of zj) and c (bits of zc) counters onto an operand whose
+// element index is the compaction of the z bits in zo.
+bool fill_rop(uint64_t zj, uint64_t zc, uint64_t zo, XROp& op) {
+  std::vector<std::pair<int, int>> py, pc;
+  int iy = 0, ic = 0, io = 0;
+  for (int b = 0; b < 64; ++b) {
+    const bool inj = (zj >> b) & 1u, inc = (zc >> b) & 1u, ino = (zo >> b) & 1u;
+    if (ino) {
+      if (inj) py.emplace_back(iy, io);
+      if (inc) pc.emplace_back(ic, io);
+    }
+    iy += inj;
+    ic += inc;
+    io += ino;
+  }
+  return add_run_pairs(py, op.y_lo, op.y_len, op.y_dst) && add_run_pairs(pc, op.c_lo, op.c_len, op.c_dst);
+}
+
+int gate_deriv_kind(int kind) {
+  switch (kind) {
+    case QT_T_ZZ: return 0;
+    case QT_T_ZZ_DAG: return 1;
+    case QT_T_RX: return 2;
+    case QT_T_RX_DAG: return 3;
+    default: return -1;
+  }
+}
+
+int count_records(const qt_plan& plan) {
+  int n = 0;
+  for (const SymStep& st : plan.steps)
+    for (const SymIn& in : st.ins) {
+      const SymTensor& T = plan.tensors[in.tensor];
+      if (T.leaf >= 0 && gate_deriv_kind(plan.net.leaves[T.leaf].kind) >= 0) ++n;
+    }
+  return n;
+}
+
+qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, int prog_id, Program& pg) {
+  if (!plan.slice_vars.empty()) return fail(QT_EINVAL, "qt_energy_grad: lightcone plans take no slicing");
+  const auto& T = plan.tensors;
+  const auto& S = plan.steps;
+  const int ns = (int)S.size(), nt = (int)T.size(), p = plan.net.p;
+  for (int t : plan.finals)
+    if (T[t].leaf >= 0 || T[t].rank != 0) return fail(QT_EPLAN, "qt_energy_grad: internal: closing tensor is not a scalar");
+  std::vector<char> keep(nt, 0);
+  for (int t = 0; t < nt; ++t) keep[t] = T[t].leaf < 0;
+  GradSched g;
+  grad_schedule(plan, keep, g);
+  while (g.top > cap_elems) {
+    int best = -1;
+    GradSched bg;
+    for (int t = 0; t < nt; ++t) {
+      if (!keep[t] || T[t].consumer == -2) continue;
+      keep[t] = 0;
+      GradSched h;
+      grad_schedule(plan, keep, h);
+      keep[t] = 1;
+      if (best < 0 || h.top < bg.top || (h.top == bg.top && h.recompute < bg.recompute)) {
+        best = t;
+        bg = std::move(h);
+      }
+    }
+    if (best < 0) break;
+    keep[best] = 0;
+    ++pg.dropped;
+    g = std::move(bg);
+  }
+  if (g.top > cap_elems) {
+    if (env_int("QT_DEBUG_GRAD_SCHEDULE", 0))
+      std::fprintf(stderr, "[qt grad] program %d: needs %lld tensor elements after %d drops, %lld available\n", prog_id,
+                   (long long)g.top, pg.dropped, (long long)cap_elems);
+    pg.fits = false;
+    return QT_OK;
+  }
+  const int tbase = x_tensor_base(p);
+  pg.lds_elems = (int)g.top + tbase;
+  pg.log2_const = plan.log2_const;
+  pg.n_levels = g.n_levels;
+  // scale slots: forward value (shared by its recomputation), then adjoint
+  std::vector<int> sf(nt, -1), sb(nt, -1);
+  for (int t = 0; t < nt; ++t)
+    if (T[t].leaf < 0) {
+      sf[t] = pg.n_slots++;
+      sb[t] = pg.n_slots++;
+    }
+  auto at = [&](int id) { return (uint32_t)(g.off[id] + tbase); };
+  auto val = [&](int t) { return Loc{at(3 * t), sf[t]}; };
+  auto rval = [&](int t) { return keep[t] ? val(t) : Loc{at(3 * t + 1), sf[t]}; };
+  auto adj = [&](int t) { return Loc{at(3 * t + 2), sb[t]}; };
+
+  // forward steps keep their indices; recomputation steps follow
+  pg.steps.assign(ns, XStep{});
+  std::vector<int> rstep(ns, -1);
+  for (int s = 0; s < ns; ++s) {
+    QT_TRY(fill_xstep(plan, s, elt, val(S[s].out), val, pg.steps[s]));
+    pg.cost += std::ldexp(1.0, S[s].rank) * (double)S[s].ins.size();
+    pg.bytes_c64 += S[s].bytes_c64;
+    pg.flops += S[s].flops;
+  }
+  for (int s = 0; s < ns; ++s)
+    if (g.lr[s] >= 0) {
+      XStep xs;
+      QT_TRY(fill_xstep(plan, s, elt, rval(S[s].out), rval, xs));
+      rstep[s] = (int)pg.steps.size();
+      pg.steps.push_back(xs);
+      ++pg.recomputed;
+      pg.cost += std::ldexp(1.0, S[s].rank) * (double)S[s].ins.size();
+    }
+
+  // reverse operations, gate records grouped by parameter
+  struct RecRef {
+    int param, rev;
+  };
+  std::vector<RecRef> recs;
+  std::vector<std::vector<int>> revs_of(ns);
+  for (int s = 0; s < ns; ++s) {
+    const SymStep& st = S[s];
+    const int zs = st.sum ? 1 : 0;
+    const int nz = st.rank + zs;
+    const uint64_t full = (nz >= 64 ? ~0ull : ((1ull << nz) - 1ull));
+    auto zmask = [&](const SymIn& in) { return ((uint64_t)in.mask << zs) | (uint64_t)(in.has_v ? 1 : 0); };
+    const uint64_t zr = (((1ull << st.rank) - 1ull) << zs);
+    for (size_t j = 0; j < st.ins.size(); ++j) {
+      const int tj = st.ins[j].tensor;
+      int gk = -1, param = -1;
+      if (T[tj].leaf >= 0) {
+        const Leaf& L = plan.net.leaves[T[tj].leaf];
+        gk = gate_deriv_kind(L.kind);
+        if (gk < 0) continue;  // constant leaf
+        param = (gk < 2 ? 0 : p) + L.layer - 1;
+      }
+      XRev rv;
+      std::memset(&rv, 0, sizeof(rv));
+      const uint64_t zj = zmask(st.ins[j]);
+      const uint64_t zc = full & ~zj;
+      rv.ry = __builtin_popcountll(zj);
+      rv.nc = __builtin_popcountll(zc);
+      rv.n_ops = x_nin_class((int)st.ins.size());
+      rv.gate = gk;
+      rv.param = param;
+      rv.rec = -1;
+      if (gk < 0) {
+        const Loc a = adj(tj);
+        rv.out_off = a.off;
+        rv.out_slot = a.slot;
+      } else {
+        rv.out_slot = -1;
+      }
+      int o = 0;
+      const Loc ar = adj(st.out);
+      rv.op[o].lds_off = ar.off;
+      rv.op[o].slot = ar.slot;
+      if (!fill_rop(zj, zc, zr, rv.op[o])) return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
+      ++o;
+      for (size_t i = 0; i < st.ins.size(); ++i) {
+        if (i == j) continue;
+        const int ti = st.ins[i].tensor;
+        XROp& op = rv.op[o++];
+        if (T[ti].leaf >= 0) {
+          const int goff = gate_offset(plan, ti);
+          if (goff < 0) return fail(QT_EUNSUPPORTED, "qt_energy_grad: dense tensors are not supported in lightcones");
+          op.lds_off = (uint32_t)goff;
+          op.slot = -1;
+        } else {
+          const Loc l = rval(ti);
+          op.lds_off = l.off;
+          op.slot = l.slot;
+        }
+        if (!fill_rop(zj, zc, zmask(st.ins[i]), op))
+          return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
+      }
+      for (; o < rv.n_ops; ++o) rv.op[o].slot = -1;  // identity operands (element 0, no runs)
+      if (gk >= 0) recs.push_back({param, (int)pg.revs.size()});
+      revs_of[s].push_back((int)pg.revs.size());
+      pg.revs.push_back(rv);
+    }
+  }
+  std::stable_sort(recs.begin(), recs.end(), [](const RecRef& a, const RecRef& b) { return a.param < b.param; });
+  pg.rec_off.assign(2 * p + 1, 0);
+  for (size_t r = 0; r < recs.size(); ++r) {
+    pg.revs[recs[r].rev].rec = (int32_t)r;
+    pg.rec_off[recs[r].param + 1] = (int32_t)(r + 1);
+  }
+  for (int q = 1; q <= 2 * p; ++q) pg.rec_off[q] = std::max(pg.rec_off[q], pg.rec_off[q - 1]);
+  pg.n_recs = (int)recs.size();
+
+  for (int L = 0; L < g.n_levels; ++L) {
+    pg.levels.push_back((int32_t)pg.units.size());
+    for (int s = 0; s < ns; ++s) {
+      if (g.lf[s] == L) push_step_units(plan, s, s, elt, pg.units);
+      if (g.lr[s] == L) push_step_units(plan, s, rstep[s], elt, pg.units);
+    }
+    if (g.lfa == L) pg.units.push_back(make_uint2(kXUnitFinal, 0));
+    for (int s = 0; s < ns; ++s) {
+      if (g.lb[s] != L) continue;
+      for (int r : revs_of[s]) {
+        const int ry = pg.revs[r].ry;
+        const uint32_t chunks = ry >= 6 ? (1u << ry) / 64u : 1u;
+        for (uint32_t c = 0; c < chunks; ++c) pg.units.push_back(make_uint2(kXUnitRev | (uint32_t)r, c));
+      }
+    }
+  }
+  pg.levels.push_back((int32_t)pg.units.size());
+  for (int t : plan.finals) pg.finals.push_back({val(t).off, val(t).slot});
+  for (int t : plan.finals) pg.finals.push_back({adj(t).off, adj(t).slot});
+  if (env_int("QT_DEBUG_GRAD_SCHEDULE", 0))
+    std::fprintf(stderr,
+                 "[qt grad] program %d: %d steps, %d levels, %d reverse ops, %d records, %d dropped, %d recomputed, "
+                 "%d LDS elements\n",
+                 prog_id, ns, pg.n_levels, (int)pg.revs.size(), pg.n_recs, pg.dropped, pg.recomputed, pg.lds_elems);
+  return QT_OK;
+}
+
+uint32_t run_max(const uint8_t* lo, const uint8_t* len, const uint8_t* dst, uint64_t all) {
+  uint32_t r = 0;
+  for (int i = 0; i < kXRuns; ++i)
+    if (len[i]) r |= (uint32_t)(((all >> lo[i]) & ((1ull << len[i]) - 1ull)) << dst[i]);
+  return r;
+}
+
+// Every LDS element, scale slot and record a program's descriptors can
+// touch lies inside its areas.
+qt_status check_program(const Program& pg, int p) {
+  const uint32_t gate_end = (uint32_t)(kXGate + x_gate_elems(p));
+  auto in_range = [&](uint32_t off, uint64_t extent) { return (uint64_t)off + extent <= (uint64_t)pg.lds_elems; };
+  auto bad = [](const char* what) { return fail(QT_EPLAN, std::string("qt_energy_grad: internal: ") + what); };
+  for (const XStep& xs : pg.steps) {
+    if (!in_range(xs.out.lds_off, 1ull << xs.r) || xs.out.slot >= pg.n_slots) return bad("step output out of range");
+    for (int j = 0; j < xs.n_in; ++j) {
+      const XOp& x = xs.in[j];
+      const uint64_t all = (1ull << xs.r) - 1ull;
+      const uint64_t hi = ((uint64_t)run_max(x.run_lo, x.run_len, x.run_dst, all) << x.has_v) + x.has_v;
+      if (!in_range(x.lds_off, hi + 1) || x.slot >= pg.n_slots) return bad("step operand out of range");
+      if (x.slot < 0 && x.lds_off >= 2 && x.lds_off + hi >= gate_end) return bad("gate operand out of range");
+    }
+  }
+  for (const XRev& rv : pg.revs) {
+    if (rv.ry > 16 || rv.nc > 20) return bad("reverse operation too large");
+    if (rv.gate < 0 && (!in_range(rv.out_off, 1ull << rv.ry) || rv.out_slot < 0 || rv.out_slot >= pg.n_slots))
+      return bad("adjoint output out of range");
+    if (rv.gate >= 0 && (rv.rec < 0 || rv.rec >= pg.n_recs || rv.param < 0 || rv.param >= 2 * p))
+      return bad("gradient record out of range");
+    for (int o = 0; o < rv.n_ops; ++o) {
+      const XROp& op = rv.op[o];
+      const uint64_t hi = (uint64_t)run_max(op.y_lo, op.y_len, op.y_dst, (1ull << rv.ry) - 1ull) +
+                          run_max(op.c_lo, op.c_len, op.c_dst, (1ull << rv.nc) - 1ull);
+      if (!in_range(op.lds_off, hi + 1) || op.slot >= pg.n_slots) return bad("reverse operand out of range");
+    }
+  }
+  for (const XFinal& f : pg.finals)
+    if (!in_range(f.lds_off, 1) || f.slot >= pg.n_slots) return bad("closing scalar out of range");
+  for (const uint2& u : pg.units) {
+    const uint32_t kind = u.x & ~kXUnitIndex, idx = u.x & kXUnitIndex;
+    if ((kind == 0 && idx >= pg.steps.size()) || (kind == kXUnitRev && idx >= pg.revs.size()))
+      return bad("unit names no descriptor");
+  }
+  return QT_OK;
+}
+
+struct GlobalProg {
+  int prog = 0, n_levels = 0;
+  std::vector<int32_t> level_sizes;
+  int64_t arena_stride = 0;  // elements per item
+  int slot_stride = 0, rec_stride = 0;
+  size_t arena_off = 0, smax_off = 0, sexp_off = 0, gacc_off = 0;  // bytes into the scratch area
+};
+
 struct EnergyJob {
   std::vector<uint64_t> serials;
   int np = 0, precision = 0, p = 0;
+  bool grad = false;
+  int64_t budget = 0;
   int n_progs = 0;
   void* tables = nullptr;
   double* params = nullptr;
   double* out = nullptr;     // [np][n_progs][3]
   double* sums = nullptr;    // [np][3]
   double* reals = nullptr;   // [np] energies then [np][n_progs] per edge
+  double* gout = nullptr;    // gradient jobs: [np][n_progs][2p]
+  double* gsum = nullptr;    // [np][2p]
   XMulti multi{};
   int n_fit = 0;
+  char* scratch = nullptr;          // gradient programs run from global memory
+  std::vector<GlobalProg> global;
   std::vector<int> big;  // programs that do not fit in LDS
   double bytes_c64 = 0, flops = 0;
   ~EnergyJob() {
-    for (void* q : {tables, (void*)params, (void*)out, (void*)sums, (void*)reals})
+    for (void* q : {tables, (void*)params, (void*)out, (void*)sums, (void*)reals, (void*)gout, (void*)gsum,
+                    (void*)scratch})
       if (q) (void)hipFree(q);
   }
 };
@@ -157,23 +567,41 @@ qt_status alloc(T** p, size_t count) {
   return QT_OK;
 }
 
-#define QT_TRY(expr)            \
-  do {                          \
-    qt_status _s = (expr);      \
-    if (_s != QT_OK) return _s; \
-  } while (0)
-
-qt_status build_job(qt_plan* const* plans, int n, int np, EnergyJob& job) {
+qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds_bytes, EnergyJob& job) {
   const int elt = plans[0]->precision == QT_C128 ? 16 : 8;
-  const int64_t lds_bytes = std::min(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
+  const int p = plans[0]->net.p;
+  // one launch shares the largest slot and record areas: size every
+  // program's tensor area against them
+  int max_slots = 0, max_recs = 0;
+  for (int e = 0; e < n; ++e) {
+    const int ni = count_intermediates(*plans[e]);
+    max_slots = std::max(max_slots, grad ? 2 * ni : ni);
+    if (grad) max_recs = std::max(max_recs, count_records(*plans[e]));
+  }
+  const int64_t fixed = 8 * (int64_t)((max_slots + 3) & ~3) + 8 * (int64_t)((max_recs + 1) & ~1);
+  const int64_t cap_elems = (lds_bytes - fixed) / elt - x_tensor_base(p);
   std::vector<Program> progs(n);
-  for (int e = 0; e < n; ++e) QT_TRY(build_program(*plans[e], elt, lds_bytes, progs[e]));
+  for (int e = 0; e < n; ++e) {
+    if (grad) {
+      QT_TRY(build_grad_program(*plans[e], elt, cap_elems, e, progs[e]));
+      if (!progs[e].fits) {  // every intermediate kept, in global scratch
+        progs[e] = Program{};
+        QT_TRY(build_grad_program(*plans[e], elt, int64_t(1) << 40, e, progs[e]));
+        progs[e].global = true;
+      }
+    } else {
+      QT_TRY(build_program(*plans[e], elt, cap_elems, progs[e]));
+    }
+    if (progs[e].fits) QT_TRY(check_program(progs[e], p));
+  }
   std::vector<XProg> xp(n);
   std::vector<XStep> steps;
+  std::vector<XRev> revs;
   std::vector<uint2> units;
-  std::vector<int32_t> levels;
+  std::vector<int32_t> levels, rec_off;
   std::vector<XFinal> finals;
-  int max_lds = 0, max_slots = 0;
+  int max_lds = 0;
+  max_slots = max_recs = 0;
   for (int e = 0; e < n; ++e) {
     const Program& pg = progs[e];
     XProg& x = xp[e];
@@ -184,14 +612,22 @@ qt_status build_job(qt_plan* const* plans, int n, int np, EnergyJob& job) {
     x.n_levels = pg.n_levels;
     x.n_slots = pg.n_slots;
     x.finals_off = (int32_t)finals.size();
-    x.n_finals = (int32_t)pg.finals.size();
+    x.n_finals = (int32_t)(grad ? pg.finals.size() / 2 : pg.finals.size());
+    x.revs_off = (int32_t)revs.size();
+    x.recs_off = (int32_t)rec_off.size();
+    x.n_recs = pg.n_recs;
     x.log2_const = pg.log2_const;
     steps.insert(steps.end(), pg.steps.begin(), pg.steps.end());
+    revs.insert(revs.end(), pg.revs.begin(), pg.revs.end());
     units.insert(units.end(), pg.units.begin(), pg.units.end());
     levels.insert(levels.end(), pg.levels.begin(), pg.levels.end());
     finals.insert(finals.end(), pg.finals.begin(), pg.finals.end());
-    max_lds = std::max(max_lds, pg.lds_elems);
-    max_slots = std::max(max_slots, pg.n_slots);
+    rec_off.insert(rec_off.end(), pg.rec_off.begin(), pg.rec_off.end());
+    if (pg.fits && !pg.global) {
+      max_lds = std::max(max_lds, pg.lds_elems);
+      max_slots = std::max(max_slots, pg.n_slots);
+      max_recs = std::max(max_recs, pg.n_recs);
+    }
     job.bytes_c64 += pg.bytes_c64;
     job.flops += pg.flops;
   }
@@ -199,57 +635,100 @@ qt_status build_job(qt_plan* const* plans, int n, int np, EnergyJob& job) {
   // programs that do not fit in LDS run separately
   std::vector<int32_t> order;
   for (int e = 0; e < n; ++e) {
-    if (progs[e].fits) order.push_back(e);
-    else job.big.push_back(e);
+    if (progs[e].global) {
+      GlobalProg gp;
+      gp.prog = e;
+      gp.n_levels = progs[e].n_levels;
+      for (int L = 0; L < gp.n_levels; ++L) gp.level_sizes.push_back(progs[e].levels[L + 1] - progs[e].levels[L]);
+      gp.arena_stride = (progs[e].lds_elems + 31) & ~31;
+      gp.slot_stride = (progs[e].n_slots + 63) & ~63;
+      gp.rec_stride = (std::max(1, progs[e].n_recs) + 31) & ~31;
+      job.global.push_back(std::move(gp));
+    } else if (progs[e].fits) {
+      order.push_back(e);
+    } else {
+      job.big.push_back(e);
+    }
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return progs[a].cost > progs[b].cost; });
   job.n_fit = (int)order.size();
   auto pad = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t b0 = pad(xp.size() * sizeof(XProg)), b1 = pad(steps.size() * sizeof(XStep)),
-               b2 = pad(units.size() * sizeof(uint2)), b3 = pad(levels.size() * sizeof(int32_t)),
-               b4 = pad(std::max<size_t>(1, finals.size()) * sizeof(XFinal)), b5 = pad(order.size() * sizeof(int32_t));
-  const size_t total = b0 + b1 + b2 + b3 + b4 + std::max<size_t>(b5, 256);
-  std::vector<char> host(total, 0);
-  size_t o = 0;
-  auto put = [&](const void* src, size_t bytes, size_t span) {
-    if (bytes) std::memcpy(host.data() + o, src, bytes);
-    const size_t at = o;
-    o += span;
-    return at;
+  struct Part {
+    const void* src;
+    size_t bytes;
   };
-  const size_t o0 = put(xp.data(), xp.size() * sizeof(XProg), b0);
-  const size_t o1 = put(steps.data(), steps.size() * sizeof(XStep), b1);
-  const size_t o2 = put(units.data(), units.size() * sizeof(uint2), b2);
-  const size_t o3 = put(levels.data(), levels.size() * sizeof(int32_t), b3);
-  const size_t o4 = put(finals.data(), finals.size() * sizeof(XFinal), b4);
-  const size_t o5 = put(order.data(), order.size() * sizeof(int32_t), b5);
+  const Part parts[] = {{xp.data(), xp.size() * sizeof(XProg)},
+                        {steps.data(), steps.size() * sizeof(XStep)},
+                        {units.data(), units.size() * sizeof(uint2)},
+                        {levels.data(), levels.size() * sizeof(int32_t)},
+                        {finals.data(), finals.size() * sizeof(XFinal)},
+                        {order.data(), order.size() * sizeof(int32_t)},
+                        {revs.data(), revs.size() * sizeof(XRev)},
+                        {rec_off.data(), rec_off.size() * sizeof(int32_t)}};
+  constexpr int kParts = sizeof(parts) / sizeof(parts[0]);
+  size_t at[kParts], total = 0;
+  for (int i = 0; i < kParts; ++i) {
+    at[i] = total;
+    total += pad(std::max<size_t>(1, parts[i].bytes));
+  }
+  std::vector<char> host(total, 0);
+  for (int i = 0; i < kParts; ++i)
+    if (parts[i].bytes) std::memcpy(host.data() + at[i], parts[i].src, parts[i].bytes);
   QT_TRY(alloc((char**)&job.tables, total));
   QT_HIP_CHECK(hipMemcpy(job.tables, host.data(), total, hipMemcpyHostToDevice));
-  const int p = plans[0]->net.p;
   QT_TRY(alloc(&job.params, (size_t)np * 2 * std::max(1, p)));
   QT_TRY(alloc(&job.out, (size_t)np * n * 3));
   QT_TRY(alloc(&job.sums, (size_t)np * 3));
   QT_TRY(alloc(&job.reals, (size_t)np * (n + 1)));
+  if (grad) {
+    QT_TRY(alloc(&job.gout, (size_t)np * n * 2 * std::max(1, p)));
+    QT_TRY(alloc(&job.gsum, (size_t)np * 2 * std::max(1, p)));
+    // global scratch of the programs that do not fit in LDS, per item
+    size_t bytes = 0;
+    for (GlobalProg& gp : job.global) {
+      gp.arena_off = bytes;
+      bytes += (size_t)np * gp.arena_stride * elt;
+      gp.smax_off = bytes;
+      bytes += (size_t)np * gp.slot_stride * 4;
+      gp.sexp_off = bytes;
+      bytes += (size_t)np * gp.slot_stride * 4;
+      gp.gacc_off = bytes;
+      bytes += (size_t)np * gp.rec_stride * 8;
+    }
+    if (bytes) QT_TRY(alloc((char**)&job.scratch, bytes));
+  }
   char* base = (char*)job.tables;
   XMulti& m = job.multi;
-  m.progs = (const XProg*)(base + o0);
-  m.steps = (const XStep*)(base + o1);
-  m.units = (const uint2*)(base + o2);
-  m.level_off = (const int32_t*)(base + o3);
-  m.finals = (const XFinal*)(base + o4);
-  m.item_prog = (const int32_t*)(base + o5);
+  m.progs = (const XProg*)(base + at[0]);
+  m.steps = (const XStep*)(base + at[1]);
+  m.units = (const uint2*)(base + at[2]);
+  m.level_off = (const int32_t*)(base + at[3]);
+  m.finals = (const XFinal*)(base + at[4]);
+  m.item_prog = (const int32_t*)(base + at[5]);
+  m.revs = (const XRev*)(base + at[6]);
+  m.rec_off = (const int32_t*)(base + at[7]);
   m.params = job.params;
   m.out = job.out;
+  m.gout = job.gout;
   m.n_points = np;
   m.n_progs = n;
   m.p = p;
   m.lds_elems = max_lds;
   m.n_slots = max_slots;
+  m.n_recs = max_recs;
   job.np = np;
   job.n_progs = n;
   job.p = p;
+  job.grad = grad;
+  job.budget = lds_bytes;
   job.precision = plans[0]->precision;
   for (int e = 0; e < n; ++e) job.serials.push_back(plans[e]->serial);
+  if (env_int("QT_DEBUG_GRAD_SCHEDULE", 0))
+    std::fprintf(stderr, "[qt grad] job: %d of %d programs in LDS, %zu bytes of LDS per workgroup, %d from global scratch\n",
+                 job.n_fit, n,
+                 grad ? lds_grad_smem_bytes(max_slots, max_recs, max_lds, elt == 16)
+                      : lds_exec_smem_bytes(max_slots, max_lds, elt == 16),
+                 (int)job.global.size());
   return QT_OK;
 }
 
@@ -297,13 +776,15 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       if (lightcones[e]->net.p != p || lightcones[e]->precision != lightcones[0]->precision)
         return fail(QT_EINVAL, "qt_energy_grad: plans differ in p or precision");
     }
-    if (dE_dgamma || dE_dbeta) return fail(QT_EUNSUPPORTED, "qt_energy_grad: the gradient pass is not built yet");
+    const bool grad = dE_dgamma || dE_dbeta;
+    const int64_t lds_bytes = std::min<int64_t>(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
+    const int64_t budget = grad ? std::min<int64_t>(lds_bytes, env_int("QT_GRAD_LDS_BYTES", (int)lds_bytes)) : lds_bytes;
     hipStream_t stream = (hipStream_t)hip_stream;
     EnergyJob* job = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_mu);
       for (auto& j : g_jobs) {
-        if (j->np != n_points || (int)j->serials.size() != n_edges) continue;
+        if (j->np != n_points || (int)j->serials.size() != n_edges || j->grad != grad || j->budget != budget) continue;
         bool same = true;
         for (int e = 0; e < n_edges && same; ++e) same = j->serials[e] == lightcones[e]->serial;
         if (same) {
@@ -313,7 +794,7 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       }
       if (!job) {
         auto nj = std::make_unique<EnergyJob>();
-        QT_TRY(build_job(lightcones, n_edges, n_points, *nj));
+        QT_TRY(build_job(lightcones, n_edges, n_points, grad, budget, *nj));
         if (g_jobs.size() >= 16) g_jobs.erase(g_jobs.begin());
         g_jobs.push_back(std::move(nj));
         job = g_jobs.back().get();
@@ -327,11 +808,20 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_HIP_CHECK(hipMemcpy2DAsync(job->params + p, pitch, betas, p * sizeof(double), p * sizeof(double), n_points,
                                     hipMemcpyDefault, stream));
     }
-    const int waves = std::max(1, std::min(kXMaxThreads / 64, env_int("QT_LDS_WAVES_MULTI", 4)));
+    const int waves = std::max(1, std::min(kXMaxThreads / 64, env_int(grad ? "QT_LDS_WAVES_GRAD" : "QT_LDS_WAVES_MULTI", 4)));
     if (job->n_fit) {
       XMulti m = job->multi;
       m.n_progs = n_edges;  // output row length; items cover the fitting programs only
-      QT_HIP_CHECK(launch_lds_multi(m, job->n_fit, waves, c128, !c128, stream));
+      if (grad) QT_HIP_CHECK(launch_lds_grad(m, job->n_fit, waves, c128, !c128, stream));
+      else QT_HIP_CHECK(launch_lds_multi(m, job->n_fit, waves, c128, !c128, stream));
+    }
+    for (const GlobalProg& gp : job->global) {
+      XMulti m = job->multi;
+      m.n_progs = n_edges;
+      char* b = job->scratch;
+      QT_HIP_CHECK(launch_grad_global(m, gp.prog, gp.level_sizes.data(), gp.n_levels, b + gp.arena_off,
+                                      (uint32_t*)(b + gp.smax_off), (int*)(b + gp.sexp_off), (double*)(b + gp.gacc_off),
+                                      gp.arena_stride, gp.slot_stride, gp.rec_stride, c128, !c128, stream));
     }
     for (int e : job->big) {
       const double* sums = nullptr;
@@ -346,7 +836,20 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_HIP_CHECK(launch_amp_to_real(job->out, (int64_t)n_points * n_edges, job->reals + n_points, stream));
       QT_TRY(copy_out(per_edge, job->reals + n_points, (size_t)n_points * n_edges, stream));
     }
-    if (!is_device_ptr(energy) || (per_edge && !is_device_ptr(per_edge))) QT_HIP_CHECK(hipStreamSynchronize(stream));
+    bool host_out = !is_device_ptr(energy) || (per_edge && !is_device_ptr(per_edge));
+    if (grad && p > 0) {
+      QT_HIP_CHECK(launch_rows_sum(job->gout, n_points, n_edges, 2 * p, job->gsum, stream));
+      const size_t row = p * sizeof(double), pitch = 2 * p * sizeof(double);
+      if (dE_dgamma) {
+        QT_HIP_CHECK(hipMemcpy2DAsync(dE_dgamma, row, job->gsum, pitch, row, n_points, hipMemcpyDefault, stream));
+        host_out = host_out || !is_device_ptr(dE_dgamma);
+      }
+      if (dE_dbeta) {
+        QT_HIP_CHECK(hipMemcpy2DAsync(dE_dbeta, row, job->gsum + p, pitch, row, n_points, hipMemcpyDefault, stream));
+        host_out = host_out || !is_device_ptr(dE_dbeta);
+      }
+    }
+    if (host_out) QT_HIP_CHECK(hipStreamSynchronize(stream));
     return QT_OK;
   } catch (const std::exception& ex) {
     return fail(QT_ENOMEM, std::string("qt_energy_grad: ") + ex.what());

@@ -240,7 +240,8 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
     lds[tid].x = 1;
     lds[tid].y = 0;
   }
-  if (tid < x_gate_elems(X.p)) lds[kXGate + tid] = x_gate<E>(tid, X.params + (int64_t)c.pt * 2 * X.p, X.p);
+  for (int t = tid; t < x_gate_elems(X.p); t += blockDim.x)
+    lds[kXGate + t] = x_gate<E>(t, X.params + (int64_t)c.pt * 2 * X.p, X.p);
   // stage the segment's external inputs (with their scale slots)
   for (int e = wave; e < X.n_copies; e += nw) {
     const XCopy& cp = copies[e];
@@ -366,7 +367,8 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, cons
     lds[tid].x = 1;
     lds[tid].y = 0;
   }
-  if (tid < x_gate_elems(M.p)) lds[kXGate + tid] = x_gate<E>(tid, M.params + (int64_t)c.pt * 2 * M.p, M.p);
+  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x)
+    lds[kXGate + t] = x_gate<E>(t, M.params + (int64_t)c.pt * 2 * M.p, M.p);
   __syncthreads();
 
   constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
@@ -446,6 +448,415 @@ hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c
 hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_amp_to_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, amp, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace qt
+
+namespace qt {
+namespace {
+
+// Derivative of gate-table entry y (row-major over the gate's two bits) of a
+// parametrised gate by its parameter t, in FP64: ZZ(t) has 1 on the diagonal
+// and e^{-it} off it, ZZ^dagger e^{+it}; RX(t) has cos t on the diagonal and
+// -i sin t off it, RX^dagger +i sin t.
+__device__ __forceinline__ double2 x_dgate(int kind, uint32_t y, double t) {
+  double sn, cs;
+  sincos(t, &sn, &cs);
+  const bool diag = y == 0 || y == 3;
+  switch (kind) {
+    case 0: return diag ? make_double2(0.0, 0.0) : make_double2(-sn, -cs);
+    case 1: return diag ? make_double2(0.0, 0.0) : make_double2(-sn, cs);
+    case 2: return diag ? make_double2(-sn, 0.0) : make_double2(0.0, -cs);
+    default: return diag ? make_double2(-sn, 0.0) : make_double2(0.0, cs);
+  }
+}
+
+// One wavefront runs one unit of a reverse operation: 64 outputs y of a
+// large adjoint, or all 2^ry outputs of a small one with the complement
+// split over 64 / 2^ry lane groups and summed by a fixed butterfly.
+template <typename E, bool SCALED, int NOPS>
+__device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t lane, E* __restrict__ lds,
+                                        uint32_t* __restrict__ smax, int* __restrict__ sexp,
+                                        double* __restrict__ gacc, const double* prm) {
+  using R = typename XReal<E>::R;
+  const int ry = rv.ry;
+  const bool wide = ry >= 6;
+  const uint32_t y = wide ? chunk * 64u + lane : (lane & ((1u << ry) - 1u));
+  const uint32_t g = wide ? 0u : (lane >> ry);
+  const uint32_t G = wide ? 1u : (64u >> ry);
+  const uint32_t C = 1u << rv.nc;
+  uint32_t base[NOPS];
+  R sc[NOPS];
+  int eacc = 0;
+#pragma unroll
+  for (int o = 0; o < NOPS; ++o) {
+    const XROp& op = rv.op[o];
+    base[o] = op.lds_off + xpext_all(y, op.y_lo, op.y_len, op.y_dst);
+    sc[o] = (R)1;
+    if (SCALED && op.slot >= 0) {
+      const int sh = xshift(smax[op.slot]);
+      sc[o] = (R)xpow2neg(sh);
+      eacc += sexp[op.slot] + sh;
+    }
+  }
+  E acc;
+  acc.x = 0;
+  acc.y = 0;
+  for (uint32_t c = g; c < C; c += G) {
+    const XROp& op0 = rv.op[0];
+    E t = lds[base[0] + xpext_all(c, op0.c_lo, op0.c_len, op0.c_dst)];
+    if (SCALED) t = xscale(t, sc[0]);
+#pragma unroll
+    for (int o = 1; o < NOPS; ++o) {
+      const XROp& op = rv.op[o];
+      E x = lds[base[o] + xpext_all(c, op.c_lo, op.c_len, op.c_dst)];
+      if (SCALED) x = xscale(x, sc[o]);
+      t = xmul(t, x);
+    }
+    acc = xadd(acc, t);
+  }
+  if (!wide) {
+    for (uint32_t off = 1u << ry; off < 64u; off <<= 1) {
+      acc.x += __shfl_xor(acc.x, (int)off);
+      acc.y += __shfl_xor(acc.y, (int)off);
+    }
+  }
+  if (rv.gate >= 0) {
+    double v = 0.0;
+    if (g == 0) {
+      const double2 d = x_dgate(rv.gate, y, prm[rv.param]);
+      v = (double)acc.x * d.x - (double)acc.y * d.y;
+    }
+    for (uint32_t off = 1; off < (1u << ry); off <<= 1) v += __shfl_xor(v, (int)off);
+    if (lane == 0) gacc[rv.rec] = SCALED ? ldexp(v, eacc) : v;
+    return;
+  }
+  if (g == 0) lds[rv.out_off + y] = acc;
+  if (SCALED) {
+    float m = g == 0 ? fmaxf(fabsf((float)acc.x), fabsf((float)acc.y)) : 0.f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (lane == 0) {
+      atomicMax(smax + rv.out_slot, __float_as_uint(m));
+      if (chunk == 0) sexp[rv.out_slot] = eacc;
+    }
+  }
+}
+
+// Adjoints of a program's closing scalars: the item's value is
+// 2^log2_const times their product, so the adjoint of scalar f is
+// 2^log2_const times the product of the others (FP64, renormalised).
+template <typename E, bool SCALED>
+__device__ void x_final_adjoints(const XProg& P, const XFinal* __restrict__ fin, const E* lds, uint32_t* smax,
+                                 int* sexp, E* ldsw) {
+  const int nf = P.n_finals;
+  for (int f = 0; f < nf; ++f) {
+    double re = 1.0, im = 0.0;
+    int e = 0;
+    for (int h = 0; h < nf; ++h) {
+      if (h == f) continue;
+      const E a = lds[fin[h].lds_off];
+      const double ar = (double)a.x, ai = (double)a.y;
+      const double nr = re * ar - im * ai;
+      im = re * ai + im * ar;
+      re = nr;
+      if (SCALED && fin[h].slot >= 0) e += sexp[fin[h].slot];
+    }
+    const XFinal& B = fin[nf + f];
+    if (SCALED) {
+      const double fl = floor(P.log2_const);
+      const double s = exp2(P.log2_const - fl);
+      re *= s;
+      im *= s;
+      e += (int)fl;
+      const double m = fmax(fabs(re), fabs(im));
+      if (m > 0.0) {
+        const int k = ilogb(m) + 1;
+        re = ldexp(re, -k);
+        im = ldexp(im, -k);
+        e += k;
+      }
+      E v;
+      v.x = (typename XReal<E>::R)re;
+      v.y = (typename XReal<E>::R)im;
+      ldsw[B.lds_off] = v;
+      smax[B.slot] = __float_as_uint(fmaxf(fabsf((float)re), fabsf((float)im)));
+      sexp[B.slot] = e;
+    } else {
+      const double s = exp2(P.log2_const);
+      E v;
+      v.x = (typename XReal<E>::R)(re * s);
+      v.y = (typename XReal<E>::R)(im * s);
+      ldsw[B.lds_off] = v;
+    }
+  }
+}
+
+// One unit of the gradient schedule: a forward or recomputation step, a
+// reverse operation, or the adjoints of the closing scalars.
+template <typename E, bool SCALED>
+__device__ __forceinline__ void x_grad_unit(const uint2 un, const XStep* __restrict__ psteps,
+                                            const XRev* __restrict__ prevs, const XProg& P,
+                                            const XFinal* __restrict__ pfin, const XCtx& c, E* __restrict__ lds,
+                                            uint32_t* __restrict__ smax, int* __restrict__ sexp,
+                                            double* __restrict__ gacc, const double* prm) {
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  const uint32_t kind = un.x & ~kXUnitIndex;
+  const uint32_t idx = un.x & kXUnitIndex;
+  if (kind == 0) {
+    const XStep& st = psteps[idx];
+    const bool big = st.r >= kXBigRank;
+    if (st.n_in <= 2) {
+      if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+    } else if (st.n_in <= 4) {
+      if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+    } else {
+      if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+    }
+  } else if (kind == kXUnitRev) {
+    const XRev& rv = prevs[idx];
+    if (rv.n_ops <= 2) x_runit<E, SCALED, 2>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
+    else if (rv.n_ops <= 4) x_runit<E, SCALED, 4>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
+    else x_runit<E, SCALED, 8>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
+  } else if (c.lane == 0) {
+    x_final_adjoints<E, SCALED>(P, pfin, lds, smax, sexp, lds);
+  }
+}
+
+// Item value (thread 0: product of the closing scalars, FP64, with the
+// accumulated exponent) and its 2p derivatives (threads 1..2p: each the sum
+// of its parameter's gradient records in record order).
+template <typename E, bool SCALED>
+__device__ __forceinline__ void x_grad_epilogue(const XMulti& M, const XProg& P, int prog_id,
+                                                const XFinal* __restrict__ pfin, const int32_t* __restrict__ rec_off,
+                                                uint32_t pt, int tid, const E* lds, const int* sexp,
+                                                const double* gacc) {
+  if (tid == 0) {
+    double re = 1.0, im = 0.0, ex = P.log2_const;
+    for (int f = 0; f < P.n_finals; ++f) {
+      const XFinal& F = pfin[f];
+      const E a = lds[F.lds_off];
+      const double ar = (double)a.x, ai = (double)a.y;
+      if (SCALED && F.slot >= 0) ex += sexp[F.slot];
+      const double nr = re * ar - im * ai;
+      im = re * ai + im * ar;
+      re = nr;
+    }
+    double* o = M.out + 3 * ((int64_t)pt * M.n_progs + prog_id);
+    o[0] = re;
+    o[1] = im;
+    o[2] = ex;
+  } else if (tid <= 2 * M.p) {
+    const int q = tid - 1;
+    const int32_t* ro = rec_off + P.recs_off;
+    double s = 0.0;
+    for (int r = ro[q]; r < ro[q + 1]; ++r) s += gacc[r];
+    M.gout[((int64_t)pt * M.n_progs + prog_id) * 2 * M.p + q] = s;
+  }
+}
+
+// Gradient executor: one workgroup per (program, point) item runs the
+// program's forward steps, the adjoints of its closing scalars, its
+// recomputation steps and its reverse operations, all from one level
+// schedule, then forms the item's value (as the multi-program executor) and
+// its derivatives by the 2p parameters, each the FP64 sum of the parameter's
+// gradient records in record order.
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(kXMaxThreads) void k_lds_grad(const XMulti M, const XProg* __restrict__ progs,
+                                                           const XStep* __restrict__ steps,
+                                                           const XRev* __restrict__ revs,
+                                                           const uint2* __restrict__ units,
+                                                           const int32_t* __restrict__ level_off,
+                                                           const XFinal* __restrict__ finals,
+                                                           const int32_t* __restrict__ item_prog,
+                                                           const int32_t* __restrict__ rec_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int slots16 = (M.n_slots + 3) & ~3;
+  const int recs2 = (M.n_recs + 1) & ~1;
+  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
+  int* sexp = reinterpret_cast<int*>(smem + 4 * slots16);
+  double* gacc = reinterpret_cast<double*>(smem + 8 * slots16);
+  E* lds = reinterpret_cast<E*>(smem + 8 * slots16 + 8 * recs2);
+
+  const uint32_t item = blockIdx.x;
+  const int prog_id = item_prog[item / (uint32_t)M.n_points];
+  const XProg& P = progs[prog_id];
+  XCtx c;
+  c.pt = item % (uint32_t)M.n_points;
+  c.sb = 0;
+  c.sid = 0;
+  const int tid = threadIdx.x;
+  c.lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nw = blockDim.x >> 6;
+  const double* prm = M.params + (int64_t)c.pt * 2 * M.p;
+
+  for (int i = tid; i < P.n_slots; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  if (tid < 2) {
+    lds[tid].x = 1;
+    lds[tid].y = 0;
+  }
+  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x) lds[kXGate + t] = x_gate<E>(t, prm, M.p);
+  __syncthreads();
+
+  const XStep* psteps = steps + P.steps_off;
+  const XRev* prevs = revs + P.revs_off;
+  const uint2* punits = units + P.units_off;
+  const int32_t* plev = level_off + P.levels_off;
+  const XFinal* pfin = finals + P.finals_off;
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw)
+      x_grad_unit<E, SCALED>(punits[u], psteps, prevs, P, pfin, c, lds, smax, sexp, gacc, prm);
+    __syncthreads();
+  }
+  x_grad_epilogue<E, SCALED>(M, P, prog_id, pfin, rec_off, c.pt, tid, lds, sexp, gacc);
+}
+
+// The gradient schedule of one program whose tensors do not fit in LDS,
+// run level by level, one launch per level, with each item's tensors, scale
+// slots and gradient records in its own slice of a global scratch area.
+// Launch boundaries order every write before the reads of later levels.
+struct XScratch {
+  void* arena;          // [points][arena_stride] elements
+  uint32_t* smax;       // [points][slot_stride]
+  int* sexp;            // [points][slot_stride]
+  double* gacc;         // [points][rec_stride]
+  int64_t arena_stride;
+  int32_t slot_stride;
+  int32_t rec_stride;
+};
+
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(64) void k_grad_init(const XMulti M, const XProg* __restrict__ progs, int prog_id,
+                                                  const XScratch S) {
+  const XProg& P = progs[prog_id];
+  const uint32_t pt = blockIdx.x;
+  E* lds = reinterpret_cast<E*>(S.arena) + (int64_t)pt * S.arena_stride;
+  uint32_t* smax = S.smax + (int64_t)pt * S.slot_stride;
+  int* sexp = S.sexp + (int64_t)pt * S.slot_stride;
+  for (int i = threadIdx.x; i < P.n_slots; i += 64) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  if (threadIdx.x < 2) {
+    lds[threadIdx.x].x = 1;
+    lds[threadIdx.x].y = 0;
+  }
+  for (int t = threadIdx.x; t < x_gate_elems(M.p); t += 64)
+    lds[kXGate + t] = x_gate<E>(t, M.params + (int64_t)pt * 2 * M.p, M.p);
+}
+
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(64) void k_grad_level(const XMulti M, const XProg* __restrict__ progs,
+                                                   const XStep* __restrict__ steps, const XRev* __restrict__ revs,
+                                                   const uint2* __restrict__ units,
+                                                   const int32_t* __restrict__ level_off,
+                                                   const XFinal* __restrict__ finals, int prog_id, int level,
+                                                   const XScratch S) {
+  const XProg& P = progs[prog_id];
+  XCtx c;
+  c.pt = blockIdx.y;
+  c.sb = 0;
+  c.sid = 0;
+  c.lane = threadIdx.x;
+  E* lds = reinterpret_cast<E*>(S.arena) + (int64_t)c.pt * S.arena_stride;
+  uint32_t* smax = S.smax + (int64_t)c.pt * S.slot_stride;
+  int* sexp = S.sexp + (int64_t)c.pt * S.slot_stride;
+  double* gacc = S.gacc + (int64_t)c.pt * S.rec_stride;
+  const int u = level_off[P.levels_off + level] + blockIdx.x;
+  x_grad_unit<E, SCALED>(units[P.units_off + u], steps + P.steps_off, revs + P.revs_off, P, finals + P.finals_off, c,
+                         lds, smax, sexp, gacc, M.params + (int64_t)c.pt * 2 * M.p);
+}
+
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(64) void k_grad_final(const XMulti M, const XProg* __restrict__ progs,
+                                                   const XFinal* __restrict__ finals,
+                                                   const int32_t* __restrict__ rec_off, int prog_id,
+                                                   const XScratch S) {
+  const XProg& P = progs[prog_id];
+  const uint32_t pt = blockIdx.x;
+  const E* lds = reinterpret_cast<const E*>(S.arena) + (int64_t)pt * S.arena_stride;
+  x_grad_epilogue<E, SCALED>(M, P, prog_id, finals + P.finals_off, rec_off, pt, (int)threadIdx.x, lds,
+                             S.sexp + (int64_t)pt * S.slot_stride, S.gacc + (int64_t)pt * S.rec_stride);
+}
+
+// One workgroup per output (r, q): lane-strided partial sums in index order,
+// then a fixed tree, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_rows_sum(const double* __restrict__ in, int n, int nq,
+                                                  double* __restrict__ out) {
+  __shared__ double part[256];
+  const int r = blockIdx.x / nq, q = blockIdx.x % nq;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += in[((int64_t)r * n + i) * nq + q];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+}  // namespace
+
+size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128) {
+  const size_t slots16 = (size_t)((n_slots + 3) & ~3);
+  const size_t recs2 = (size_t)((n_recs + 1) & ~1);
+  return 8 * slots16 + 8 * recs2 + (size_t)lds_elems * (c128 ? 16 : 8);
+}
+
+hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled, hipStream_t stream) {
+  const int64_t n_items = (int64_t)n_item_progs * m.n_points;
+  if (n_items == 0) return hipSuccess;
+  const size_t smem = lds_grad_smem_bytes(m.n_slots, m.n_recs, m.lds_elems, c128);
+  const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
+  const void* fn = c128 ? reinterpret_cast<const void*>(&k_lds_grad<double2, false>)
+                        : (scaled ? reinterpret_cast<const void*>(&k_lds_grad<float2, true>)
+                                  : reinterpret_cast<const void*>(&k_lds_grad<float2, false>));
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  if (c128)
+    hipLaunchKernelGGL((k_lds_grad<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
+                       m.level_off, m.finals, m.item_prog, m.rec_off);
+  else if (scaled)
+    hipLaunchKernelGGL((k_lds_grad<float2, true>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
+                       m.level_off, m.finals, m.item_prog, m.rec_off);
+  else
+    hipLaunchKernelGGL((k_lds_grad<float2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
+                       m.level_off, m.finals, m.item_prog, m.rec_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
+                              uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
+                              int rec_stride, bool c128, bool scaled, hipStream_t stream) {
+  const XScratch S{arena, smax, sexp, gacc, arena_stride, slot_stride, rec_stride};
+  const unsigned np = (unsigned)m.n_points;
+  auto go = [&](auto init, auto level, auto fin) -> hipError_t {
+    hipLaunchKernelGGL(init, dim3(np), dim3(64), 0, stream, m, m.progs, prog_id, S);
+    for (int L = 0; L < n_levels; ++L)
+      if (level_sizes[L] > 0)
+        hipLaunchKernelGGL(level, dim3((unsigned)level_sizes[L], np), dim3(64), 0, stream, m, m.progs, m.steps, m.revs,
+                           m.units, m.level_off, m.finals, prog_id, L, S);
+    hipLaunchKernelGGL(fin, dim3(np), dim3(64), 0, stream, m, m.progs, m.finals, m.rec_off, prog_id, S);
+    return hipGetLastError();
+  };
+  if (c128) return go(k_grad_init<double2, false>, k_grad_level<double2, false>, k_grad_final<double2, false>);
+  if (scaled) return go(k_grad_init<float2, true>, k_grad_level<float2, true>, k_grad_final<float2, true>);
+  return go(k_grad_init<float2, false>, k_grad_level<float2, false>, k_grad_final<float2, false>);
+}
+
+hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream) {
+  if (rows == 0 || nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)(rows * nq)), dim3(256), 0, stream, in, n, nq, out);
   return hipGetLastError();
 }
 

@@ -220,11 +220,46 @@ struct XProg {
   int32_t levels_off;  // first of its n_levels + 1 level offsets (relative to units_off)
   int32_t n_levels;
   int32_t n_slots;
-  int32_t finals_off;
+  int32_t finals_off;  // gradient programs: n_finals values, then their n_finals adjoints
   int32_t n_finals;
-  int32_t pad;
+  int32_t revs_off;    // first XRev (gradient programs; units name them relative to it)
+  int32_t recs_off;    // first of 2p + 1 offsets of its gradient records, grouped by parameter
+  int32_t n_recs;
   double log2_const;   // exponent of the |+> normalisations
 };
+
+// Reverse (adjoint) operation of the gradient executor.  For one input T_j
+// of a bucket step with output R (Algorithm 1 run backwards), over the
+// step's index space z (the output bits, and the summed variable as bit 0):
+//   Tbar_j[y] = sum_c Rbar[.] * prod_{i != j} T_i[.]
+// where y runs over the bits of T_j and c over the remaining bits of z.
+// Operand o is read at lds_off + map_y(y) + map_c(c), each map a list of
+// bit runs (source bit, length, destination bit); padding operands read the
+// identity element.  For a gate input the result is not stored: it is
+// contracted with the gate's derivative by its parameter and kept as one
+// FP64 gradient record.
+struct XROp {
+  uint32_t lds_off;
+  int32_t slot;  // scale slot, -1: unscaled
+  uint8_t y_lo[kXRuns], y_len[kXRuns], y_dst[kXRuns];
+  uint8_t c_lo[kXRuns], c_len[kXRuns], c_dst[kXRuns];
+};
+struct XRev {
+  uint32_t out_off;   // LDS element offset of Tbar_j
+  int32_t out_slot;   // its scale slot (-1: unscaled)
+  int32_t ry;         // bits of y (rank of T_j)
+  int32_t nc;         // bits of c
+  int32_t n_ops;      // operand class: 2, 4 or 8
+  int32_t gate;       // -1: tensor adjoint; 0..3: derivative of ZZ, ZZ^dagger, RX, RX^dagger
+  int32_t param;      // gate parameter: layer k's gamma at k, its beta at p + k
+  int32_t rec;        // gradient record of a gate input
+  XROp op[kMaxIn];
+};
+// Unit kinds of the gradient executor (top bits of a unit's first word).
+constexpr uint32_t kXUnitRev = 1u << 30;    // reverse operation
+constexpr uint32_t kXUnitFinal = 2u << 30;  // adjoints of the closing scalars
+constexpr uint32_t kXUnitIndex = (1u << 30) - 1u;
+
 struct XMulti {
   const XProg* progs;
   const XStep* steps;
@@ -234,12 +269,15 @@ struct XMulti {
   const int32_t* item_prog;
   const double* params;    // [points][2p]
   double* out;             // [points][programs][3]: re, im, log2 scale
+  const XRev* revs;        // gradient executor only
+  const int32_t* rec_off;
+  double* gout;            // [points][programs][2p]: per-edge derivatives
   int32_t n_points;
   int32_t n_progs;
   int32_t p;
   int32_t lds_elems;       // max over programs
   int32_t n_slots;         // max over programs
-  int32_t pad;
+  int32_t n_recs;          // max over programs
 };
 
 // Leaf (gate) tensor materialisation record.
@@ -361,6 +399,16 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
                            uint32_t* maxbits, hipStream_t stream);
 hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
                             hipStream_t stream);
+hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
+                           hipStream_t stream);
+size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128);
+// The gradient schedule of one program with its tensors in global scratch,
+// one launch per level (level_sizes: units per level, host memory).
+hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
+                              uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
+                              int rec_stride, bool c128, bool scaled, hipStream_t stream);
+// out[r][q] = sum_i in[(r * n + i) * nq + q] in FP64, in order of i.
+hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream);
 hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream);
 size_t lds_exec_smem_bytes(int n_slots, int lds_elems, bool c128);
 hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,

@@ -84,13 +84,14 @@ def energy_bench(steps, warmup, cpu_seconds):
 
     import oracle
     from paper_2012_02430_amd import _lib as L
-    from paper_2012_02430_amd import api
+    from paper_2012_02430_amd import api, autotune
     from workloads import qaoa_params, regular_graph
 
     n, p, npt = 1000, 3, 32
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, npt, seed=1)
     model = api.EnergyModel(n, edges, p, precision="c64")
+    tuned = autotune.tune_energy(model, npt, repeats=3)
     lib = L.load()
     stream = torch.cuda.current_stream()
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
@@ -143,12 +144,78 @@ def energy_bench(steps, warmup, cpu_seconds):
                     "networks x 32 seeded points per evaluation, one batched launch, complex64, FP64 edge sums",
         "value": rate,
         "ms_per_evaluation": 1e3 * el,
+        "tuned_waves": tuned["waves"],
         "max_abs_err_vs_oracle_sampled": err,
         "plain_c128": {"value": plain_rate, "unit": "edge-energies/s",
                        "sample": f"{len(plain)} lightcones, one launch per bucket step"},
         "speedup_vs_plain_c128": rate / plain_rate,
         "cpu_oracle": {"value": cpu_rate, "unit": "edge-energies/s", "cores": 1,
                        "sample": f"{done} lightcone contractions in {cpu_seconds:.0f} s"},
+    }
+
+
+def gradient_bench(steps, warmup, cpu_seconds):
+    """Edge-gradients/s on n=200, p=2: energy and dE/dgamma, dE/dbeta over
+    300 lightcones x 64 points per evaluation (forward + adjoint, one launch)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2012_02430_amd import api, autotune
+    from workloads import qaoa_params, regular_graph
+
+    n, p, npt = 200, 2, 64
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, npt, seed=1)
+    model = api.EnergyModel(n, edges, p, precision="c64")
+    tuned = autotune.tune_energy(model, npt, grad=True, repeats=3)
+    autotune.tune_energy(model, npt, grad=False, repeats=3)
+    gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
+    bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        model.energy_device(gd, bd, grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        model.energy_device(gd, bd, grad=True)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    # forward-only launch on the same workload, for the adjoint's cost
+    for _ in range(warmup):
+        model.energy_device(gd, bd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        model.energy_device(gd, bd)
+    torch.cuda.synchronize()
+    el_fwd = (time.perf_counter() - t0) / steps
+    E, dg, db = model.energy(gs, bs, grad=True)
+    err = 0.0
+    for i in (0, 63):
+        Eo, dgo, dbo, pe, peg = oracle.energy_grad(n, edges, gs[i], bs[i])
+        scale = np.abs(pe).sum() + np.abs(peg).sum(axis=0)
+        err = max(err, float((np.abs(np.concatenate([dg[i], db[i]]) - np.concatenate([dgo, dbo])) / scale).max()))
+    # the oracle on the host (forward-mode tangents), a sample of lightcones
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < cpu_seconds:
+        u, v = edges[done % len(edges)]
+        oracle.edge_energy_grad(n, edges, gs[0], bs[0], u, v)
+        done += 1
+    cpu_rate = done / (time.perf_counter() - t0)
+    return {
+        "metric": "edge-gradients/s",
+        "workload": "dE/dgamma, dE/dbeta of QAOA p=2 MaxCut energy, seeded random 3-regular graph n=200: 300 "
+                    "lightcone networks x 64 seeded points per evaluation, forward + adjoint in one launch, "
+                    "complex64, FP64 reductions",
+        "value": len(edges) * npt / el,
+        "ms_per_evaluation": 1e3 * el,
+        "ms_forward_only": 1e3 * el_fwd,
+        "tuned_waves": tuned["waves"],
+        "max_err_vs_oracle_sampled": err,
+        "err_scale": "sum_e |<C_e>| + |d<C_e>/dtheta|",
+        "cpu_oracle": {"value": cpu_rate, "unit": "edge-gradients/s", "cores": 1,
+                       "sample": f"{done} lightcone value+tangent contractions in {cpu_seconds:.0f} s"},
     }
 
 
@@ -171,7 +238,7 @@ def main():
     import torch
 
     import oracle
-    from paper_2012_02430_amd import api
+    from paper_2012_02430_amd import api, autotune
     from workloads import qaoa_params
 
     torch.cuda.set_device(0)
@@ -183,6 +250,10 @@ def main():
     _, _, plain, _ = build_plan("c128", slice_batch=1, plain=True)
     print(f"[bench] plan: width {sch.width} (prefix {sch.prefix_width}, slice {sch.slice_width}), "
           f"unsliced {sch.unsliced_width}, step {sch.step}, 256 slices", flush=True)
+    # measured launch shape (untimed; cached by shape signature)
+    tuning = autotune.tune_plan(plan, n_points=1, repeats=3)
+    print(f"[bench] tuned: lds_waves {tuning['lds_waves']}, lds_max_rank {tuning['lds_max_rank']} "
+          f"({'cached' if tuning['cached'] else 'measured'}: {tuning['ms']:.3f} ms)", flush=True)
 
     # accuracy against the oracle
     want = complex(oracle.sliced_values(oracle.amplitude_network(60, edges, g, b), sch.order, sch.groups).sum())
@@ -234,6 +305,13 @@ def main():
               f"1500x32 evaluation), plain c128 {energy['plain_c128']['value']:.1f}/s, "
               f"max abs err {energy['max_abs_err_vs_oracle_sampled']:.1e}", flush=True)
 
+    gradient = None
+    if not args.no_energy:
+        gradient = gradient_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5)
+        print(f"[bench] gradient: {gradient['value']:.3e} edge-gradients/s ({gradient['ms_per_evaluation']:.2f} ms "
+              f"per 300x64 evaluation, forward only {gradient['ms_forward_only']:.2f} ms), "
+              f"max rel err {gradient['max_err_vs_oracle_sampled']:.1e}", flush=True)
+
     inf = plan.info()
     line = {
         "metric": METRIC,
@@ -265,7 +343,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
+        "tuning": {"lds_waves": tuning["lds_waves"], "lds_max_rank": tuning["lds_max_rank"]},
         "energy": energy,
+        "gradient": gradient,
     }
     print(json.dumps(line), flush=True)
 

@@ -235,6 +235,33 @@ qt_status qt_profile_enable(qt_plan* plan, int32_t enable);
  * cleared afterwards. */
 qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_t reset);
 
+/* Execution tunables of a plan; 0 selects the library default (or the
+ * QT_LDS_WAVES, QT_LDS_MAX_RANK, QT_LDS_WAVES_MULTI, QT_LDS_WAVES_GRAD
+ * environment variables when set).  They choose launch shapes and which
+ * steps run from LDS rather than streaming, the role Eq. (1) of the paper
+ * gives to its thread count per pairwise product; results stay within the
+ * stated tolerances and are bitwise reproducible for fixed tunables.
+ *   lds_waves     wavefronts per workgroup of the LDS executor (1..16)
+ *   lds_max_rank  largest step output rank the LDS executor takes (6..16);
+ *                 larger steps stream from HBM
+ *   multi_waves   wavefronts per workgroup of the batched lightcone launch
+ *                 of qt_energy_grad (read from lightcones[0])
+ *   grad_waves    the same for its gradient launch */
+typedef struct {
+  int32_t lds_waves;
+  int32_t lds_max_rank;
+  int32_t multi_waves;
+  int32_t grad_waves;
+} qt_tuning;
+
+/* Sets a plan's tunables (QT_EINVAL outside the ranges above).  A change of
+ * lds_waves or lds_max_rank drops the plan's compiled schedule and device
+ * workspace, rebuilt by the next contraction; call it between contractions
+ * of the plan, never while one is in flight. */
+qt_status qt_plan_set_tuning(qt_plan* plan, const qt_tuning* tuning);
+/* The tunables as set (0: default). */
+qt_status qt_plan_get_tuning(const qt_plan* plan, qt_tuning* out);
+
 /* Host-only description of the launch schedule the plan would run with the
  * current environment: LDS-executor segments (steps, dependency levels,
  * LDS bytes, staged inputs) and streaming steps, as JSON.  Writes at most

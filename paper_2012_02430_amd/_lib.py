@@ -99,6 +99,10 @@ QT_KCLASS_NAMES = {0: "step_stream", 1: "step_small", 2: "lds", 3: "gemm", 4: "o
 QT_KCLASS_COUNT = 8
 
 # name -> (restype, argtypes); every symbol declared in include/*.h
+class qt_tuning(ctypes.Structure):
+    _fields_ = [("lds_waves", c_int32), ("lds_max_rank", c_int32), ("multi_waves", c_int32), ("grad_waves", c_int32)]
+
+
 SIGNATURES = {
     "qt_load_network": (c_int32, [POINTER(qt_network_desc), POINTER(c_void_p)]),
     "qt_load_plan": (c_int32, [c_void_p, POINTER(qt_plan_desc), POINTER(c_void_p)]),
@@ -108,6 +112,8 @@ SIGNATURES = {
     "qt_energy_grad": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qt_plan_get_info": (c_int32, [c_void_p, POINTER(qt_plan_info)]),
+    "qt_plan_set_tuning": (c_int32, [c_void_p, POINTER(qt_tuning)]),
+    "qt_plan_get_tuning": (c_int32, [c_void_p, POINTER(qt_tuning)]),
     "qt_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qt_profile_read": (c_int32, [c_void_p, POINTER(qt_kernel_stats), c_int32]),
     "qt_plan_describe": (c_int32, [c_void_p, ctypes.c_char_p, c_int64, POINTER(c_int64)]),

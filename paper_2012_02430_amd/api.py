@@ -140,6 +140,33 @@ class Plan:
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
         self.p = network.spec.p
+        self.slice_batch, self.plain, self.fold_prefix = int(slice_batch), bool(plain), bool(fold_prefix)
+
+    def signature(self) -> str:
+        """Shape signature (network structure, order, slicing, precision, flags): the autotuner's cache key."""
+        import hashlib
+        import json
+
+        spec = self.network.spec
+        blob = json.dumps({"n_vars": spec.n_vars, "p": spec.p,
+                           "tensors": [[int(t[0]), int(t[1]), [int(v) for v in t[2]]]
+                                       + ([np.asarray(t[3], dtype=np.complex128).reshape(-1).view(np.float64).tolist()]
+                                          if len(t) > 3 else [])
+                                       for t in spec.tensors],
+                           "order": self.order, "groups": [[int(g[0]), [int(v) for v in g[1]]] for g in self.groups],
+                           "precision": self.precision, "slice_batch": self.slice_batch, "plain": self.plain,
+                           "fold_prefix": self.fold_prefix}, sort_keys=True)
+        return hashlib.sha1(blob.encode()).hexdigest()
+
+    def set_tuning(self, lds_waves=0, lds_max_rank=0, multi_waves=0, grad_waves=0):
+        t = L.qt_tuning(int(lds_waves), int(lds_max_rank), int(multi_waves), int(grad_waves))
+        L.check(L.load().qt_plan_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = L.qt_tuning()
+        L.check(L.load().qt_plan_get_tuning(self.handle, ctypes.byref(t)))
+        return {"lds_waves": t.lds_waves, "lds_max_rank": t.lds_max_rank, "multi_waves": t.multi_waves,
+                "grad_waves": t.grad_waves}
 
     def __del__(self):
         if getattr(self, "handle", None) and L is not None and L._LIB is not None:
@@ -254,6 +281,17 @@ class EnergyModel:
         if grad:
             out += [dg, db]
         return out[0] if len(out) == 1 else tuple(out)
+
+    def signature(self) -> str:
+        import hashlib
+
+        return hashlib.sha1(":".join(pl.signature() for pl in self.plans).encode()).hexdigest()
+
+    def set_tuning(self, multi_waves=0, grad_waves=0):
+        """Launch shape of the batched lightcone launches (read from the first plan)."""
+        for pl in self.plans:
+            t = pl.get_tuning()
+            pl.set_tuning(t["lds_waves"], t["lds_max_rank"], multi_waves, grad_waves)
 
     def energy_device(self, gammas, betas, grad=False, per_edge=False, stream=None):
         """Device-resident call: gammas/betas are float64 torch tensors [n_points, p] on the GPU.

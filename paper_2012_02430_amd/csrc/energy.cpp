@@ -408,6 +408,7 @@ qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, in
         rv.out_off = a.off;
         rv.out_slot = a.slot;
       } else {
+        rv.out_off = (uint32_t)gate_offset(plan, tj);  // the gate's table block (read for its derivative)
         rv.out_slot = -1;
       }
       int o = 0;
@@ -502,7 +503,8 @@ qt_status check_program(const Program& pg, int p) {
     if (rv.ry > 16 || rv.nc > 20) return bad("reverse operation too large");
     if (rv.gate < 0 && (!in_range(rv.out_off, 1ull << rv.ry) || rv.out_slot < 0 || rv.out_slot >= pg.n_slots))
       return bad("adjoint output out of range");
-    if (rv.gate >= 0 && (rv.rec < 0 || rv.rec >= pg.n_recs || rv.param < 0 || rv.param >= 2 * p))
+    if (rv.gate >= 0 && (rv.rec < 0 || rv.rec >= pg.n_recs || rv.param < 0 || rv.param >= 2 * p ||
+                         rv.out_off < (uint32_t)kXGate || rv.out_off + 4 > gate_end))
       return bad("gradient record out of range");
     for (int o = 0; o < rv.n_ops; ++o) {
       const XROp& op = rv.op[o];
@@ -808,7 +810,9 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_HIP_CHECK(hipMemcpy2DAsync(job->params + p, pitch, betas, p * sizeof(double), p * sizeof(double), n_points,
                                     hipMemcpyDefault, stream));
     }
-    const int waves = std::max(1, std::min(kXMaxThreads / 64, env_int(grad ? "QT_LDS_WAVES_GRAD" : "QT_LDS_WAVES_MULTI", 4)));
+    const qt_tuning& tu = lightcones[0]->tuning;
+    const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 2)
+                                                                    : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 4)));
     if (job->n_fit) {
       XMulti m = job->multi;
       m.n_progs = n_edges;  // output row length; items cover the fitting programs only

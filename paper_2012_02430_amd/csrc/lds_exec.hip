@@ -456,29 +456,38 @@ hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStre
 namespace qt {
 namespace {
 
-// Derivative of gate-table entry y (row-major over the gate's two bits) of a
-// parametrised gate by its parameter t, in FP64: ZZ(t) has 1 on the diagonal
-// and e^{-it} off it, ZZ^dagger e^{+it}; RX(t) has cos t on the diagonal and
-// -i sin t off it, RX^dagger +i sin t.
-__device__ __forceinline__ double2 x_dgate(int kind, uint32_t y, double t) {
-  double sn, cs;
-  sincos(t, &sn, &cs);
+// Derivative of entry y (row-major over the gate's two bits) of a
+// parametrised gate by its parameter, from the gate's own table block gt:
+// ZZ(t) has 1 on the diagonal and e^{-it} off it, so its derivative is 0 and
+// -i times the entry; ZZ^dagger (e^{+it}) gives +i times the entry.  RX(t)
+// has cos t on the diagonal and -i sin t off it: the diagonal derivative
+// -sin t is the imaginary part of an off-diagonal entry, the off-diagonal
+// one -i cos t is -i times a diagonal entry (RX^dagger: signs flipped).
+template <typename E>
+__device__ __forceinline__ double2 x_dgate(int kind, uint32_t y, const E* gt) {
   const bool diag = y == 0 || y == 3;
+  const double dr = (double)gt[0].x, di = (double)gt[0].y;  // diagonal entry
+  const double or_ = (double)gt[1].x, oi = (double)gt[1].y; // off-diagonal entry
   switch (kind) {
-    case 0: return diag ? make_double2(0.0, 0.0) : make_double2(-sn, -cs);
-    case 1: return diag ? make_double2(0.0, 0.0) : make_double2(-sn, cs);
-    case 2: return diag ? make_double2(-sn, 0.0) : make_double2(0.0, -cs);
-    default: return diag ? make_double2(-sn, 0.0) : make_double2(0.0, cs);
+    case 0: return diag ? make_double2(0.0, 0.0) : make_double2(oi, -or_);
+    case 1: return diag ? make_double2(0.0, 0.0) : make_double2(-oi, or_);
+    case 2: return diag ? make_double2(oi, 0.0) : make_double2(di, -dr);
+    default: return diag ? make_double2(-oi, 0.0) : make_double2(-di, dr);
   }
 }
 
 // One wavefront runs one unit of a reverse operation: 64 outputs y of a
 // large adjoint, or all 2^ry outputs of a small one with the complement
-// split over 64 / 2^ry lane groups and summed by a fixed butterfly.
+// counter c split over G = 64 / 2^ry lane groups (lane group g takes
+// c = g + G i) and the groups summed by a fixed butterfly.  The bit maps are
+// linear over disjoint bits, so an operand's index is base + map_c(g) +
+// map_c(G i): a per-lane constant plus a wavefront-uniform term.  The
+// uniform terms of 64 iterations are computed at once, one iteration per
+// lane, and each iteration reads its own with one lane read per operand.
 template <typename E, bool SCALED, int NOPS>
 __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t lane, E* __restrict__ lds,
                                         uint32_t* __restrict__ smax, int* __restrict__ sexp,
-                                        double* __restrict__ gacc, const double* prm) {
+                                        double* __restrict__ gacc) {
   using R = typename XReal<E>::R;
   const int ry = rv.ry;
   const bool wide = ry >= 6;
@@ -492,7 +501,7 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
 #pragma unroll
   for (int o = 0; o < NOPS; ++o) {
     const XROp& op = rv.op[o];
-    base[o] = op.lds_off + xpext_all(y, op.y_lo, op.y_len, op.y_dst);
+    base[o] = op.lds_off + xpext_all(y, op.y_lo, op.y_len, op.y_dst) + xpext_all(g, op.c_lo, op.c_len, op.c_dst);
     sc[o] = (R)1;
     if (SCALED && op.slot >= 0) {
       const int sh = xshift(smax[op.slot]);
@@ -503,18 +512,25 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
   E acc;
   acc.x = 0;
   acc.y = 0;
-  for (uint32_t c = g; c < C; c += G) {
-    const XROp& op0 = rv.op[0];
-    E t = lds[base[0] + xpext_all(c, op0.c_lo, op0.c_len, op0.c_dst)];
-    if (SCALED) t = xscale(t, sc[0]);
+  const bool live = g < C;  // lane groups beyond a short complement add nothing
+  const uint32_t n_it = C > G ? C / G : 1u;
+  for (uint32_t ib = 0; ib < n_it; ib += 64) {
+    uint32_t cm[NOPS];
+    const uint32_t ci = (ib + lane) * G;
 #pragma unroll
-    for (int o = 1; o < NOPS; ++o) {
-      const XROp& op = rv.op[o];
-      E x = lds[base[o] + xpext_all(c, op.c_lo, op.c_len, op.c_dst)];
-      if (SCALED) x = xscale(x, sc[o]);
-      t = xmul(t, x);
+    for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(ci, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
+    const uint32_t nb = n_it - ib < 64u ? n_it - ib : 64u;
+    for (uint32_t t = 0; t < nb; ++t) {
+      E v = lds[base[0] + (uint32_t)__builtin_amdgcn_readlane((int)cm[0], (int)t)];
+      if (SCALED) v = xscale(v, sc[0]);
+#pragma unroll
+      for (int o = 1; o < NOPS; ++o) {
+        E x = lds[base[o] + (uint32_t)__builtin_amdgcn_readlane((int)cm[o], (int)t)];
+        if (SCALED) x = xscale(x, sc[o]);
+        v = xmul(v, x);
+      }
+      if (live) acc = xadd(acc, v);
     }
-    acc = xadd(acc, t);
   }
   if (!wide) {
     for (uint32_t off = 1u << ry; off < 64u; off <<= 1) {
@@ -525,7 +541,7 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
   if (rv.gate >= 0) {
     double v = 0.0;
     if (g == 0) {
-      const double2 d = x_dgate(rv.gate, y, prm[rv.param]);
+      const double2 d = x_dgate(rv.gate, y, lds + rv.out_off);
       v = (double)acc.x * d.x - (double)acc.y * d.y;
     }
     for (uint32_t off = 1; off < (1u << ry); off <<= 1) v += __shfl_xor(v, (int)off);
@@ -619,9 +635,9 @@ __device__ __forceinline__ void x_grad_unit(const uint2 un, const XStep* __restr
     }
   } else if (kind == kXUnitRev) {
     const XRev& rv = prevs[idx];
-    if (rv.n_ops <= 2) x_runit<E, SCALED, 2>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
-    else if (rv.n_ops <= 4) x_runit<E, SCALED, 4>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
-    else x_runit<E, SCALED, 8>(rv, un.y, c.lane, lds, smax, sexp, gacc, prm);
+    if (rv.n_ops <= 2) x_runit<E, SCALED, 2>(rv, un.y, c.lane, lds, smax, sexp, gacc);
+    else if (rv.n_ops <= 4) x_runit<E, SCALED, 4>(rv, un.y, c.lane, lds, smax, sexp, gacc);
+    else x_runit<E, SCALED, 8>(rv, un.y, c.lane, lds, smax, sexp, gacc);
   } else if (c.lane == 0) {
     x_final_adjoints<E, SCALED>(P, pfin, lds, smax, sexp, lds);
   }
@@ -666,7 +682,7 @@ __device__ __forceinline__ void x_grad_epilogue(const XMulti& M, const XProg& P,
 // its derivatives by the 2p parameters, each the FP64 sum of the parameter's
 // gradient records in record order.
 template <typename E, bool SCALED>
-__global__ __launch_bounds__(kXMaxThreads) void k_lds_grad(const XMulti M, const XProg* __restrict__ progs,
+__global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_lds_grad(const XMulti M, const XProg* __restrict__ progs,
                                                            const XStep* __restrict__ steps,
                                                            const XRev* __restrict__ revs,
                                                            const uint2* __restrict__ units,

@@ -332,6 +332,8 @@ struct SymTensor {
 };
 
 int env_int(const char* name, int dflt);
+// A tunable: the plan's value when set, else the environment, else dflt.
+int tuned(int32_t value, const char* env, int dflt);
 void energy_forget(uint64_t serial);  // drops cached energy jobs that use the plan
 // Full contraction of a plan at np points through the general schedule;
 // *sums receives the device address of its [np][3] (re, im, log2) results.
@@ -370,6 +372,7 @@ struct qt_plan {
   int32_t n_exp0 = 0, n_exp1 = 0;   // exponent slots per point / per (point x item)
   int64_t slice_batch_req = 0;
   int32_t flags = 0;
+  qt_tuning tuning{};   // execution tunables, 0 = default
   uint64_t serial = 0;  // unique per plan, never reused (cache keys)
   qt_plan_info info{};
   // HIP-event profiling of launches (qt_profile_enable / qt_profile_read)

@@ -42,6 +42,8 @@ int env_int(const char* name, int dflt) {
   return e ? std::atoi(e) : dflt;
 }
 
+int tuned(int32_t value, const char* env, int dflt) { return value > 0 ? value : env_int(env, dflt); }
+
 bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns) {
   int n = 0, d = 0;
   for (int b = 0; b < 32;) {
@@ -279,8 +281,8 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   ws.slice_ops.clear();
   ws.segs.clear();
   const bool plain = (plan.flags & QT_PLAN_PLAIN) != 0;
-  const int max_rank = std::min(16, env_int("QT_LDS_MAX_RANK", 14));
-  ws.waves = std::max(1, std::min(kXMaxThreads / 64, env_int("QT_LDS_WAVES", 16)));
+  const int max_rank = std::min(16, tuned(plan.tuning.lds_max_rank, "QT_LDS_MAX_RANK", 14));
+  ws.waves = std::max(1, std::min(kXMaxThreads / 64, tuned(plan.tuning.lds_waves, "QT_LDS_WAVES", 16)));
   const int64_t lds_bytes = std::min(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
   const int nsteps = (int)plan.steps.size();
   const int ntens = (int)plan.tensors.size();
@@ -914,6 +916,25 @@ extern "C" void qt_free_plan(qt_plan* plan) {
   if (!plan) return;
   energy_forget(plan->serial);
   delete plan;
+}
+
+extern "C" qt_status qt_plan_set_tuning(qt_plan* plan, const qt_tuning* t) {
+  if (!plan || !t) return fail(QT_EINVAL, "qt_plan_set_tuning: null argument");
+  auto waves_ok = [](int32_t w) { return w == 0 || (w >= 1 && w <= kXMaxThreads / 64); };
+  if (!waves_ok(t->lds_waves) || !waves_ok(t->multi_waves) || !waves_ok(t->grad_waves))
+    return fail(QT_EINVAL, "qt_plan_set_tuning: wavefronts per workgroup must be 0 or 1..16");
+  if (t->lds_max_rank != 0 && (t->lds_max_rank < 6 || t->lds_max_rank > 16))
+    return fail(QT_EINVAL, "qt_plan_set_tuning: lds_max_rank must be 0 or 6..16");
+  const bool reschedule = t->lds_waves != plan->tuning.lds_waves || t->lds_max_rank != plan->tuning.lds_max_rank;
+  plan->tuning = *t;
+  if (reschedule) plan->ws.reset();
+  return QT_OK;
+}
+
+extern "C" qt_status qt_plan_get_tuning(const qt_plan* plan, qt_tuning* out) {
+  if (!plan || !out) return fail(QT_EINVAL, "qt_plan_get_tuning: null argument");
+  *out = plan->tuning;
+  return QT_OK;
 }
 
 extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t cap, int64_t* needed) {

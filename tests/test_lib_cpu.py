@@ -157,3 +157,39 @@ def test_energy_network_matches_lightcone_convention():
         spec = N.energy_network(n, edges, p, u, v)
         T = oracle.energy_network(n, edges, np.zeros(p), np.zeros(p), u, v)
         assert sorted(tuple(sorted(t[2])) for t in spec.tensors) == sorted(tuple(sorted(t[1])) for t in T)
+
+
+def test_plan_tuning_roundtrip_and_validation(lib):
+    from paper_2012_02430_amd import api
+
+    edges = regular_graph(16, 3, 0)
+    net = api.Network(N.amplitude_network(16, edges, 2))
+    plan = api.Plan(net, net.order_greedy("min_fill")[0], precision="c64")
+    assert plan.get_tuning() == {"lds_waves": 0, "lds_max_rank": 0, "multi_waves": 0, "grad_waves": 0}
+    plan.set_tuning(8, 12, 2, 4)
+    assert plan.get_tuning() == {"lds_waves": 8, "lds_max_rank": 12, "multi_waves": 2, "grad_waves": 4}
+    for bad in ((17, 0, 0, 0), (0, 5, 0, 0), (0, 17, 0, 0), (0, 0, -1, 0), (0, 0, 0, 99)):
+        with pytest.raises(L.QTError) as ex:
+            plan.set_tuning(*bad)
+        assert ex.value.status == L.QT_EINVAL
+    assert plan.get_tuning()["lds_max_rank"] == 12  # a rejected call changes nothing
+    # the schedule follows the rank threshold (host-only description): at
+    # width 9, a threshold of 6 streams the larger steps, 16 keeps all in LDS
+    assert plan.info().width >= 8
+    plan.set_tuning(0, 6)
+    d6 = plan.describe()
+    plan.set_tuning(0, 16)
+    d16 = plan.describe()
+    assert len(d6["stream_steps"]) > 0 and len(d16["stream_steps"]) == 0
+
+
+def test_plan_signature_is_a_shape_key(lib):
+    from paper_2012_02430_amd import api
+
+    edges = regular_graph(8, 3, 0)
+    net = api.Network(N.amplitude_network(8, edges, 1))
+    order = net.order_greedy("min_fill")[0]
+    a = api.Plan(net, order, precision="c64")
+    b = api.Plan(net, order, precision="c64")
+    c = api.Plan(net, order, precision="c128")
+    assert a.signature() == b.signature() != c.signature()

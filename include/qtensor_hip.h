@@ -55,9 +55,19 @@ typedef enum {
  *   QT_C64_SCALED   complex64 mantissas with a per-tensor power-of-two
  *                   exponent (renormalised after every step from the
  *                   measured max|x|), FP64 slice sum.
- *   QT_C64_SCALED_MFMA_FP32, QT_C64_SCALED_MFMA_BF16X3
- *                   as QT_C64_SCALED, with buckets that are dense
- *                   contractions run as complex GEMM on the matrix cores. */
+ *   QT_C64_SCALED_MFMA_FP32
+ *                   as QT_C64_SCALED, and a bucket whose two largest
+ *                   tensors share variables held by no other tensor (but
+ *                   vectors) sums the bucket variable and those variables
+ *                   in one step, a batched complex GEMM
+ *                   C[b,m,n] = sum_k A[b,m,k] B[b,n,k] on the matrix cores
+ *                   (FP32 inputs and accumulation), when the unfused output
+ *                   would have rank >= 12 (QT_GEMM_MIN_RANK), K >= 8 and
+ *                   M, N >= 16.  Same values as eliminating the variables
+ *                   one by one, with a smaller intermediate.
+ *   QT_C64_SCALED_MFMA_BF16X3
+ *                   reserved (split-BF16 products); qt_load_plan returns
+ *                   QT_EUNSUPPORTED. */
 typedef enum {
   QT_C128 = 0,
   QT_C64_SCALED = 1,

@@ -113,8 +113,15 @@ int count_intermediates(const qt_plan& plan) {
 }
 
 // Forward-only program: every intermediate in LDS over its level interval.
+bool has_gemm(const qt_plan& plan) {
+  for (const SymStep& st : plan.steps)
+    if (st.gemm) return true;
+  return false;
+}
+
 qt_status build_program(const qt_plan& plan, int elt, int64_t cap_elems, Program& pg) {
   if (!plan.slice_vars.empty()) return fail(QT_EINVAL, "qt_energy_grad: lightcone plans take no slicing");
+  if (has_gemm(plan)) return fail(QT_EUNSUPPORTED, "qt_energy_grad: lightcone plans with GEMM buckets are not supported");
   const int nsteps = (int)plan.steps.size();
   const int ntens = (int)plan.tensors.size();
   std::vector<int> depth(nsteps, 0);
@@ -301,6 +308,7 @@ int count_records(const qt_plan& plan) {
 
 qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, int prog_id, Program& pg) {
   if (!plan.slice_vars.empty()) return fail(QT_EINVAL, "qt_energy_grad: lightcone plans take no slicing");
+  if (has_gemm(plan)) return fail(QT_EUNSUPPORTED, "qt_energy_grad: lightcone plans with GEMM buckets are not supported");
   const auto& T = plan.tensors;
   const auto& S = plan.steps;
   const int ns = (int)S.size(), nt = (int)T.size(), p = plan.net.p;

@@ -159,8 +159,8 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     *out = nullptr;
     if (d->precision < QT_C128 || d->precision > QT_C64_SCALED_MFMA_BF16X3)
       return fail(QT_EINVAL, "qt_load_plan: unknown precision");
-    if (d->precision >= QT_C64_SCALED_MFMA_FP32)
-      return fail(QT_EUNSUPPORTED, "qt_load_plan: MFMA precisions are not built yet");
+    if (d->precision == QT_C64_SCALED_MFMA_BF16X3)
+      return fail(QT_EUNSUPPORTED, "qt_load_plan: the split-BF16 MFMA precision is not built; use QT_C64_SCALED_MFMA_FP32");
     if (d->n_order < 0 || (d->n_order > 0 && !d->order)) return fail(QT_EINVAL, "qt_load_plan: bad order");
     if (d->n_groups < 0 || (d->n_groups > 0 && (!d->group_step || !d->group_len)))
       return fail(QT_EINVAL, "qt_load_plan: bad groups");
@@ -319,6 +319,141 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       return QT_OK;
     };
 
+    // Fused GEMM bucket (MFMA precisions).  When the two largest tensors A
+    // and B of the bucket of v share variables that no other live tensor
+    // holds (apart from vectors on them), summing v and those variables at
+    // once is one contraction C[b, m, n] = sum_k A[b, m, k] B[b, n, k]
+    // (b: shared kept variables, m / n: variables of A / B only); the
+    // summed variables' buckets are then empty.  The bucket's other tensors
+    // and the vectors on summed variables are first multiplied into A or B
+    // (product steps), so the result is that of eliminating the same
+    // variables one by one, with a smaller intermediate.
+    const bool mfma = d->precision == QT_C64_SCALED_MFMA_FP32;
+    const int gemm_min_rank = env_int("QT_GEMM_MIN_RANK", 12);
+    auto subset = [](const std::vector<int>& a, const std::vector<int>& b) {
+      for (int x : a)
+        if (std::find(b.begin(), b.end(), x) == b.end()) return false;
+      return true;
+    };
+    auto contains = [](const std::vector<int>& a, int x) { return std::find(a.begin(), a.end(), x) != a.end(); };
+    // Multiplies the tensors of grp into one (product steps in this bucket).
+    auto fold = [&](std::vector<int> grp, int i, int v, bool post, int& res) -> qt_status {
+      while (grp.size() > 1) {
+        std::vector<int> g(grp.begin(), grp.begin() + std::min<size_t>(kMaxIn, grp.size()));
+        grp.erase(grp.begin(), grp.begin() + g.size());
+        qt_status st = emit(g, false, v, post);
+        if (st != QT_OK) return st;
+        if (buckets[i].empty()) return fail(QT_EPLAN, "qt_load_plan: internal: product left its bucket");
+        grp.insert(grp.begin(), buckets[i].back());
+        buckets[i].pop_back();
+      }
+      res = grp[0];
+      return QT_OK;
+    };
+    auto try_fuse = [&](int i, int v, const std::vector<int>& ins, bool post, bool& fused) -> qt_status {
+      fused = false;
+      if (!mfma || ins.size() < 2) return QT_OK;
+      std::vector<int> srt = ins;
+      std::stable_sort(srt.begin(), srt.end(),
+                       [&](int a, int b) { return eff(a, post).size() > eff(b, post).size(); });
+      const int A = srt[0], B = srt[1];
+      const std::vector<int> SA = eff(A, post), SB = eff(B, post);
+      if (SA.size() < 4 || SB.size() < 4) return QT_OK;
+      std::vector<int> U;
+      for (int t : ins)
+        for (int x : eff(t, post))
+          if (!contains(U, x)) U.push_back(x);
+      if ((int)U.size() - 1 < gemm_min_rank) return QT_OK;
+      std::vector<int> toA = {A}, toB = {B};
+      for (int t : ins) {
+        if (t == A || t == B) continue;
+        const auto e = eff(t, post);
+        if (subset(e, SA)) toA.push_back(t);
+        else if (subset(e, SB)) toB.push_back(t);
+        else return QT_OK;
+      }
+      std::vector<int> K = {v};
+      std::vector<std::pair<int, int>> vecs;  // (bucket, tensor) of vectors on summed variables
+      for (int u : SA) {
+        if (u == v || !contains(SB, u) || key[u] >= n_order) continue;
+        bool excl = true;
+        std::vector<std::pair<int, int>> uv;
+        for (int j = i + 1; j < n_order && excl; ++j)
+          for (int t : buckets[j]) {
+            const auto e = eff(t, post);
+            if (!contains(e, u)) continue;
+            if (e.size() == 1) uv.emplace_back(j, t);
+            else {
+              excl = false;
+              break;
+            }
+          }
+        if (!excl) continue;
+        K.push_back(u);
+        vecs.insert(vecs.end(), uv.begin(), uv.end());
+      }
+      int nm = 0, nn = 0, nb = 0;
+      for (int x : SA) nm += !contains(SB, x);
+      for (int x : SB) nn += !contains(SA, x);
+      for (int x : SA) nb += contains(SB, x) && !contains(K, x);
+      if (K.size() < 3 || nm < 4 || nn < 4 || nb + nm + nn > kMaxRank) return QT_OK;
+      for (const auto& jt : vecs) {
+        auto& bk = buckets[jt.first];
+        bk.erase(std::find(bk.begin(), bk.end(), jt.second));
+        toA.push_back(jt.second);
+      }
+      int Ap = -1, Bp = -1;
+      qt_status st = fold(toA, i, v, post, Ap);
+      if (st != QT_OK) return st;
+      st = fold(toB, i, v, post, Bp);
+      if (st != QT_OK) return st;
+      std::sort(K.begin(), K.end(), by_key);
+      std::vector<int> outv;
+      for (int x : eff(Ap, post))
+        if (!contains(K, x)) outv.push_back(x);
+      for (int x : eff(Bp, post))
+        if (!contains(K, x) && !contains(outv, x)) outv.push_back(x);
+      std::sort(outv.begin(), outv.end(), by_key);
+      SymTensor o;
+      o.vars = outv;
+      o.level = post ? 1 : 0;
+      o.rank = (int)outv.size();
+      o.producer = (int)steps.size();
+      const int ot = (int)T.size();
+      T.push_back(o);
+      SymStep gs;
+      gs.out = ot;
+      gs.level = o.level;
+      gs.rank = o.rank;
+      gs.sum = 1;
+      gs.var = v;
+      gs.nbr = o.rank;
+      gs.gemm = 1;
+      gs.kvars = K;
+      double in_elems = 0;
+      for (int t : {Ap, Bp}) {
+        const auto e = eff(t, post);
+        SymIn si{};
+        si.tensor = t;
+        for (size_t q = 0; q < outv.size(); ++q)
+          if (contains(e, outv[q])) si.mask |= 1u << q;
+        if (post && T[t].level == 0) {
+          for (int x : T[t].vars)
+            if (slice_index[x] >= 0) si.smask |= 1u << (k - 1 - slice_index[x]);
+          si.slow = (int)e.size();
+        }
+        in_elems += std::ldexp(1.0, (int)e.size());
+        T[t].consumer = (int)steps.size();
+        gs.ins.push_back(si);
+      }
+      gs.bytes_c64 = 8.0 * (in_elems + std::ldexp(1.0, o.rank));
+      gs.flops = 8.0 * std::ldexp(1.0, nb + nm + nn + (int)K.size());
+      steps.push_back(std::move(gs));
+      place(ot);
+      fused = true;
+      return QT_OK;
+    };
+
     // With QT_PLAN_FOLD_PREFIX every step runs per slice (slice variables
     // fixed from the start).
     const int s_exec = (k > 0 && (d->flags & QT_PLAN_FOLD_PREFIX)) ? 0 : s;
@@ -326,7 +461,15 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       const bool post = k > 0 && i >= s_exec;
       const int v = plan->order[i];
       std::vector<int> ins = std::move(buckets[i]);
+      buckets[i].clear();
       if (ins.empty()) continue;
+      bool fused = false;
+      qt_status fs = try_fuse(i, v, ins, post, fused);
+      if (fs != QT_OK) return fs;
+      if (fused) {
+        if (!post) plan->n_prefix_steps = (int)steps.size();
+        continue;
+      }
       while ((int)ins.size() > kMaxIn) {
         std::stable_sort(ins.begin(), ins.end(),
                          [&](int a, int b) { return eff(a, post).size() < eff(b, post).size(); });

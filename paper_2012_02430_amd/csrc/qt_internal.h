@@ -280,6 +280,37 @@ struct XMulti {
   int32_t n_recs;          // max over programs
 };
 
+// Fused GEMM bucket: C[b, m, n] = sum_k A[b, m, k] B[b, n, k] over complex
+// values, for every batch item (point, slice).  The counters b, m, n, k run
+// over their variables in key order; a tensor's element index is the sum of
+// its bit maps of the counters it has (runs: source bit, length, destination
+// bit), plus the slice-selected block of a prefix tensor.
+constexpr int kGRuns = 12;
+struct GMap {
+  uint8_t lo[kGRuns];
+  uint8_t len[kGRuns];
+  uint8_t dst[kGRuns];
+  uint8_t n;
+  uint8_t pad[3];
+};
+struct DevGemm {
+  const void* a;
+  const void* b;
+  void* c;
+  int64_t a_pt, a_sb, b_pt, b_sb, c_pt, c_sb;  // element strides per point and per slice item
+  uint32_t a_smask, b_smask;
+  int32_t a_slow, b_slow;
+  int64_t chunk_base;
+  int32_t lg_nsb;
+  int32_t n_items;
+  int32_t nb, nm, nn, nk;  // counter bits
+  int32_t a_exp_base, a_exp_pt, a_exp_sb;  // -1 base: unscaled (a leaf)
+  int32_t b_exp_base, b_exp_pt, b_exp_sb;
+  int32_t c_exp_base, c_exp_pt, c_exp_sb;
+  int32_t pad;
+  GMap a_b, a_m, a_k, b_b, b_n, b_k, c_b, c_m, c_n;
+};
+
 // Leaf (gate) tensor materialisation record.
 struct DevLeaf {
   int32_t kind;
@@ -316,6 +347,8 @@ struct SymStep {
   int32_t sum;
   int32_t var;          // eliminated variable (internal id), -1 for product steps
   int32_t nbr;          // neighbour count of the eliminated variable (its width)
+  int32_t gemm = 0;     // fused GEMM bucket: ins = {A, B}, summed over kvars
+  std::vector<int32_t> kvars;  // GEMM: summed variables, by key (the bucket variable first)
   std::vector<SymIn> ins;
   double bytes_c64;     // algorithmic bytes per item at 8 B per element
   double flops;         // real flops per item
@@ -395,6 +428,8 @@ hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, co
 hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits,
                        int64_t n_elems, hipStream_t stream, int* n_launches, int* kclass);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t stream);
+// gemm.hip: one fused GEMM bucket for all batch items (complex64, MFMA).
+hipError_t launch_gemm(const DevGemm& g, bool scaled, int* exps, uint32_t* maxbits, hipStream_t stream);
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items,
                         bool c128, bool scaled, const int* exps, const uint32_t* maxbits,
                         double* per_slice, int64_t slice_end, hipStream_t stream);

@@ -85,6 +85,7 @@ struct qt_plan::Workspace {
   int64_t bytes = 0;
   int64_t n_exp = 0, exp1_base = 0, exp1_count = 0;
   std::vector<DevStep> steps;
+  std::vector<DevGemm> gemms;  // per step (used by GEMM steps only)
   std::vector<int64_t> step_elems;
   std::vector<DevIn> finals;
   // Launch sequence: a streaming step (seg < 0, index `step`) or an LDS
@@ -398,7 +399,7 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   };
   for (int i = 0; i < nsteps; ++i) {
     const SymStep& st = plan.steps[i];
-    if (plain || st.rank > max_rank) {
+    if (plain || st.rank > max_rank || st.gemm) {
       flush();
       (st.level == 0 ? ws.prefix_ops : ws.slice_ops).push_back({i, -1});
       continue;
@@ -604,6 +605,105 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   return QT_OK;
 }
 
+// Bit map from a counter over `counter` (variables in key order) to the
+// storage bits of a tensor with variables `vars` (key order).
+bool make_gmap(const std::vector<int32_t>& counter, const std::vector<int32_t>& vars, GMap& g) {
+  std::memset(&g, 0, sizeof(g));
+  int n = 0;
+  for (size_t j = 0; j < counter.size();) {
+    const int pos = (int)(std::find(vars.begin(), vars.end(), counter[j]) - vars.begin());
+    if (pos >= (int)vars.size()) return false;
+    size_t e = j + 1;
+    while (e < counter.size() && e - j < 32) {
+      const int pe = (int)(std::find(vars.begin(), vars.end(), counter[e]) - vars.begin());
+      if (pe != pos + (int)(e - j)) break;
+      ++e;
+    }
+    if (n == kGRuns) return false;
+    g.lo[n] = (uint8_t)j;
+    g.len[n] = (uint8_t)(e - j);
+    g.dst[n] = (uint8_t)pos;
+    ++n;
+    j = e;
+  }
+  g.n = (uint8_t)n;
+  return true;
+}
+
+qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const SymStep& st, int elt, int np,
+                     int64_t chunk, DevGemm& g) {
+  std::memset(&g, 0, sizeof(g));
+  const int ta = st.ins[0].tensor, tb = st.ins[1].tensor;
+  const auto& va = plan.tensors[ta].vars;
+  const auto& vb = plan.tensors[tb].vars;
+  const auto& vc = plan.tensors[st.out].vars;
+  auto has = [](const std::vector<int32_t>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
+  std::vector<int32_t> cb, cm, cn;
+  for (int x : vc) {
+    const bool ia = has(va, x), ib = has(vb, x);
+    if (ia && ib) cb.push_back(x);
+    else if (ia) cm.push_back(x);
+    else cn.push_back(x);
+  }
+  DevIn da, db, dc;
+  build_in(plan, ws, ta, 0, 0, st.ins[0].smask, st.ins[0].slow, elt, da);
+  build_in(plan, ws, tb, 0, 0, st.ins[1].smask, st.ins[1].slow, elt, db);
+  build_in(plan, ws, st.out, 0, 0, 0, 0, elt, dc);
+  g.a = da.ptr;
+  g.b = db.ptr;
+  g.c = const_cast<void*>(dc.ptr);
+  g.a_pt = da.pt_stride;
+  g.a_sb = da.sb_stride;
+  g.b_pt = db.pt_stride;
+  g.b_sb = db.sb_stride;
+  g.c_pt = dc.pt_stride;
+  g.c_sb = dc.sb_stride;
+  g.a_smask = st.ins[0].smask;
+  g.b_smask = st.ins[1].smask;
+  g.a_slow = st.ins[0].slow;
+  g.b_slow = st.ins[1].slow;
+  g.lg_nsb = st.level == 1 ? ilog2(chunk) : 0;
+  g.n_items = (int32_t)(np * (st.level == 1 ? chunk : 1));
+  g.nb = (int)cb.size();
+  g.nm = (int)cm.size();
+  g.nn = (int)cn.size();
+  g.nk = (int)st.kvars.size();
+  g.a_exp_base = da.exp_base;
+  g.a_exp_pt = da.exp_pt;
+  g.a_exp_sb = da.exp_sb;
+  g.b_exp_base = db.exp_base;
+  g.b_exp_pt = db.exp_pt;
+  g.b_exp_sb = db.exp_sb;
+  g.c_exp_base = dc.exp_base;
+  g.c_exp_pt = dc.exp_pt;
+  g.c_exp_sb = dc.exp_sb;
+  if (!make_gmap(cb, va, g.a_b) || !make_gmap(cm, va, g.a_m) || !make_gmap(st.kvars, va, g.a_k) ||
+      !make_gmap(cb, vb, g.b_b) || !make_gmap(cn, vb, g.b_n) || !make_gmap(st.kvars, vb, g.b_k) ||
+      !make_gmap(cb, vc, g.c_b) || !make_gmap(cm, vc, g.c_m) || !make_gmap(cn, vc, g.c_n))
+    return fail(QT_EUNSUPPORTED, "GEMM operand index map has too many runs of bits");
+  // each operand's maps cover distinct bits inside its rank (below its
+  // slice bits), so every index stays in the tensor's block
+  auto covers = [](std::initializer_list<const GMap*> maps, int bits, int rank) {
+    uint64_t seen = 0;
+    int total = 0;
+    for (const GMap* m : maps)
+      for (int i = 0; i < m->n; ++i) {
+        if (m->dst[i] + m->len[i] > rank) return false;
+        const uint64_t run = ((1ull << m->len[i]) - 1ull) << m->dst[i];
+        if (seen & run) return false;
+        seen |= run;
+        total += m->len[i];
+      }
+    return total == bits;
+  };
+  const int ra = st.ins[0].smask ? st.ins[0].slow : (int)va.size();
+  const int rb = st.ins[1].smask ? st.ins[1].slow : (int)vb.size();
+  if (!covers({&g.a_b, &g.a_m, &g.a_k}, g.nb + g.nm + g.nk, ra) || !covers({&g.b_b, &g.b_n, &g.b_k}, g.nb + g.nn + g.nk, rb) ||
+      !covers({&g.c_b, &g.c_m, &g.c_n}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3)
+    return fail(QT_EPLAN, "internal: GEMM operand maps do not tile their tensors");
+  return QT_OK;
+}
+
 qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
   const bool c128 = plan.precision == QT_C128;
   const int elt = c128 ? 16 : 8;
@@ -649,6 +749,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
                            hipMemcpyHostToDevice));
     // streaming step descriptors
     ws.steps.clear();
+    ws.gemms.assign(plan.steps.size(), DevGemm{});
     ws.step_elems.clear();
     for (const SymStep& st : plan.steps) {
       DevStep d;
@@ -657,6 +758,11 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
       ws.step_elems.push_back((int64_t)np * (st.level == 1 ? chunk : 1) << ot.rank);
       if (ws.seg_of[&st - plan.steps.data()] >= 0) {
         ws.steps.push_back(d);  // runs inside an LDS segment
+        continue;
+      }
+      if (st.gemm) {
+        ws.steps.push_back(d);
+        QT_TRY(build_gemm(plan, ws, st, elt, np, chunk, ws.gemms[&st - plan.steps.data()]));
         continue;
       }
       DevIn od;
@@ -757,6 +863,14 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
     });
   };
   auto run_op = [&](const qt_plan::Workspace::Op& op, int64_t cb) -> hipError_t {
+    if (op.seg < 0 && plan.steps[op.step].gemm) {
+      DevGemm g = ws.gemms[op.step];
+      g.chunk_base = cb;
+      const SymStep& st = plan.steps[op.step];
+      ++launches;
+      return timed(plan, stream, QT_KCLASS_GEMM, st.bytes_c64 * g.n_items, st.flops * g.n_items,
+                   [&] { return launch_gemm(g, scaled, ws.exps, ws.maxbits, stream); });
+    }
     if (op.seg < 0) {
       DevStep d = ws.steps[op.step];
       d.chunk_base = cb;
@@ -965,9 +1079,13 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
     for (auto* ops : {&ws.prefix_ops, &ws.slice_ops})
       for (const auto& op : *ops)
         if (op.seg < 0) {
+          const SymStep& st = plan->steps[op.step];
           j += std::string(first ? "" : ",") + "{\"step\":" + std::to_string(op.step) + ",\"rank\":" +
-               std::to_string(plan->steps[op.step].rank) + ",\"inputs\":" +
-               std::to_string(plan->steps[op.step].ins.size()) + "}";
+               std::to_string(st.rank) + ",\"inputs\":" + std::to_string(st.ins.size()) +
+               (st.gemm ? ",\"gemm\":{\"k_bits\":" + std::to_string(st.kvars.size()) + ",\"flops\":" +
+                              std::to_string(st.flops) + "}"
+                        : std::string()) +
+               "}";
           first = false;
         }
     j += "],\"arena0_units\":" + std::to_string(ws.arena0_units) + ",\"arena1_units\":" +

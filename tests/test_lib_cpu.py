@@ -193,3 +193,39 @@ def test_plan_signature_is_a_shape_key(lib):
     b = api.Plan(net, order, precision="c64")
     c = api.Plan(net, order, precision="c128")
     assert a.signature() == b.signature() != c.signature()
+
+
+def test_gemm_fusion_only_for_mfma_precision_and_above_threshold(monkeypatch):
+    from paper_2012_02430_amd import api
+
+    n, p = 30, 2
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    order, _ = net.order_greedy("min_fill")
+
+    def n_gemm(prec):
+        return sum("gemm" in s for s in api.Plan(net, order, precision=prec).describe()["stream_steps"])
+
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "8")
+    assert n_gemm("c64_mfma_fp32") == 1
+    assert n_gemm("c64") == 0 and n_gemm("c128") == 0
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "40")
+    assert n_gemm("c64_mfma_fp32") == 0
+    with pytest.raises(L.QTError) as ex:
+        api.Plan(net, order, precision="c64_mfma_bf16x3")
+    assert ex.value.status == L.QT_EUNSUPPORTED
+
+
+def test_gemm_fusion_shrinks_the_n210_plan():
+    # the n=210, p=1 min-degree plan with 8 slice variables: two buckets are
+    # fused and the largest per-slice intermediate shrinks from 2^29 to 2^25
+    from paper_2012_02430_amd import api
+
+    edges = regular_graph(210, 3, 0)
+    net = api.Network(N.amplitude_network(210, edges, 1))
+    sch = net.plan_slicing(8, algo="min_degree")
+    fused = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32")
+    plain = api.Plan(net, sch.order, sch.groups, precision="c64")
+    g = [s for s in fused.describe()["stream_steps"] if "gemm" in s]
+    assert len(g) >= 1
+    assert fused.info().width < plain.info().width

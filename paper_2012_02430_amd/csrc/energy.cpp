@@ -20,11 +20,6 @@
 namespace qt {
 namespace {
 
-#define QT_TRY(expr)            \
-  do {                          \
-    qt_status _s = (expr);      \
-    if (_s != QT_OK) return _s; \
-  } while (0)
 
 
 struct Program {
@@ -742,20 +737,9 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   return QT_OK;
 }
 
-bool is_device_ptr(const void* p) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
-
 qt_status copy_out(double* dst, const double* src, size_t n, hipStream_t stream) {
   if (!dst) return QT_OK;
-  QT_HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double),
-                              is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
-  return QT_OK;
+  return copy_2d(dst, n * sizeof(double), src, n * sizeof(double), n * sizeof(double), 1, stream);
 }
 
 }  // namespace
@@ -813,10 +797,8 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
     const bool c128 = job->precision == QT_C128;
     if (p > 0) {
       const size_t pitch = 2 * p * sizeof(double);
-      QT_HIP_CHECK(hipMemcpy2DAsync(job->params, pitch, gammas, p * sizeof(double), p * sizeof(double), n_points,
-                                    hipMemcpyDefault, stream));
-      QT_HIP_CHECK(hipMemcpy2DAsync(job->params + p, pitch, betas, p * sizeof(double), p * sizeof(double), n_points,
-                                    hipMemcpyDefault, stream));
+      (void)pitch;
+      QT_TRY(upload_params_to(job->params, n_points, p, gammas, betas, stream));
     }
     const qt_tuning& tu = lightcones[0]->tuning;
     const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 2)
@@ -848,20 +830,12 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_HIP_CHECK(launch_amp_to_real(job->out, (int64_t)n_points * n_edges, job->reals + n_points, stream));
       QT_TRY(copy_out(per_edge, job->reals + n_points, (size_t)n_points * n_edges, stream));
     }
-    bool host_out = !is_device_ptr(energy) || (per_edge && !is_device_ptr(per_edge));
     if (grad && p > 0) {
       QT_HIP_CHECK(launch_rows_sum(job->gout, n_points, n_edges, 2 * p, job->gsum, stream));
       const size_t row = p * sizeof(double), pitch = 2 * p * sizeof(double);
-      if (dE_dgamma) {
-        QT_HIP_CHECK(hipMemcpy2DAsync(dE_dgamma, row, job->gsum, pitch, row, n_points, hipMemcpyDefault, stream));
-        host_out = host_out || !is_device_ptr(dE_dgamma);
-      }
-      if (dE_dbeta) {
-        QT_HIP_CHECK(hipMemcpy2DAsync(dE_dbeta, row, job->gsum + p, pitch, row, n_points, hipMemcpyDefault, stream));
-        host_out = host_out || !is_device_ptr(dE_dbeta);
-      }
+      if (dE_dgamma) QT_TRY(copy_2d(dE_dgamma, row, job->gsum, pitch, row, n_points, stream));
+      if (dE_dbeta) QT_TRY(copy_2d(dE_dbeta, row, job->gsum + p, pitch, row, n_points, stream));
     }
-    if (host_out) QT_HIP_CHECK(hipStreamSynchronize(stream));
     return QT_OK;
   } catch (const std::exception& ex) {
     return fail(QT_ENOMEM, std::string("qt_energy_grad: ") + ex.what());

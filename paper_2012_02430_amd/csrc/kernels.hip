@@ -62,6 +62,14 @@ __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevIn& in) {
   return r;
 }
 
+__device__ __forceinline__ uint32_t pext_tile(uint32_t tile, const DevIn& in) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxRuns; ++i)
+    if (i < in.t_nruns) r |= ((tile >> in.t_lo[i]) & ((1u << in.t_len[i]) - 1u)) << in.t_dst[i];
+  return r;
+}
+
 __device__ __forceinline__ uint32_t pext_bits(uint64_t x, uint32_t m) {
   uint32_t r = 0;
   int o = 0;
@@ -118,7 +126,7 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   for (int j = 0; j < NIN; ++j) {
     const DevIn& in = s.in[j];
     src[j] = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-             ((int64_t)pext_bits(sid, in.smask) << in.slow);
+             ((int64_t)pext_bits(sid, in.smask) << in.slow) + ((int64_t)pext_tile(tile, in) << in.has_v);
     lanep[j] = pext_runs(tid, in);
     scale[j] = (R)1;
     if (SCALED && in.exp_base >= 0) {
@@ -131,13 +139,16 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   E a0[kEPT][NIN], a1[kEPT][NIN];
 #pragma unroll
   for (int e = 0; e < kEPT; ++e) {
-    const uint32_t hi = (tile << kLgTile) | ((uint32_t)e << 8);
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       const int hv = s.in[j].has_v;
-      const int64_t idx = (int64_t)(pext_runs(hi, s.in[j]) + lanep[j]) << hv;
-      a0[e][j] = src[j][idx];
-      a1[e][j] = src[j][idx + hv];
+      const uint32_t idx = (s.in[j].ep[e] + lanep[j]) << hv;
+      if (hv) {
+        Cx<E>::load_pair(src[j], idx, a0[e][j], a1[e][j]);
+      } else {
+        a0[e][j] = src[j][idx];
+        a1[e][j] = a0[e][j];
+      }
     }
   }
   E* out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);

@@ -336,18 +336,35 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       return true;
     };
     auto contains = [](const std::vector<int>& a, int x) { return std::find(a.begin(), a.end(), x) != a.end(); };
-    // Multiplies the tensors of grp into one (product steps in this bucket).
-    auto fold = [&](std::vector<int> grp, int i, int v, bool post, int& res) -> qt_status {
-      while (grp.size() > 1) {
-        std::vector<int> g(grp.begin(), grp.begin() + std::min<size_t>(kMaxIn, grp.size()));
-        grp.erase(grp.begin(), grp.begin() + g.size());
-        qt_status st = emit(g, false, v, post);
-        if (st != QT_OK) return st;
-        if (buckets[i].empty()) return fail(QT_EPLAN, "qt_load_plan: internal: product left its bucket");
-        grp.insert(grp.begin(), buckets[i].back());
-        buckets[i].pop_back();
+    // Multiplies the tensors of grp into one (product steps).  The small
+    // tensors are multiplied among themselves first, so the big one (grp[0])
+    // is read and rewritten once.
+    auto fold = [&](std::vector<int> grp, int v, bool post, int& res) -> qt_status {
+      auto take_product = [&](const std::vector<int>& g) -> int {
+        const int id = (int)T.size();  // emit appends the product as the next tensor
+        if (emit(g, false, v, post) != QT_OK) return -1;
+        for (auto& bk : buckets) {
+          auto it = std::find(bk.begin(), bk.end(), id);
+          if (it != bk.end()) {
+            bk.erase(it);
+            break;
+          }
+        }
+        return id;
+      };
+      std::vector<int> small(grp.begin() + 1, grp.end());
+      while (small.size() > 1) {
+        std::vector<int> g(small.begin(), small.begin() + std::min<size_t>(kMaxIn, small.size()));
+        small.erase(small.begin(), small.begin() + g.size());
+        const int t = take_product(g);
+        if (t < 0) return fail(QT_EPLAN, "qt_load_plan: internal: product of small tensors failed");
+        small.insert(small.begin(), t);
       }
       res = grp[0];
+      if (!small.empty()) {
+        res = take_product({grp[0], small[0]});
+        if (res < 0) return fail(QT_EPLAN, "qt_load_plan: internal: product failed");
+      }
       return QT_OK;
     };
     auto try_fuse = [&](int i, int v, const std::vector<int>& ins, bool post, bool& fused) -> qt_status {
@@ -364,14 +381,20 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
         for (int x : eff(t, post))
           if (!contains(U, x)) U.push_back(x);
       if ((int)U.size() - 1 < gemm_min_rank) return QT_OK;
+      // the other tensors go to the smaller operand that holds their variables
+      const bool a_small = SA.size() <= SB.size();
       std::vector<int> toA = {A}, toB = {B};
-      for (int t : ins) {
-        if (t == A || t == B) continue;
+      auto assign = [&](int t) {
         const auto e = eff(t, post);
-        if (subset(e, SA)) toA.push_back(t);
-        else if (subset(e, SB)) toB.push_back(t);
-        else return QT_OK;
-      }
+        const bool inA = subset(e, SA), inB = subset(e, SB);
+        if (inA && inB) (a_small ? toA : toB).push_back(t);
+        else if (inA) toA.push_back(t);
+        else if (inB) toB.push_back(t);
+        else return false;
+        return true;
+      };
+      for (int t : ins)
+        if (t != A && t != B && !assign(t)) return QT_OK;
       std::vector<int> K = {v};
       std::vector<std::pair<int, int>> vecs;  // (bucket, tensor) of vectors on summed variables
       for (int u : SA) {
@@ -400,12 +423,12 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       for (const auto& jt : vecs) {
         auto& bk = buckets[jt.first];
         bk.erase(std::find(bk.begin(), bk.end(), jt.second));
-        toA.push_back(jt.second);
+        (a_small ? toA : toB).push_back(jt.second);  // summed variables are in both
       }
       int Ap = -1, Bp = -1;
-      qt_status st = fold(toA, i, v, post, Ap);
+      qt_status st = fold(toA, v, post, Ap);
       if (st != QT_OK) return st;
-      st = fold(toB, i, v, post, Bp);
+      st = fold(toB, v, post, Bp);
       if (st != QT_OK) return st;
       std::sort(K.begin(), K.end(), by_key);
       std::vector<int> outv;

@@ -17,6 +17,11 @@ namespace qt {
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
 qt_status fail(qt_status code, const std::string& msg);
+#define QT_TRY(expr)            \
+  do {                          \
+    qt_status _s = (expr);      \
+    if (_s != QT_OK) return _s; \
+  } while (0)
 #define QT_HIP_CHECK(expr)                                                           \
   do {                                                                               \
     hipError_t _e = (expr);                                                          \
@@ -74,7 +79,14 @@ struct DevIn {
   int32_t exp_base;
   int32_t exp_pt;
   int32_t exp_sb;
-  int32_t pad;
+  // Streaming tiles of 1024 outputs (x = tile << 10 | e << 8 | lane): the
+  // index splits as pext(tile << 10) + pext(e << 8) + pext(lane); the tile
+  // part has its own runs (over the tile index), the e part is tabulated.
+  int32_t t_nruns;
+  uint8_t t_lo[kMaxRuns];
+  uint8_t t_len[kMaxRuns];
+  uint8_t t_dst[kMaxRuns];
+  uint32_t ep[4];
 };
 
 struct DevStep {
@@ -365,6 +377,20 @@ struct SymTensor {
 };
 
 int env_int(const char* name, int dflt);
+// True for device (or managed) memory of the HIP runtime.
+bool is_device_ptr(const void* p);
+// Copy between library buffers and caller memory (a 2-D block of `height`
+// rows of `width` bytes).  Device to device runs asynchronously on the
+// stream; whenever host memory is involved the stream is drained first and
+// the copy blocks, so host data is in place (or consumed) on return:
+// asynchronous copies to pageable host memory are not ordered by a later
+// stream synchronisation.
+qt_status copy_2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
+                  hipStream_t stream);
+// Writes [np][2p] (gammas of a point, then its betas) to device memory `dev`
+// from caller arrays [np][p] in host or device memory.
+qt_status upload_params_to(double* dev, int np, int p, const double* gammas, const double* betas,
+                           hipStream_t stream);
 // A tunable: the plan's value when set, else the environment, else dflt.
 int tuned(int32_t value, const char* env, int dflt);
 void energy_forget(uint64_t serial);  // drops cached energy jobs that use the plan

@@ -3,6 +3,7 @@
 // the per-slice steps batched over slices (the loop over ranks becomes a
 // batch dimension), per-slice scalars, and the FP64 sum over slices.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
@@ -16,14 +17,6 @@ namespace {
 // Default device workspace budget for the per-slice arena.
 constexpr int64_t kDefaultBudget = 64ll << 30;
 
-bool is_device_ptr(const void* p) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
 
 int ilog2(int64_t x) {
   int r = 0;
@@ -43,6 +36,57 @@ int env_int(const char* name, int dflt) {
 }
 
 int tuned(int32_t value, const char* env, int dflt) { return value > 0 ? value : env_int(env, dflt); }
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+qt_status copy_2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
+                  hipStream_t stream) {
+  if (!dst || !src || width == 0 || height == 0) return QT_OK;
+  if (is_device_ptr(dst) && is_device_ptr(src)) {
+    QT_HIP_CHECK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, hipMemcpyDeviceToDevice, stream));
+    return QT_OK;
+  }
+  // host memory involved: drain the stream, then blocking 1-D copies with
+  // an explicit direction (2-D copies to pageable memory were seen to leave
+  // the destination unwritten)
+  const bool dd = is_device_ptr(dst), sd = is_device_ptr(src);
+  const hipMemcpyKind kind = dd ? hipMemcpyHostToDevice : (sd ? hipMemcpyDeviceToHost : hipMemcpyHostToHost);
+  QT_HIP_CHECK(hipStreamSynchronize(stream));
+  if (dpitch == width && spitch == width) {
+    QT_HIP_CHECK(hipMemcpy(dst, src, width * height, kind));
+  } else {
+    for (size_t r = 0; r < height; ++r)
+      QT_HIP_CHECK(hipMemcpy((char*)dst + r * dpitch, (const char*)src + r * spitch, width, kind));
+  }
+  return QT_OK;
+}
+
+qt_status upload_params_to(double* dev, int np, int p, const double* gammas, const double* betas,
+                           hipStream_t stream) {
+  if (p == 0) return QT_OK;
+  const size_t row = (size_t)p * sizeof(double), pitch = 2 * row;
+  if (is_device_ptr(gammas) && is_device_ptr(betas)) {
+    QT_TRY(copy_2d(dev, pitch, gammas, row, row, np, stream));
+    return copy_2d(dev + p, pitch, betas, row, row, np, stream);
+  }
+  // host parameters: interleave here, one blocking copy
+  std::vector<double> h((size_t)np * 2 * p);
+  for (int i = 0; i < np; ++i)
+    for (int k = 0; k < p; ++k) {
+      h[(size_t)i * 2 * p + k] = gammas[(size_t)i * p + k];
+      h[(size_t)i * 2 * p + p + k] = betas[(size_t)i * p + k];
+    }
+  return copy_2d(dev, h.size() * sizeof(double), h.data(), h.size() * sizeof(double), h.size() * sizeof(double), 1,
+                 stream);
+}
 
 bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns) {
   int n = 0, d = 0;
@@ -228,11 +272,6 @@ qt_status dev_alloc(T** p, int64_t count, int64_t& bytes) {
   return QT_OK;
 }
 
-#define QT_TRY(expr)            \
-  do {                          \
-    qt_status _s = (expr);      \
-    if (_s != QT_OK) return _s; \
-  } while (0)
 
 
 constexpr int64_t kUnitAlign = 64;  // arena offsets in multiples of 64 elements
@@ -265,7 +304,18 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
   d.smask = smask;
   d.slow = slow;
   d.has_v = has_v;
-  return make_runs(mask, kMaxRuns, d.run_lo, d.run_len, d.run_dst, d.nruns);
+  if (!make_runs(mask, kMaxRuns, d.run_lo, d.run_len, d.run_dst, d.nruns)) return false;
+  // tile part: the bits of x from 10 up, as runs over the tile index
+  constexpr int kLgTile = 10;
+  const uint32_t below = (uint32_t)__builtin_popcount(mask & ((1u << kLgTile) - 1u));
+  if (!make_runs(mask >> kLgTile, kMaxRuns, d.t_lo, d.t_len, d.t_dst, d.t_nruns)) return false;
+  for (int i = 0; i < d.t_nruns; ++i) d.t_dst[i] = (uint8_t)(d.t_dst[i] + below);
+  for (uint32_t e = 0; e < 4; ++e) {
+    uint32_t r = 0;
+    for (int i = 0; i < d.nruns; ++i) r |= (((e << 8) >> d.run_lo[i]) & ((1u << d.run_len[i]) - 1u)) << d.run_dst[i];
+    d.ep[e] = r;
+  }
+  return true;
 }
 
 // Launch schedule, independent of batch size and pointers:
@@ -824,10 +874,8 @@ qt_status upload_params(qt_plan& plan, int np, const double* gammas, const doubl
   if (p == 0) return QT_OK;
   auto& ws = *plan.ws;
   const size_t pitch = 2 * p * sizeof(double);
-  QT_HIP_CHECK(hipMemcpy2DAsync(ws.params, pitch, gammas, p * sizeof(double), p * sizeof(double), np,
-                                hipMemcpyDefault, stream));
-  QT_HIP_CHECK(hipMemcpy2DAsync(ws.params + p, pitch, betas, p * sizeof(double), p * sizeof(double), np,
-                                hipMemcpyDefault, stream));
+  (void)pitch;
+  QT_TRY(upload_params_to(ws.params, np, p, gammas, betas, stream));
   return QT_OK;
 }
 
@@ -992,8 +1040,6 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
         injected = true;
       }
     }
-    const bool out_dev = is_device_ptr(out);
-    const bool ps_dev = per_slice_out && is_device_ptr(per_slice_out);
     const int64_t n_range = slice_end - slice_begin;
     for (int i = 0; i < n_plans; ++i) {
       qt_plan& plan = *plans[i];
@@ -1003,15 +1049,14 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
       if (per_slice_out && stop > slice_begin) {
         const size_t row = (size_t)n_range * 3 * sizeof(double);
         const size_t width = (size_t)(stop - slice_begin) * 3 * sizeof(double);
-        QT_HIP_CHECK(hipMemcpy2DAsync(per_slice_out + (size_t)i * n_points * n_range * 3, row, ws.per_slice, row,
-                                      width, n_points, ps_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                      stream));
+        QT_TRY(copy_2d(per_slice_out + (size_t)i * n_points * n_range * 3, row, ws.per_slice, row, width, n_points,
+                       stream));
       }
-      if (!injected)
-        QT_HIP_CHECK(hipMemcpyAsync(out + (size_t)i * n_points, ws.sums, (size_t)n_points * sizeof(qt_amp),
-                                    out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+      if (!injected) {
+        const size_t bytes = (size_t)n_points * sizeof(qt_amp);
+        QT_TRY(copy_2d(out + (size_t)i * n_points, bytes, ws.sums, bytes, bytes, 1, stream));
+      }
     }
-    if (!out_dev || (per_slice_out && !ps_dev)) QT_HIP_CHECK(hipStreamSynchronize(stream));
     if (injected) return fail(QT_EFAULT_INJECTED, "qt_contract_batch: QT_FAULT_AFTER_SLICE fired");
     return QT_OK;
   } catch (const std::exception& ex) {
@@ -1081,7 +1126,18 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
         if (op.seg < 0) {
           const SymStep& st = plan->steps[op.step];
           j += std::string(first ? "" : ",") + "{\"step\":" + std::to_string(op.step) + ",\"rank\":" +
-               std::to_string(st.rank) + ",\"inputs\":" + std::to_string(st.ins.size()) +
+               std::to_string(st.rank) + ",\"inputs\":" + std::to_string(st.ins.size()) + ",\"level\":" +
+               std::to_string(st.level) + ",\"bytes\":" + std::to_string(st.bytes_c64) + ",\"in_ranks\":[" +
+               [&] {
+                 // per input: its rank within one slice, and whether it holds the summed variable
+                 std::string r, h;
+                 for (size_t q = 0; q < st.ins.size(); ++q) {
+                   const int rk = plan->tensors[st.ins[q].tensor].rank - __builtin_popcount(st.ins[q].smask);
+                   r += (q ? "," : "") + std::to_string(rk);
+                   h += (q ? "," : "") + std::to_string(st.ins[q].has_v);
+                 }
+                 return r + "],\"in_has_v\":[" + h;
+               }() + "]" +
                (st.gemm ? ",\"gemm\":{\"k_bits\":" + std::to_string(st.kvars.size()) + ",\"flops\":" +
                               std::to_string(st.flops) + "}"
                         : std::string()) +

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -75,7 +76,7 @@ def cpu_baseline(edges, g, b, sch, budget_s):
     return reps / el, reps, el
 
 
-def energy_bench(steps, warmup, cpu_seconds):
+def energy_bench(steps, warmup, cpu_seconds, waves=0):
     """Edge-energies/s on n=1000, p=3: 1500 lightcones x 32 points per evaluation."""
     import ctypes
 
@@ -91,7 +92,11 @@ def energy_bench(steps, warmup, cpu_seconds):
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, npt, seed=1)
     model = api.EnergyModel(n, edges, p, precision="c64")
-    tuned = autotune.tune_energy(model, npt, repeats=3)
+    if waves:
+        model.set_tuning(waves, 0)
+        tuned = {"waves": waves}
+    else:
+        tuned = autotune.tune_energy(model, npt, repeats=3)
     lib = L.load()
     stream = torch.cuda.current_stream()
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
@@ -154,7 +159,7 @@ def energy_bench(steps, warmup, cpu_seconds):
     }
 
 
-def gradient_bench(steps, warmup, cpu_seconds):
+def gradient_bench(steps, warmup, cpu_seconds, grad_waves=0, multi_waves=0):
     """Edge-gradients/s on n=200, p=2: energy and dE/dgamma, dE/dbeta over
     300 lightcones x 64 points per evaluation (forward + adjoint, one launch)."""
     import numpy as np
@@ -168,8 +173,12 @@ def gradient_bench(steps, warmup, cpu_seconds):
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, npt, seed=1)
     model = api.EnergyModel(n, edges, p, precision="c64")
-    tuned = autotune.tune_energy(model, npt, grad=True, repeats=3)
-    autotune.tune_energy(model, npt, grad=False, repeats=3)
+    if grad_waves:
+        model.set_tuning(multi_waves, grad_waves)
+        tuned = {"waves": grad_waves}
+    else:
+        tuned = autotune.tune_energy(model, npt, grad=True, repeats=3)
+        autotune.tune_energy(model, npt, grad=False, repeats=3)
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
     bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
@@ -219,6 +228,90 @@ def gradient_bench(steps, warmup, cpu_seconds):
     }
 
 
+def mfma_bench():
+    """QAOA p=1 amplitude on n=210: the 256 slices of an 8-variable step-dependent slicing plan
+    (min-degree order), fused GEMM buckets on MFMA vs the same plan unfused, and the plain path."""
+    import numpy as np
+    import torch
+
+    from paper_2012_02430_amd import api
+    from paper_2012_02430_amd import network as N
+    from workloads import qaoa_params, regular_graph
+
+    n, p, k = 210, 1, 8
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(k, algo="min_degree")
+    g, b = qaoa_params(p, 1, seed=1)
+    fused = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32")
+    unfused = api.Plan(net, sch.order, sch.groups, precision="c64")
+    plain = api.Plan(net, sch.order, sch.groups, precision="c128", plain=True, slice_batch=1)
+
+    def timed(plan, s1):
+        plan.contract_batch(g, b, 0, min(s1, 8))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        vals, per = plan.contract_batch(g, b, 0, s1, per_slice=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, vals, per
+
+    el_f, _, per_f = timed(fused, 256)
+    fused.profile_enable(True)
+    fused.contract_batch(g, b, 0, 256)
+    prof = fused.profile_read()
+    fused.profile_enable(False)
+    el_u, _, per_u = timed(unfused, 256)
+    el_p, _, per_p = timed(plain, 4)
+    err = float(np.max(np.abs(per_f[0, :4] - per_p[0]) / np.abs(per_p[0])))
+    err_u = float(np.max(np.abs(per_u[0, :4] - per_p[0]) / np.abs(per_p[0])))
+    gemm = prof.get("gemm", (0, 0.0, 0.0, 0.0))
+    gemms = [s for s in fused.describe()["stream_steps"] if "gemm" in s]
+    return {
+        "metric": "slices/s",
+        "workload": "QAOA p=1 single amplitude, seeded random 3-regular graph n=210 (315 edges): 256 slices of a "
+                    "step-dependent slicing plan over 8 variables (min-degree order), complex64 with power-of-two "
+                    "scaling, FP64 slice sum",
+        "value": 256 / el_f,
+        "s_per_256_slices": el_f,
+        "width": {"fused": fused.info().width, "unfused": unfused.info().width},
+        "gemm_buckets": [{"rank": s["rank"], "k_bits": s["gemm"]["k_bits"], "gflop_per_slice": s["gemm"]["flops"] / 1e9}
+                         for s in gemms],
+        "gemm_kernel": {"launches": gemm[0], "ms": gemm[1], "TFLOP/s": gemm[3] / gemm[1] / 1e9 if gemm[1] else 0,
+                        "GB/s": gemm[2] / gemm[1] / 1e6 if gemm[1] else 0, "peak_TFLOP/s": 157.3},
+        "kernel_classes_ms": {k: round(v[1], 2) for k, v in prof.items()},
+        "unfused_c64": {"value": 256 / el_u, "unit": "slices/s"},
+        "plain_c128": {"value": 4 / el_p, "unit": "slices/s", "sample": "slices 0-3"},
+        "speedup_vs_unfused": el_u / el_f,
+        "speedup_vs_plain_c128": (4 / el_p) and (256 / el_f) / (4 / el_p),
+        "max_rel_err_vs_c128_slices_0_3": {"fused": err, "unfused": err_u},
+    }
+
+
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "lds_exec_qaoa_n60_p2_256slices.md")
+
+
+def measured_traffic(tuning):
+    """HBM bytes per launch of the LDS executor on this workload, from the committed FETCH_SIZE/WRITE_SIZE
+    measurement, while the kernel sources and launch shape are those it was taken with (else None)."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, re.M))
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2012_02430_amd", "csrc")
+    h = hashlib.sha1()
+    for f in ("lds_exec.hip", "qt_internal.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    if fields.get("source_sha1") != h.hexdigest():
+        return None
+    if fields.get("tuning") != f"{tuning['lds_waves']}/{tuning['lds_max_rank']}":
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,8 +320,20 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-energy", action="store_true", help="amplitude section only")
+    ap.add_argument("--sections", default="amp,energy,gradient,mfma",
+                    help="comma list of amp (the headline line), energy, gradient, mfma")
+    ap.add_argument("--lds-waves", type=int, default=0, help="fix the LDS executor launch shape (skips tuning)")
+    ap.add_argument("--lds-max-rank", type=int, default=0)
+    ap.add_argument("--multi-waves", type=int, default=0, help="fix the lightcone launch shape (skips tuning)")
+    ap.add_argument("--grad-waves", type=int, default=0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="program for rocprofv3 --pmc: a 256 MiB device copy (counter calibration), then 5 "
+                         "amplitudes of the headline workload at the given launch shape; prints no JSON")
     args = ap.parse_args()
+    sections = set(args.sections.split(","))
+    if args.no_energy:
+        sections = {"amp"}
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
               "described in DESIGN.md, not built)", file=sys.stderr)
@@ -247,11 +352,26 @@ def main():
     g, b = g[0], b[0]
 
     net, sch, plan, edges = build_plan("c64", fold=True)
+    if args.traffic_probe:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        plan.set_tuning(args.lds_waves, args.lds_max_rank)
+        gd = torch.tensor(g, dtype=torch.float64, device="cuda")
+        bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+        time_calls(plan, gd, bd, torch.zeros(3, dtype=torch.float64, device="cuda"), stream, 5, 1)
+        print(f"[bench] traffic probe done: tuning {plan.get_tuning()}", flush=True)
+        return
     _, _, plain, _ = build_plan("c128", slice_batch=1, plain=True)
     print(f"[bench] plan: width {sch.width} (prefix {sch.prefix_width}, slice {sch.slice_width}), "
           f"unsliced {sch.unsliced_width}, step {sch.step}, 256 slices", flush=True)
-    # measured launch shape (untimed; cached by shape signature)
-    tuning = autotune.tune_plan(plan, n_points=1, repeats=3)
+    # measured launch shape (untimed; cached by shape signature), or the one given
+    if args.lds_waves or args.lds_max_rank:
+        plan.set_tuning(args.lds_waves, args.lds_max_rank)
+        tuning = dict(plan.get_tuning(), cached=False, ms=float("nan"))
+    else:
+        tuning = autotune.tune_plan(plan, n_points=1, repeats=3)
     print(f"[bench] tuned: lds_waves {tuning['lds_waves']}, lds_max_rank {tuning['lds_max_rank']} "
           f"({'cached' if tuning['cached'] else 'measured'}: {tuning['ms']:.3f} ms)", flush=True)
 
@@ -299,18 +419,27 @@ def main():
         print(f"[bench] oracle on host: {rate:.3f} amplitudes/s", flush=True)
 
     energy = None
-    if not args.no_energy:
-        energy = energy_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5)
+    if "energy" in sections:
+        energy = energy_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5, args.multi_waves)
         print(f"[bench] energy: {energy['value']:.3e} edge-energies/s ({energy['ms_per_evaluation']:.2f} ms per "
               f"1500x32 evaluation), plain c128 {energy['plain_c128']['value']:.1f}/s, "
               f"max abs err {energy['max_abs_err_vs_oracle_sampled']:.1e}", flush=True)
 
     gradient = None
-    if not args.no_energy:
-        gradient = gradient_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5)
+    if "gradient" in sections:
+        gradient = gradient_bench(max(5, args.steps // 5), 2, 3.0 if not args.no_cpu_baseline else 0.5,
+                                  args.grad_waves, args.multi_waves)
         print(f"[bench] gradient: {gradient['value']:.3e} edge-gradients/s ({gradient['ms_per_evaluation']:.2f} ms "
               f"per 300x64 evaluation, forward only {gradient['ms_forward_only']:.2f} ms), "
               f"max rel err {gradient['max_err_vs_oracle_sampled']:.1e}", flush=True)
+
+    mfma = None
+    if "mfma" in sections:
+        mfma = mfma_bench()
+        print(f"[bench] n=210 fused GEMM plan: {mfma['value']:.1f} slices/s (unfused c64 "
+              f"{mfma['unfused_c64']['value']:.1f}, plain c128 {mfma['plain_c128']['value']:.1f}); GEMM "
+              f"{mfma['gemm_kernel']['TFLOP/s']:.1f} TFLOP/s; rel err {mfma['max_rel_err_vs_c128_slices_0_3']['fused']:.1e}",
+              flush=True)
 
     inf = plan.info()
     line = {
@@ -341,11 +470,14 @@ def main():
         "launches_per_amplitude": inf.n_launches,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(tuning) if dom == "lds" else None,
+                     "algorithmic_bytes_per_launch": bytes_ / launches},
         "cpu_baseline": cpu,
         "tuning": {"lds_waves": tuning["lds_waves"], "lds_max_rank": tuning["lds_max_rank"]},
         "energy": energy,
         "gradient": gradient,
+        "mfma_gemm": mfma,
     }
     print(json.dumps(line), flush=True)
 

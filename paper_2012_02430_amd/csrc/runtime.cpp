@@ -1139,7 +1139,26 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
                  return r + "],\"in_has_v\":[" + h;
                }() + "]" +
                (st.gemm ? ",\"gemm\":{\"k_bits\":" + std::to_string(st.kvars.size()) + ",\"flops\":" +
-                              std::to_string(st.flops) + "}"
+                              std::to_string(st.flops) + ",\"layouts\":" + [&] {
+                                // per operand, from bit 0 up: the counter each storage bit belongs to
+                                const auto& va = plan->tensors[st.ins[0].tensor].vars;
+                                const auto& vb = plan->tensors[st.ins[1].tensor].vars;
+                                auto has = [](const std::vector<int32_t>& v, int x) {
+                                  return std::find(v.begin(), v.end(), x) != v.end();
+                                };
+                                auto code = [&](int x) {
+                                  if (has(st.kvars, x)) return 'k';
+                                  const bool ia = has(va, x), ib = has(vb, x);
+                                  return ia && ib ? 'b' : (ia ? 'm' : (ib ? 'n' : 's'));
+                                };
+                                std::string r = "[\"";
+                                for (int x : va) r += code(x);
+                                r += "\",\"";
+                                for (int x : vb) r += code(x);
+                                r += "\",\"";
+                                for (int x : plan->tensors[st.out].vars) r += code(x);
+                                return r + "\"]";
+                              }() + "}"
                         : std::string()) +
                "}";
           first = false;

@@ -275,20 +275,21 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
   const bool tracing = trace != nullptr && blockIdx.x == 0 && tid == 0;
   if (tracing) trace[0] = wall_clock64();
   for (int L = 0; L < X.n_levels; ++L) {
+    const int u_beg = level_off[L];
     const int u_end = level_off[L + 1];
-    for (int u = level_off[L] + wave; u < u_end; u += nw) {
-      const uint2 un = units[u];
-      const XStep& st = steps[un.x];
+    for (int u = u_beg + wave; u < u_end; u += nw) {
+      const XStep& st = steps[u];
+      const uint32_t chunk = (uint32_t)st.pad;
       const bool big = st.r >= kXBigRank;
       if (st.n_in <= 2) {
-        if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 2, kBig>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 2, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       } else if (st.n_in <= 4) {
-        if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 4, kBig>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 4, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       } else {
-        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 8, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       }
     }
     __syncthreads();

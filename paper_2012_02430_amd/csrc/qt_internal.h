@@ -202,10 +202,13 @@ inline int x_gate_off(int kind, int layer) {
 }
 
 // One launch of the executor: every workgroup runs the same level schedule
-// for its batch item (pt, sb).
+// for its batch item (pt, sb).  Work unit u (levels in order) is described
+// by steps[u], a copy of its step's descriptor whose pad field holds the
+// unit's chunk, so a wavefront reaches its descriptor without first reading
+// a unit table.
 struct XLaunch {
-  const XStep* steps;
-  const uint2* units;      // (step, 64-element chunk) work units, level by level
+  const XStep* steps;      // per unit
+  const uint2* units;      // unused by the executor (kept for the host)
   const int32_t* level_off;  // n_levels + 1 offsets into units
   const XCopy* copies;     // inputs staged into LDS at the start
   const double* params;    // [points][2p]: gammas then betas

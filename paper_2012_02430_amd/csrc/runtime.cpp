@@ -146,6 +146,7 @@ struct qt_plan::Workspace {
     int lds_elems = 0;
     double bytes_c64 = 0, flops = 0;  // per item
     std::vector<XStep> xsteps;
+    std::vector<XStep> ustep;  // per unit, level order
     std::vector<XCopy> copies;
     std::vector<uint2> units;
     std::vector<int32_t> level_off;
@@ -623,7 +624,13 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
         cp.lslot = ws.lds_slot[t];
         S.copies.push_back(cp);
       }
-    total += ((S.xsteps.size() * sizeof(XStep) + 255) & ~(size_t)255) +
+    // per-unit descriptors (the unit's chunk in the pad field)
+    S.ustep.clear();
+    for (const uint2& u : S.units) {
+      S.ustep.push_back(S.xsteps[u.x]);
+      S.ustep.back().pad = (int32_t)u.y;
+    }
+    total += ((S.ustep.size() * sizeof(XStep) + 255) & ~(size_t)255) +
              ((S.copies.size() * sizeof(XCopy) + 255) & ~(size_t)255) +
              ((S.units.size() * sizeof(uint2) + 255) & ~(size_t)255) +
              ((S.level_off.size() * sizeof(int32_t) + 255) & ~(size_t)255);
@@ -640,7 +647,7 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     return at;
   };
   for (auto& S : ws.segs) {
-    S.launch.steps = (const XStep*)put(S.xsteps.data(), S.xsteps.size() * sizeof(XStep));
+    S.launch.steps = (const XStep*)put(S.ustep.data(), S.ustep.size() * sizeof(XStep));
     S.launch.units = (const uint2*)put(S.units.data(), S.units.size() * sizeof(uint2));
     S.launch.level_off = (const int32_t*)put(S.level_off.data(), S.level_off.size() * sizeof(int32_t));
     S.launch.copies = (const XCopy*)put(S.copies.data(), S.copies.size() * sizeof(XCopy));

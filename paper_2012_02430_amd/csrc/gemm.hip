@@ -56,31 +56,45 @@ __device__ __forceinline__ int gshift(uint32_t maxbits) {
   return s < -126 ? -126 : (s > 127 ? 127 : s);
 }
 
-template <int TM, int TN>
+// Tile: NB = 2^TB batch indices x TM = 2^LM rows x TN = 2^LN columns, the
+// low bits of the b, m and n counters.  The host picks (TB, LM, LN) so that
+// the tile's bits are C's lowest storage bits where it can, which makes the
+// tile's output one contiguous block.  Wavefront w owns the 16 x 16
+// sub-tile (batch, m block, n block) number w.
+template <int TB, int LM, int LN>
 __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __restrict__ exps,
                                                     uint32_t* __restrict__ maxbits, uint32_t tiles_per_block,
                                                     uint64_t n_tiles) {
-  constexpr int kLgM = TM == 32 ? 5 : 4, kLgN = TN == 32 ? 5 : 4;
-  constexpr int kTileBits = kLgM + kLgN;
-  __shared__ float sAr[TM][kTK + 1], sAi[TM][kTK + 1], sBr[TN][kTK + 1], sBi[TN][kTK + 1];
-  __shared__ float sCr[TM * (TN + 1)], sCi[TM * (TN + 1)];
+  constexpr int NB = 1 << TB, TM = 1 << LM, TN = 1 << LN;
+  constexpr int kARows = NB * TM, kBRows = NB * TN;
+  constexpr int kTileBits = TB + LM + LN;
+  constexpr int kTileElems = NB * TM * TN;
+  constexpr int kSubM = TM / 16, kSubN = TN / 16;
+  constexpr int kSubs = NB * kSubM * kSubN;
+  static_assert(kSubs <= kGThreads / 64, "one 16 x 16 sub-tile per wavefront");
+  __shared__ float sAr[kARows][kTK + 1], sAi[kARows][kTK + 1], sBr[kBRows][kTK + 1], sBi[kBRows][kTK + 1];
+  __shared__ float sCr[NB * TM * (TN + 1)], sCi[NB * TM * (TN + 1)];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
-  // Output order: the tile's bits sorted by their position in C, so that
-  // consecutive threads write consecutive addresses where C's low bits are
-  // tile bits.  Bit j of a write index t carries C offset cw[j] and LDS
-  // offset lw[j] (all wavefront-uniform).
+  // Output order: the tile's bits sorted by their position in C; bit j of a
+  // write index t carries C offset cw[j] and staging offset lw[j].
   uint32_t cw[kTileBits], lw[kTileBits];
   {
     uint32_t pos[kTileBits];
 #pragma unroll
     for (int i = 0; i < kTileBits; ++i) {
-      const bool isn = i >= kLgM;
-      const int bit = isn ? i - kLgM : i;
-      cw[i] = isn ? gmap(g.c_n, 1u << bit) : gmap(g.c_m, 1u << bit);
-      lw[i] = isn ? (1u << bit) : (1u << bit) * (TN + 1);
+      if (i < TB) {
+        cw[i] = gmap(g.c_b, 1u << i);
+        lw[i] = (1u << i) * TM * (TN + 1);
+      } else if (i < TB + LM) {
+        cw[i] = gmap(g.c_m, 1u << (i - TB));
+        lw[i] = (1u << (i - TB)) * (TN + 1);
+      } else {
+        cw[i] = gmap(g.c_n, 1u << (i - TB - LM));
+        lw[i] = 1u << (i - TB - LM);
+      }
       pos[i] = cw[i];
     }
     for (int i = 1; i < kTileBits; ++i)  // insertion sort by C offset (tiny, uniform)
@@ -91,35 +105,70 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       }
   }
 
-  const uint32_t n_nt = (1u << g.nn) / TN, n_mt = (1u << g.nm) / TM;
+  const uint32_t n_nt = (1u << g.nn) / TN, n_mt = (1u << g.nm) / TM, n_bt = (1u << g.nb) / NB;
   const uint32_t K = 1u << g.nk;
   const int tk = K < (uint32_t)kTK ? (int)K : kTK;  // K >= 8
-  constexpr int kALoads = (TM * kTK + kGThreads - 1) / kGThreads, kBLoads = (TN * kTK + kGThreads - 1) / kGThreads;
-  constexpr int kSubN = TN / 16;
-  constexpr int kSubs = (TM / 16) * kSubN;
-  const int wm = wave / kSubN, wn = wave % kSubN;
+  constexpr int kALoads = (kARows * kTK + kGThreads - 1) / kGThreads;
+  constexpr int kBLoads = (kBRows * kTK + kGThreads - 1) / kGThreads;
+  constexpr int kCWrites = (kTileElems + kGThreads - 1) / kGThreads;
+  const int wb = wave / (kSubM * kSubN), wm = (wave / kSubN) % kSubM, wn = wave % kSubN;
   const int li = lane & 15, lk = lane >> 4;
 
+  // Per-thread parts of every index, the same for all tiles: maps are
+  // linear over disjoint bits, so an element's offset is its in-tile part
+  // plus the tile's base (uniform).  Row r of the A block is (batch r / TM,
+  // m r % TM), k part ki.
+  uint32_t a_loc[kALoads], a_ki[kALoads], b_loc[kBLoads], b_ki[kBLoads], c_loc[kCWrites], s_loc[kCWrites];
+  int a_r[kALoads], b_r[kBLoads];
+#pragma unroll
+  for (int q = 0; q < kALoads; ++q) {
+    const int e = tid + q * kGThreads;
+    a_r[q] = e / tk;
+    a_ki[q] = (uint32_t)(e % tk);
+    a_loc[q] = gmap(g.a_b, (uint32_t)a_r[q] / TM) + gmap(g.a_m, (uint32_t)a_r[q] % TM) + gmap(g.a_k, a_ki[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kBLoads; ++q) {
+    const int e = tid + q * kGThreads;
+    b_r[q] = e / tk;
+    b_ki[q] = (uint32_t)(e % tk);
+    b_loc[q] = gmap(g.b_b, (uint32_t)b_r[q] / TN) + gmap(g.b_n, (uint32_t)b_r[q] % TN) + gmap(g.b_k, b_ki[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kCWrites; ++q) {
+    const uint32_t t = (uint32_t)(tid + q * kGThreads);
+    uint32_t co = 0, lo = 0;
+#pragma unroll
+    for (int j = 0; j < kTileBits; ++j)
+      if ((t >> j) & 1u) {
+        co += cw[j];
+        lo += lw[j];
+      }
+    c_loc[q] = co;
+    s_loc[q] = lo;
+  }
+
   for (uint32_t it = 0; it < tiles_per_block; ++it) {
-    const uint64_t tile_id = (uint64_t)blockIdx.x * tiles_per_block + it;
+    const uint64_t tile_id = (uint64_t)blockIdx.x + (uint64_t)it * gridDim.x;  // grid-strided
     if (tile_id >= n_tiles) break;
-    // tile -> (n tile, m tile, batch index, item), n tile fastest
+    // tile -> (n tile, m tile, batch tile, item), n tile fastest
     uint64_t bid = tile_id;
     const uint32_t nt = (uint32_t)(bid % n_nt);
     bid /= n_nt;
     const uint32_t mt = (uint32_t)(bid % n_mt);
     bid /= n_mt;
-    const uint32_t bb = (uint32_t)(bid & ((1ull << g.nb) - 1ull));
-    const uint32_t item = (uint32_t)(bid >> g.nb);
+    const uint32_t bt = (uint32_t)(bid % n_bt);
+    const uint32_t item = (uint32_t)(bid / n_bt);
     const uint32_t sb = item & ((1u << g.lg_nsb) - 1u);
     const uint32_t pt = item >> g.lg_nsb;
     const uint64_t sid = (uint64_t)g.chunk_base + sb;
+    const uint32_t b0 = bt * NB;
 
     const float2* A = reinterpret_cast<const float2*>(g.a) + (int64_t)pt * g.a_pt + (int64_t)sb * g.a_sb +
-                      ((int64_t)gpext(sid, g.a_smask) << g.a_slow) + gmap(g.a_b, bb);
+                      ((int64_t)gpext(sid, g.a_smask) << g.a_slow) + gmap(g.a_b, b0) + gmap(g.a_m, mt * TM);
     const float2* B = reinterpret_cast<const float2*>(g.b) + (int64_t)pt * g.b_pt + (int64_t)sb * g.b_sb +
-                      ((int64_t)gpext(sid, g.b_smask) << g.b_slow) + gmap(g.b_b, bb);
-    float2* C = reinterpret_cast<float2*>(g.c) + (int64_t)pt * g.c_pt + (int64_t)sb * g.c_sb + gmap(g.c_b, bb) +
+                      ((int64_t)gpext(sid, g.b_smask) << g.b_slow) + gmap(g.b_b, b0) + gmap(g.b_n, nt * TN);
+    float2* C = reinterpret_cast<float2*>(g.c) + (int64_t)pt * g.c_pt + (int64_t)sb * g.c_sb + gmap(g.c_b, b0) +
                 gmap(g.c_m, mt * TM) + gmap(g.c_n, nt * TN);
 
     float sa = 1.f, sbs = 1.f;
@@ -137,25 +186,6 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       eacc += exps[slot] + sh;
     }
 
-    // per-thread load coordinates (fixed over the K loop); the k part of an
-    // index splits as map(k0) + map(ki) because k0 is a multiple of tk
-    uint32_t a_off[kALoads], a_ki[kALoads], b_off[kBLoads], b_ki[kBLoads];
-    int a_mi[kALoads], b_ni[kBLoads];
-#pragma unroll
-    for (int q = 0; q < kALoads; ++q) {
-      const int e = tid + q * kGThreads;
-      a_mi[q] = e / tk;
-      a_ki[q] = (uint32_t)(e % tk);
-      a_off[q] = gmap(g.a_m, mt * TM + (uint32_t)a_mi[q]) + gmap(g.a_k, a_ki[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < kBLoads; ++q) {
-      const int e = tid + q * kGThreads;
-      b_ni[q] = e / tk;
-      b_ki[q] = (uint32_t)(e % tk);
-      b_off[q] = gmap(g.b_n, nt * TN + (uint32_t)b_ni[q]) + gmap(g.b_k, b_ki[q]);
-    }
-
     v4f totR = {0.f, 0.f, 0.f, 0.f}, totI = {0.f, 0.f, 0.f, 0.f};  // running sums
     v4f cmpR = {0.f, 0.f, 0.f, 0.f}, cmpI = {0.f, 0.f, 0.f, 0.f};  // their compensations
     float2 va[kALoads], vb[kBLoads];
@@ -163,32 +193,33 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       const uint32_t ka = gmap(g.a_k, k0), kb = gmap(g.b_k, k0);
 #pragma unroll
       for (int q = 0; q < kALoads; ++q)
-        if (a_mi[q] < TM) va[q] = A[a_off[q] + ka];
+        if (a_r[q] < kARows) va[q] = A[a_loc[q] + ka];
 #pragma unroll
       for (int q = 0; q < kBLoads; ++q)
-        if (b_ni[q] < TN) vb[q] = B[b_off[q] + kb];
+        if (b_r[q] < kBRows) vb[q] = B[b_loc[q] + kb];
     };
     fetch(0);
     for (uint32_t k0 = 0; k0 < K; k0 += (uint32_t)tk) {
 #pragma unroll
       for (int q = 0; q < kALoads; ++q)
-        if (a_mi[q] < TM) {
-          sAr[a_mi[q]][a_ki[q]] = va[q].x * sa;
-          sAi[a_mi[q]][a_ki[q]] = va[q].y * sa;
+        if (a_r[q] < kARows) {
+          sAr[a_r[q]][a_ki[q]] = va[q].x * sa;
+          sAi[a_r[q]][a_ki[q]] = va[q].y * sa;
         }
 #pragma unroll
       for (int q = 0; q < kBLoads; ++q)
-        if (b_ni[q] < TN) {
-          sBr[b_ni[q]][b_ki[q]] = vb[q].x * sbs;
-          sBi[b_ni[q]][b_ki[q]] = vb[q].y * sbs;
+        if (b_r[q] < kBRows) {
+          sBr[b_r[q]][b_ki[q]] = vb[q].x * sbs;
+          sBi[b_r[q]][b_ki[q]] = vb[q].y * sbs;
         }
       __syncthreads();
       if (k0 + (uint32_t)tk < K) fetch(k0 + (uint32_t)tk);  // next stage in flight during the products
       if (wave < kSubs) {
+        const int ra = wb * TM + wm * 16 + li, rbw = wb * TN + wn * 16 + li;
         v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
         for (int kk = 0; kk < tk; kk += 4) {
-          const float ar = sAr[wm * 16 + li][kk + lk], ai = sAi[wm * 16 + li][kk + lk];
-          const float br = sBr[wn * 16 + li][kk + lk], bi = sBi[wn * 16 + li][kk + lk];
+          const float ar = sAr[ra][kk + lk], ai = sAi[ra][kk + lk];
+          const float br = sBr[rbw][kk + lk], bi = sBi[rbw][kk + lk];
           accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accR, 0, 0, 0);
           accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accR, 0, 0, 0);
           accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, accI, 0, 0, 0);
@@ -211,7 +242,7 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
     if (wave < kSubs) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int o = (wm * 16 + 4 * lk + r) * (TN + 1) + wn * 16 + li;
+        const int o = (wb * TM + wm * 16 + 4 * lk + r) * (TN + 1) + wn * 16 + li;
         sCr[o] = totR[r];
         sCi[o] = totI[r];
       }
@@ -219,42 +250,38 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
     __syncthreads();
     float m = 0.f;
 #pragma unroll
-    for (int q = 0; q < (TM * TN) / kGThreads; ++q) {
-      const uint32_t t = (uint32_t)(tid + q * kGThreads);
-      uint32_t co = 0, lo = 0;
-#pragma unroll
-      for (int j = 0; j < kTileBits; ++j)
-        if ((t >> j) & 1u) {
-          co += cw[j];
-          lo += lw[j];
-        }
-      float2 v;
-      v.x = sCr[lo];
-      v.y = sCi[lo];
-      C[co] = v;
-      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    for (int q = 0; q < kCWrites; ++q) {
+      if (tid + q * kGThreads < kTileElems) {
+        float2 v;
+        v.x = sCr[s_loc[q]];
+        v.y = sCi[s_loc[q]];
+        C[c_loc[q]] = v;
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+      }
     }
     if (g.c_exp_base >= 0) {
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
       const int slot = g.c_exp_base + (int)pt * g.c_exp_pt + (int)sb * g.c_exp_sb;
       if (lane == 0) atomicMax(maxbits + slot, __float_as_uint(m));
-      if (tid == 0 && bb == 0 && mt == 0 && nt == 0) exps[slot] = eacc;
+      if (tid == 0 && bt == 0 && mt == 0 && nt == 0) exps[slot] = eacc;
     }
     __syncthreads();  // sC is rewritten by the next tile
   }
 }
 
-template <int TM, int TN>
+template <int TB, int LM, int LN>
 hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream) {
-  const uint64_t n_tiles = ((uint64_t)g.n_items << g.nb) * ((1ull << g.nm) / TM) * ((1ull << g.nn) / TN);
+  const uint64_t n_tiles = ((uint64_t)g.n_items << (g.nb - TB)) << ((g.nm - LM) + (g.nn - LN));
   if (n_tiles == 0) return hipSuccess;
   // short-K products get several tiles per workgroup (their setup is a
   // large part of a tile's work); keep >= 16K workgroups in flight
-  const uint32_t tpb = g.nk <= 5 ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, n_tiles / 16384)) : 1u;
-  const uint64_t grid = (n_tiles + tpb - 1) / tpb;
+  // about 4K workgroups stride over the tiles, so the per-thread setup is
+  // paid once per workgroup
+  const uint64_t grid = std::min<uint64_t>(n_tiles, 4096);
+  const uint32_t tpb = (uint32_t)((n_tiles + grid - 1) / grid);
   if (grid > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm<TM, TN>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps, maxbits, tpb,
+  hipLaunchKernelGGL((k_gemm<TB, LM, LN>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps, maxbits, tpb,
                      n_tiles);
   return hipGetLastError();
 }
@@ -262,12 +289,19 @@ hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream
 }  // namespace
 
 hipError_t launch_gemm(const DevGemm& g, bool scaled, int* exps, uint32_t* maxbits, hipStream_t stream) {
-  if (!scaled || g.nm < 4 || g.nn < 4 || g.nk < 3) return hipErrorInvalidValue;
-  const bool m32 = g.nm >= 5, n32 = g.nn >= 5;
-  if (m32 && n32) return go<32, 32>(g, exps, maxbits, stream);
-  if (m32) return go<32, 16>(g, exps, maxbits, stream);
-  if (n32) return go<16, 32>(g, exps, maxbits, stream);
-  return go<16, 16>(g, exps, maxbits, stream);
+  if (!scaled || g.nm < 4 || g.nn < 4 || g.nk < 3 || g.tb > g.nb || g.tm > g.nm || g.tn > g.nn)
+    return hipErrorInvalidValue;
+  switch (g.tb * 100 + g.tm * 10 + g.tn) {
+    case 55: return go<0, 5, 5>(g, exps, maxbits, stream);
+    case 154: return go<1, 5, 4>(g, exps, maxbits, stream);
+    case 145: return go<1, 4, 5>(g, exps, maxbits, stream);
+    case 244: return go<2, 4, 4>(g, exps, maxbits, stream);
+    case 54: return go<0, 5, 4>(g, exps, maxbits, stream);
+    case 45: return go<0, 4, 5>(g, exps, maxbits, stream);
+    case 144: return go<1, 4, 4>(g, exps, maxbits, stream);
+    case 44: return go<0, 4, 4>(g, exps, maxbits, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace qt

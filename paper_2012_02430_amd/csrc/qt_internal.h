@@ -322,6 +322,7 @@ struct DevGemm {
   int32_t a_exp_base, a_exp_pt, a_exp_sb;  // -1 base: unscaled (a leaf)
   int32_t b_exp_base, b_exp_pt, b_exp_sb;
   int32_t c_exp_base, c_exp_pt, c_exp_sb;
+  int32_t tb, tm, tn;      // tile bits of the b, m, n counters (chosen on the host)
   int32_t pad;
   GMap a_b, a_m, a_k, b_b, b_n, b_k, c_b, c_m, c_n;
 };

@@ -758,6 +758,42 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
   if (!covers({&g.a_b, &g.a_m, &g.a_k}, g.nb + g.nm + g.nk, ra) || !covers({&g.b_b, &g.b_n, &g.b_k}, g.nb + g.nn + g.nk, rb) ||
       !covers({&g.c_b, &g.c_m, &g.c_n}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3)
     return fail(QT_EPLAN, "internal: GEMM operand maps do not tile their tensors");
+  // Tile shape: (batch, m, n) tile bits with four 16 x 16 sub-tiles where
+  // possible.  A short-K product is output-bound: prefer the shape whose
+  // bits cover the longest run of C's low storage bits (a contiguous output
+  // block per tile).  A long-K product is operand-bound: prefer the largest
+  // m x n tile (most reuse of each loaded element), then the output run.
+  std::vector<char> kind(vc.size());  // counter of each C storage bit, with its index
+  std::vector<int> idx(vc.size());
+  for (size_t q = 0; q < vc.size(); ++q) {
+    auto at = [&](const std::vector<int32_t>& v) { return (int)(std::find(v.begin(), v.end(), vc[q]) - v.begin()); };
+    if (has(cb, vc[q])) kind[q] = 'b', idx[q] = at(cb);
+    else if (has(cm, vc[q])) kind[q] = 'm', idx[q] = at(cm);
+    else kind[q] = 'n', idx[q] = at(cn);
+  }
+  const int shapes[8][3] = {{0, 5, 5}, {1, 5, 4}, {1, 4, 5}, {2, 4, 4}, {0, 5, 4}, {0, 4, 5}, {1, 4, 4}, {0, 4, 4}};
+  int best = -1, best_run = -1, best_subs = 0;
+  for (int s = 0; s < 8; ++s) {
+    const int tb = shapes[s][0], tm = shapes[s][1], tn = shapes[s][2];
+    if (tb > g.nb || tm > g.nm || tn > g.nn) continue;
+    int run = 0;
+    while (run < (int)vc.size()) {
+      const char k = kind[run];
+      const int lim = k == 'b' ? tb : (k == 'm' ? tm : tn);
+      if (idx[run] >= lim) break;
+      ++run;
+    }
+    const int subs = 1 << (tb + tm + tn - 8);
+    if (g.nk > 5) run += 64 * (tm + tn);  // reuse first
+    if (run > best_run || (run == best_run && subs > best_subs)) {
+      best = s;
+      best_run = run;
+      best_subs = subs;
+    }
+  }
+  g.tb = shapes[best][0];
+  g.tm = shapes[best][1];
+  g.tn = shapes[best][2];
   return QT_OK;
 }
 

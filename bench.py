@@ -28,7 +28,7 @@ METRIC = "QAOA amplitudes/s and edge-energies/s vs plain complex128 path at stat
 HBM_PEAK_GBS = 8000.0
 
 
-def build_plan(precision, slice_batch=0, plain=False, fold=False):
+def build_plan(precision, slice_batch=0, plain=False, fold=False, graph=False):
     from paper_2012_02430_amd import api
     from paper_2012_02430_amd import network as N
     from workloads import regular_graph
@@ -38,7 +38,7 @@ def build_plan(precision, slice_batch=0, plain=False, fold=False):
     net = api.Network(N.amplitude_network(n, edges, p))
     sch = net.plan_slicing(k, algo="min_fill")
     plan = api.Plan(net, sch.order, sch.groups, precision=precision, slice_batch=slice_batch, plain=plain,
-                    fold_prefix=fold)
+                    fold_prefix=fold, graph=graph)
     return net, sch, plan, edges
 
 
@@ -397,6 +397,23 @@ def main():
     plain_value = args.plain_steps / el_plain
     print(f"[bench] plain c128 path: {plain_value:.2f} amplitudes/s", flush=True)
 
+    # the same contraction replayed from a captured graph (device-resident inputs and outputs)
+    _, _, gplan, _ = build_plan("c64", fold=True, graph=True)
+    gplan.set_tuning(tuning["lds_waves"], tuning["lds_max_rank"])
+    g2 = g_dev.reshape(1, -1)
+    b2 = b_dev.reshape(1, -1)
+    o2 = torch.zeros(1, 3, dtype=torch.float64, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        gplan.contract_device(g2, b2, o2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gplan.contract_device(g2, b2, o2)
+    torch.cuda.synchronize()
+    graph_value = args.steps / (time.perf_counter() - t0)
+    graph_err = abs(api.amp_to_complex(*o2[0].tolist()) - want) / abs(want)
+    print(f"[bench] graph replay: {graph_value:.1f} amplitudes/s, rel err {graph_err:.2e}", flush=True)
+
     # per-kernel-class HIP-event timings over the same number of steps
     plan.profile_enable(True)
     time_calls(plan, g_dev, b_dev, out_dev, stream, args.steps, 0)
@@ -467,6 +484,7 @@ def main():
         "plain_c128": {"value": plain_value, "unit": "amplitudes/s", "rel_err_vs_oracle": err_plain,
                        "launches_per_amplitude": plain.info().n_launches},
         "speedup_vs_plain_c128": value / plain_value,
+        "graph_replay": {"value": graph_value, "unit": "amplitudes/s", "rel_err_vs_oracle": graph_err},
         "launches_per_amplitude": inf.n_launches,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

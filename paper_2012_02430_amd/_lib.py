@@ -66,6 +66,7 @@ class qt_plan_desc(ctypes.Structure):
 
 QT_PLAN_PLAIN = 1
 QT_PLAN_FOLD_PREFIX = 2
+QT_PLAN_GRAPH = 4
 
 
 class qt_amp(ctypes.Structure):

@@ -119,7 +119,7 @@ class Plan:
     """A compiled plan (``qt_load_plan``) over a loaded network."""
 
     def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False,
-                 fold_prefix=False):
+                 fold_prefix=False, graph=False):
         lib = L.load()
         self.network = network
         groups = list(groups)
@@ -135,12 +135,14 @@ class Plan:
                            ctypes.cast(lens, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(sv, ctypes.POINTER(ctypes.c_int32)),
                            PRECISIONS[precision], int(slice_batch),
-                           (L.QT_PLAN_PLAIN if plain else 0) | (L.QT_PLAN_FOLD_PREFIX if fold_prefix else 0))
+                           (L.QT_PLAN_PLAIN if plain else 0) | (L.QT_PLAN_FOLD_PREFIX if fold_prefix else 0)
+                           | (L.QT_PLAN_GRAPH if graph else 0))
         h = ctypes.c_void_p()
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
         self.p = network.spec.p
         self.slice_batch, self.plain, self.fold_prefix = int(slice_batch), bool(plain), bool(fold_prefix)
+        self.graph = bool(graph)
 
     def signature(self) -> str:
         """Shape signature (network structure, order, slicing, precision, flags): the autotuner's cache key."""
@@ -211,6 +213,21 @@ class Plan:
         L.check(L.load().qt_contract_amplitude(self.handle, g.ctypes.data, b.ctypes.data, ctypes.byref(out),
                                                stream or 0))
         return amp_to_complex(out.re, out.im, out.log2_scale)
+
+    def contract_device(self, gammas, betas, out, per_slice=None, slice_begin=0, slice_end=None, stream=None):
+        """Device-resident call: gammas/betas float64 GPU tensors [n_points, p]; out a float64 GPU tensor
+        [n_points, 3] (re, im, log2 scale); per_slice optional [n_points, n_range, 3].  With graph=True the
+        launch sequence is captured on the first call and replayed on later ones."""
+        import torch
+
+        n_points = out.shape[0]
+        end = self.n_slices if slice_end is None else slice_end
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        arr = (ctypes.c_void_p * 1)(self.handle.value)
+        L.check(L.load().qt_contract_batch(arr, 1, n_points, gammas.data_ptr() if self.p else None,
+                                           betas.data_ptr() if self.p else None, slice_begin, end,
+                                           ctypes.c_void_p(out.data_ptr()),
+                                           per_slice.data_ptr() if per_slice is not None else None, s))
 
     def contract_batch(self, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
         """Partial sums over a slice range at every point; optional per-slice values.

@@ -443,6 +443,9 @@ struct qt_plan {
   std::unique_ptr<Profile> prof;
   struct Workspace;
   std::unique_ptr<Workspace> ws;
+  // QT_PLAN_GRAPH: instantiated launch sequences, by call signature
+  struct Graphs;
+  std::unique_ptr<Graphs> graphs;
   qt_plan();
   ~qt_plan();
 };

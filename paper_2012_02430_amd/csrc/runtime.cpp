@@ -3,6 +3,7 @@
 // the per-slice steps batched over slices (the loop over ranks becomes a
 // batch dimension), per-slice scalars, and the FP64 sum over slices.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -36,6 +37,11 @@ int env_int(const char* name, int dflt) {
 }
 
 int tuned(int32_t value, const char* env, int dflt) { return value > 0 ? value : env_int(env, dflt); }
+
+uint64_t next_ws_gen() {
+  static std::atomic<uint64_t> g{1};
+  return g++;
+}
 
 bool is_device_ptr(const void* p) {
   hipPointerAttribute_t a;
@@ -128,6 +134,7 @@ struct qt_plan::Workspace {
   double* sums = nullptr;
   int64_t bytes = 0;
   int64_t n_exp = 0, exp1_base = 0, exp1_count = 0;
+  uint64_t gen = 0;  // changes whenever device buffers are (re)allocated
   std::vector<DevStep> steps;
   std::vector<DevGemm> gemms;  // per step (used by GEMM steps only)
   std::vector<int64_t> step_elems;
@@ -233,6 +240,26 @@ struct qt_plan::Profile {
     (void)drain();
     for (auto e : pool) (void)hipEventDestroy(e);
   }
+};
+
+struct qt_plan::Graphs {
+  struct Entry {
+    int np;
+    int64_t begin, end;
+    const void *g, *b, *out, *per_slice;
+    uint64_t gen;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Entry> entries;
+  void clear() {
+    for (auto& e : entries) {
+      (void)hipGraphExecDestroy(e.exec);
+      (void)hipGraphDestroy(e.graph);
+    }
+    entries.clear();
+  }
+  ~Graphs() { clear(); }
 };
 
 qt_plan::qt_plan() = default;
@@ -822,6 +849,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     ws.release();
     ws.np = np;
     ws.chunk = chunk;
+    ws.gen = next_ws_gen();
     int64_t& b = ws.bytes;
     QT_TRY(dev_alloc((char**)&ws.leaves, (int64_t)plan.leaf_block * np * elt, b));
     QT_TRY(dev_alloc((char**)&ws.arena0, std::max<int64_t>(1, ws.arena0_units) * np * elt, b));
@@ -901,6 +929,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     plan.info.slice_batch = chunk;
   }
   if (ws.per_slice_cap < (int64_t)np * n_range) {
+    ws.gen = next_ws_gen();
     if (ws.per_slice) (void)hipFree(ws.per_slice);
     ws.per_slice = nullptr;
     ws.per_slice_cap = 0;
@@ -1057,6 +1086,73 @@ qt_status run_plan_points(qt_plan& plan, int np, const double* gammas, const dou
 }
 }  // namespace qt
 
+namespace qt {
+namespace {
+
+// Enqueues one plan's full contraction and its result copies on `stream`
+// (all pointers device memory: nothing here waits on the host).
+qt_status enqueue_device(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin,
+                         int64_t end, qt_amp* out, double* per_slice_out, hipStream_t stream) {
+  const int64_t n_range = end - begin;
+  QT_TRY(run_plan(plan, np, gammas, betas, begin, end, end, stream));
+  auto& ws = *plan.ws;
+  if (per_slice_out) {
+    const size_t row = (size_t)n_range * 3 * sizeof(double);
+    QT_TRY(copy_2d(per_slice_out, row, ws.per_slice, row, row, np, stream));
+  }
+  const size_t bytes = (size_t)np * sizeof(qt_amp);
+  return copy_2d(out, bytes, ws.sums, bytes, bytes, 1, stream);
+}
+
+// Capture on first use (per parameters/results addresses, batch shape and
+// workspace generation), then replay.  The workspace is allocated before
+// capture, so the graph holds kernels and device-to-device copies only.
+qt_status contract_graph(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
+                         qt_amp* out, double* per_slice_out, hipStream_t stream) {
+  QT_TRY(ensure_workspace(plan, np, end - begin));
+  if (!plan.graphs) plan.graphs = std::make_unique<qt_plan::Graphs>();
+  const uint64_t gen = plan.ws->gen;
+  qt_plan::Graphs::Entry* hit = nullptr;
+  for (auto& e : plan.graphs->entries)
+    if (e.np == np && e.begin == begin && e.end == end && e.g == gammas && e.b == betas && e.out == out &&
+        e.per_slice == per_slice_out && e.gen == gen)
+      hit = &e;
+  if (!hit) {
+    if (plan.graphs->entries.size() >= 8) plan.graphs->clear();
+    hipStream_t cs = nullptr;
+    QT_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool prof = plan.prof && plan.prof->enabled;
+    if (prof) plan.prof->enabled = false;  // no event nodes in the graph
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    qt_status st = QT_OK;
+    if (e == hipSuccess) {
+      st = enqueue_device(plan, np, gammas, betas, begin, end, out, per_slice_out, cs);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (prof) plan.prof->enabled = true;
+    (void)hipStreamDestroy(cs);
+    if (st != QT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(QT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(QT_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    }
+    plan.graphs->entries.push_back({np, begin, end, gammas, betas, out, per_slice_out, gen, graph, exec});
+    hit = &plan.graphs->entries.back();
+  }
+  QT_HIP_CHECK(hipGraphLaunch(hit->exec, stream));
+  return QT_OK;
+}
+
+}  // namespace
+}  // namespace qt
+
 extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_points,
                                        const double* gammas, const double* betas, int64_t slice_begin,
                                        int64_t slice_end, qt_amp* out, double* per_slice_out, void* hip_stream) {
@@ -1084,6 +1180,12 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
       }
     }
     const int64_t n_range = slice_end - slice_begin;
+    // QT_PLAN_GRAPH: replay an instantiated capture of the whole sequence
+    // (device-resident parameters and results only)
+    if (n_plans == 1 && (plans[0]->flags & QT_PLAN_GRAPH) && !injected &&
+        (p == 0 || (is_device_ptr(gammas) && is_device_ptr(betas))) && is_device_ptr(out) &&
+        (!per_slice_out || is_device_ptr(per_slice_out)))
+      return contract_graph(*plans[0], n_points, gammas, betas, slice_begin, slice_end, out, per_slice_out, stream);
     for (int i = 0; i < n_plans; ++i) {
       qt_plan& plan = *plans[i];
       if (stop > slice_begin) QT_TRY(run_plan(plan, n_points, gammas, betas, slice_begin, slice_end, stop, stream));
@@ -1129,7 +1231,10 @@ extern "C" qt_status qt_plan_set_tuning(qt_plan* plan, const qt_tuning* t) {
     return fail(QT_EINVAL, "qt_plan_set_tuning: lds_max_rank must be 0 or 6..16");
   const bool reschedule = t->lds_waves != plan->tuning.lds_waves || t->lds_max_rank != plan->tuning.lds_max_rank;
   plan->tuning = *t;
-  if (reschedule) plan->ws.reset();
+  if (reschedule) {
+    if (plan->graphs) plan->graphs->clear();
+    plan->ws.reset();
+  }
   return QT_OK;
 }
 

@@ -139,16 +139,10 @@ typedef struct {
  *     one launch per step per slice.
  *   QT_PLAN_FOLD_PREFIX: run the serial prefix inside every slice with the
  *     slice variables already fixed (same order, same per-slice values),
- *     instead of once before the slices. */
-/* Plan flags:
- *   QT_PLAN_PLAIN        every bucket step its own launch per slice item (the
- *                        plain baseline path);
- *   QT_PLAN_FOLD_PREFIX  the serial prefix runs inside each slice with the
- *                        slice variables already fixed (same values);
- *   QT_PLAN_GRAPH        when parameters and results are device memory,
- *                        qt_contract_batch captures the launch sequence as a
- *                        HIP graph on first use (per addresses and batch
- *                        shape) and replays it afterwards. */
+ *     instead of once before the slices.
+ *   QT_PLAN_GRAPH: when parameters and results are device memory,
+ *     qt_contract_batch captures the launch sequence as a HIP graph on first
+ *     use (per addresses and batch shape) and replays it afterwards. */
 enum { QT_PLAN_PLAIN = 1, QT_PLAN_FOLD_PREFIX = 2, QT_PLAN_GRAPH = 4 };
 
 typedef struct {

@@ -143,8 +143,15 @@ def energy_bench(steps, warmup, cpu_seconds, waves=0):
         oracle.edge_energy(n, edges, gs[0], bs[0], u, v)
         done += 1
     cpu_rate = done / (time.perf_counter() - t0)
+    # roofline of the lightcone launch: algorithmic bytes = sum over lightcones of their steps'
+    # 8 B x (inputs + output) elements, per point
+    alg = sum(pl.info().prefix_bytes for pl in model.plans) * npt
+    roof = {"bound": "hbm", "kernel": "k_lds_multi (whole evaluation)", "achieved": alg / el / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / el / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": alg, "traffic": None}
     return {
         "metric": "edge-energies/s",
+        "roofline": roof,
         "workload": "QAOA p=3 MaxCut energy, seeded random 3-regular graph n=1000: 1500 per-edge lightcone "
                     "networks x 32 seeded points per evaluation, one batched launch, complex64, FP64 edge sums",
         "value": rate,
@@ -212,8 +219,14 @@ def gradient_bench(steps, warmup, cpu_seconds, grad_waves=0, multi_waves=0):
         oracle.edge_energy_grad(n, edges, gs[0], bs[0], u, v)
         done += 1
     cpu_rate = done / (time.perf_counter() - t0)
+    alg = sum(pl.info().prefix_bytes for pl in model.plans) * npt
+    roof = {"bound": "hbm", "kernel": "k_lds_grad (whole evaluation)",
+            "achieved": alg / el / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg / el / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg,
+            "note": "forward-step bytes only (a lower bound of the adjoint's)", "traffic": None}
     return {
         "metric": "edge-gradients/s",
+        "roofline": roof,
         "workload": "dE/dgamma, dE/dbeta of QAOA p=2 MaxCut energy, seeded random 3-regular graph n=200: 300 "
                     "lightcone networks x 64 seeded points per evaluation, forward + adjoint in one launch, "
                     "complex64, FP64 reductions",
@@ -265,6 +278,8 @@ def mfma_bench():
     err = float(np.max(np.abs(per_f[0, :4] - per_p[0]) / np.abs(per_p[0])))
     err_u = float(np.max(np.abs(per_u[0, :4] - per_p[0]) / np.abs(per_p[0])))
     gemm = prof.get("gemm", (0, 0.0, 0.0, 0.0))
+    st = prof.get("step_stream", (0, 0.0, 0.0, 0.0))
+    stream_gbs = st[2] / st[1] / 1e6 if st[1] else 0.0
     gemms = [s for s in fused.describe()["stream_steps"] if "gemm" in s]
     return {
         "metric": "slices/s",
@@ -278,6 +293,13 @@ def mfma_bench():
                          for s in gemms],
         "gemm_kernel": {"launches": gemm[0], "ms": gemm[1], "TFLOP/s": gemm[3] / gemm[1] / 1e9 if gemm[1] else 0,
                         "GB/s": gemm[2] / gemm[1] / 1e6 if gemm[1] else 0, "peak_TFLOP/s": 157.3},
+        "roofline": {
+            "gemm": {"bound": "mfma", "achieved": gemm[3] / gemm[1] / 1e9 if gemm[1] else 0, "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": (gemm[3] / gemm[1] / 1e9 / 157.3) if gemm[1] else 0,
+                     "hbm_GB/s": gemm[2] / gemm[1] / 1e6 if gemm[1] else 0, "traffic": None},
+            "streaming": {"bound": "hbm", "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": stream_gbs / HBM_PEAK_GBS, "traffic": None},
+        },
         "kernel_classes_ms": {k: round(v[1], 2) for k, v in prof.items()},
         "unfused_c64": {"value": 256 / el_u, "unit": "slices/s"},
         "plain_c128": {"value": 4 / el_p, "unit": "slices/s", "sample": "slices 0-3"},

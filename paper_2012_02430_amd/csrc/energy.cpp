@@ -549,6 +549,10 @@ struct EnergyJob {
   double* gsum = nullptr;    // [np][2p]
   XMulti multi{};
   int n_fit = 0;
+  struct Class {
+    int off = 0, count = 0, lds_elems = 0, n_slots = 0, n_recs = 0;  // items [off, off + count) of the order
+  };
+  std::vector<Class> classes;
   char* scratch = nullptr;          // gradient programs run from global memory
   std::vector<GlobalProg> global;
   std::vector<int> big;  // programs that do not fit in LDS
@@ -655,8 +659,41 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
       job.big.push_back(e);
     }
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return progs[a].cost > progs[b].cost; });
+  // One launch per LDS size class (powers of two of the workgroup's LDS
+  // bytes), each sized for its largest member, so small lightcones are not
+  // held to the occupancy of the largest; within a class, longest first.
+  auto smem_of = [&](int e) {
+    const Program& pg = progs[e];
+    return grad ? lds_grad_smem_bytes(pg.n_slots, pg.n_recs, pg.lds_elems, elt == 16)
+                : lds_exec_smem_bytes(pg.n_slots, pg.lds_elems, elt == 16);
+  };
+  auto class_of = [&](int e) {
+    int c = 14;  // up to 16 KiB: the wavefront count, not LDS, bounds occupancy
+    while ((size_t(1) << c) < smem_of(e)) ++c;
+    return c;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ca = class_of(a), cb = class_of(b);
+    if (ca != cb) return ca < cb;
+    return progs[a].cost > progs[b].cost;
+  });
   job.n_fit = (int)order.size();
+  for (size_t i = 0; i < order.size();) {
+    size_t j = i;
+    EnergyJob::Class cl;
+    cl.off = (int)i;
+    const int c = class_of(order[i]);
+    while (j < order.size() && class_of(order[j]) == c) {
+      const Program& pg = progs[order[j]];
+      cl.lds_elems = std::max(cl.lds_elems, pg.lds_elems);
+      cl.n_slots = std::max(cl.n_slots, pg.n_slots);
+      cl.n_recs = std::max(cl.n_recs, pg.n_recs);
+      ++j;
+    }
+    cl.count = (int)(j - i);
+    job.classes.push_back(cl);
+    i = j;
+  }
   auto pad = [](size_t b) { return (b + 255) & ~(size_t)255; };
   struct Part {
     const void* src;
@@ -734,6 +771,9 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
                  grad ? lds_grad_smem_bytes(max_slots, max_recs, max_lds, elt == 16)
                       : lds_exec_smem_bytes(max_slots, max_lds, elt == 16),
                  (int)job.global.size());
+  if (env_int("QT_DEBUG_GRAD_SCHEDULE", 0))
+    for (const auto& cl : job.classes)
+      std::fprintf(stderr, "[qt grad] class: %d programs, %d LDS elements\n", cl.count, cl.lds_elems);
   return QT_OK;
 }
 
@@ -803,11 +843,15 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
     const qt_tuning& tu = lightcones[0]->tuning;
     const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 2)
                                                                     : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 4)));
-    if (job->n_fit) {
+    for (const auto& cl : job->classes) {
       XMulti m = job->multi;
-      m.n_progs = n_edges;  // output row length; items cover the fitting programs only
-      if (grad) QT_HIP_CHECK(launch_lds_grad(m, job->n_fit, waves, c128, !c128, stream));
-      else QT_HIP_CHECK(launch_lds_multi(m, job->n_fit, waves, c128, !c128, stream));
+      m.n_progs = n_edges;  // output row length; items cover the class's programs only
+      m.item_prog = job->multi.item_prog + cl.off;
+      m.lds_elems = cl.lds_elems;
+      m.n_slots = cl.n_slots;
+      m.n_recs = cl.n_recs;
+      if (grad) QT_HIP_CHECK(launch_lds_grad(m, cl.count, waves, c128, !c128, stream));
+      else QT_HIP_CHECK(launch_lds_multi(m, cl.count, waves, c128, !c128, stream));
     }
     for (const GlobalProg& gp : job->global) {
       XMulti m = job->multi;

@@ -50,9 +50,13 @@ using gmut_t = __attribute__((address_space(1))) XRaw<E>*;
 template <int N>
 __device__ __forceinline__ uint32_t xpext_all(uint32_t x, const uint8_t (&lo)[N], const uint8_t (&len)[N],
                                               const uint8_t (&dst)[N]) {
+  // runs are packed from index 0; the first empty one ends the list (a
+  // uniform branch: the tables are wavefront-uniform)
   uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r |= ((x >> lo[i]) & ((1u << len[i]) - 1u)) << dst[i];
+  for (int i = 0; i < N; ++i) {
+    if (len[i] == 0) break;
+    r |= ((x >> lo[i]) & ((1u << len[i]) - 1u)) << dst[i];
+  }
   return r;
 }
 

@@ -148,43 +148,67 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
     s_loc[q] = lo;
   }
 
+  // A workgroup takes a contiguous range of tiles, n tile fastest.  The
+  // counter maps are monotone bit deposits, so stepping the n tile advances
+  // the n parts of the B and C offsets by one masked increment each
+  // ((x | ~M) + 1) & M; the rest is recomputed when the n tile wraps.
+  const uint32_t mbn = gmap(g.b_n, ((1u << g.nn) - 1u) & ~(uint32_t)(TN - 1));
+  const uint32_t mcn = gmap(g.c_n, ((1u << g.nn) - 1u) & ~(uint32_t)(TN - 1));
+  const uint64_t first = (uint64_t)blockIdx.x * tiles_per_block;
+  uint32_t nt = 0, mt = 0, bt = 0, item = 0, sb = 0, pt = 0;
+  uint32_t bn = 0, cn = 0;
+  float sa = 1.f, sbs = 1.f;
+  int eacc = 0;
+  const float2* A = nullptr;
+  const float2* Bb = nullptr;
+  float2* Cb = nullptr;
   for (uint32_t it = 0; it < tiles_per_block; ++it) {
-    const uint64_t tile_id = (uint64_t)blockIdx.x + (uint64_t)it * gridDim.x;  // grid-strided
+    const uint64_t tile_id = first + it;
     if (tile_id >= n_tiles) break;
-    // tile -> (n tile, m tile, batch tile, item), n tile fastest
-    uint64_t bid = tile_id;
-    const uint32_t nt = (uint32_t)(bid % n_nt);
-    bid /= n_nt;
-    const uint32_t mt = (uint32_t)(bid % n_mt);
-    bid /= n_mt;
-    const uint32_t bt = (uint32_t)(bid % n_bt);
-    const uint32_t item = (uint32_t)(bid / n_bt);
-    const uint32_t sb = item & ((1u << g.lg_nsb) - 1u);
-    const uint32_t pt = item >> g.lg_nsb;
-    const uint64_t sid = (uint64_t)g.chunk_base + sb;
-    const uint32_t b0 = bt * NB;
-
-    const float2* A = reinterpret_cast<const float2*>(g.a) + (int64_t)pt * g.a_pt + (int64_t)sb * g.a_sb +
-                      ((int64_t)gpext(sid, g.a_smask) << g.a_slow) + gmap(g.a_b, b0) + gmap(g.a_m, mt * TM);
-    const float2* B = reinterpret_cast<const float2*>(g.b) + (int64_t)pt * g.b_pt + (int64_t)sb * g.b_sb +
-                      ((int64_t)gpext(sid, g.b_smask) << g.b_slow) + gmap(g.b_b, b0) + gmap(g.b_n, nt * TN);
-    float2* C = reinterpret_cast<float2*>(g.c) + (int64_t)pt * g.c_pt + (int64_t)sb * g.c_sb + gmap(g.c_b, b0) +
-                gmap(g.c_m, mt * TM) + gmap(g.c_n, nt * TN);
-
-    float sa = 1.f, sbs = 1.f;
-    int eacc = 0;
-    if (g.a_exp_base >= 0) {
-      const int slot = g.a_exp_base + (int)pt * g.a_exp_pt + (int)sb * g.a_exp_sb;
-      const int sh = gshift(maxbits[slot]);
-      sa = __int_as_float((127 - sh) << 23);
-      eacc += exps[slot] + sh;
+    if (it == 0 || nt + 1 == n_nt) {
+      // tile -> (n tile, m tile, batch tile, item)
+      uint64_t bid = tile_id;
+      nt = (uint32_t)(bid % n_nt);
+      bid /= n_nt;
+      mt = (uint32_t)(bid % n_mt);
+      bid /= n_mt;
+      bt = (uint32_t)(bid % n_bt);
+      item = (uint32_t)(bid / n_bt);
+      sb = item & ((1u << g.lg_nsb) - 1u);
+      pt = item >> g.lg_nsb;
+      const uint64_t sid = (uint64_t)g.chunk_base + sb;
+      const uint32_t b0 = bt * NB;
+      A = reinterpret_cast<const float2*>(g.a) + (int64_t)pt * g.a_pt + (int64_t)sb * g.a_sb +
+          ((int64_t)gpext(sid, g.a_smask) << g.a_slow) + gmap(g.a_b, b0) + gmap(g.a_m, mt * TM);
+      Bb = reinterpret_cast<const float2*>(g.b) + (int64_t)pt * g.b_pt + (int64_t)sb * g.b_sb +
+           ((int64_t)gpext(sid, g.b_smask) << g.b_slow) + gmap(g.b_b, b0);
+      Cb = reinterpret_cast<float2*>(g.c) + (int64_t)pt * g.c_pt + (int64_t)sb * g.c_sb + gmap(g.c_b, b0) +
+           gmap(g.c_m, mt * TM);
+      bn = gmap(g.b_n, nt * TN);
+      cn = gmap(g.c_n, nt * TN);
+      // operand scales of the item
+      sa = 1.f;
+      sbs = 1.f;
+      eacc = 0;
+      if (g.a_exp_base >= 0) {
+        const int slot = g.a_exp_base + (int)pt * g.a_exp_pt + (int)sb * g.a_exp_sb;
+        const int sh = gshift(maxbits[slot]);
+        sa = __int_as_float((127 - sh) << 23);
+        eacc += exps[slot] + sh;
+      }
+      if (g.b_exp_base >= 0) {
+        const int slot = g.b_exp_base + (int)pt * g.b_exp_pt + (int)sb * g.b_exp_sb;
+        const int sh = gshift(maxbits[slot]);
+        sbs = __int_as_float((127 - sh) << 23);
+        eacc += exps[slot] + sh;
+      }
+    } else {
+      ++nt;
+      bn = ((bn | ~mbn) + 1u) & mbn;
+      cn = ((cn | ~mcn) + 1u) & mcn;
     }
-    if (g.b_exp_base >= 0) {
-      const int slot = g.b_exp_base + (int)pt * g.b_exp_pt + (int)sb * g.b_exp_sb;
-      const int sh = gshift(maxbits[slot]);
-      sbs = __int_as_float((127 - sh) << 23);
-      eacc += exps[slot] + sh;
-    }
+    const float2* B = Bb + bn;
+    float2* C = Cb + cn;
 
     v4f totR = {0.f, 0.f, 0.f, 0.f}, totI = {0.f, 0.f, 0.f, 0.f};  // running sums
     v4f cmpR = {0.f, 0.f, 0.f, 0.f}, cmpI = {0.f, 0.f, 0.f, 0.f};  // their compensations
@@ -276,10 +300,10 @@ hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream
   if (n_tiles == 0) return hipSuccess;
   // short-K products get several tiles per workgroup (their setup is a
   // large part of a tile's work); keep >= 16K workgroups in flight
-  // about 4K workgroups stride over the tiles, so the per-thread setup is
-  // paid once per workgroup
-  const uint64_t grid = std::min<uint64_t>(n_tiles, 4096);
-  const uint32_t tpb = (uint32_t)((n_tiles + grid - 1) / grid);
+  // about 4K workgroups over contiguous tile ranges, so the per-thread setup
+  // is paid once per workgroup
+  const uint32_t tpb = (uint32_t)std::max<uint64_t>(1, (n_tiles + 4095) / 4096);
+  const uint64_t grid = (n_tiles + tpb - 1) / tpb;
   if (grid > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gemm<TB, LM, LN>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps, maxbits, tpb,
                      n_tiles);

@@ -32,9 +32,16 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kGThreads = 256;
 constexpr int kTK = 16;
 
+// Unrolled with an early exit: every table read has a constant offset, so
+// the tables stay scalar kernel-argument loads (a loop-indexed read of the
+// by-value argument became dependent vector loads).
 __device__ __forceinline__ uint32_t gmap(const GMap& g, uint32_t x) {
   uint32_t r = 0;
-  for (int i = 0; i < g.n; ++i) r |= ((x >> g.lo[i]) & ((1u << g.len[i]) - 1u)) << g.dst[i];
+#pragma unroll
+  for (int i = 0; i < kGRuns; ++i) {
+    if (i >= g.n) break;
+    r |= ((x >> g.lo[i]) & ((1u << g.len[i]) - 1u)) << g.dst[i];
+  }
   return r;
 }
 
@@ -117,23 +124,55 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   // Per-thread parts of every index, the same for all tiles: maps are
   // linear over disjoint bits, so an element's offset is its in-tile part
   // plus the tile's base (uniform).  Row r of the A block is (batch r / TM,
-  // m r % TM), k part ki.
+  // m r % TM), k part ki.  A thread's elements are numbered with the block's
+  // bits sorted by their storage position, so consecutive lanes load
+  // consecutive addresses wherever the layout allows.
   uint32_t a_loc[kALoads], a_ki[kALoads], b_loc[kBLoads], b_ki[kBLoads], c_loc[kCWrites], s_loc[kCWrites];
   int a_r[kALoads], b_r[kBLoads];
-#pragma unroll
-  for (int q = 0; q < kALoads; ++q) {
-    const int e = tid + q * kGThreads;
-    a_r[q] = e / tk;
-    a_ki[q] = (uint32_t)(e % tk);
-    a_loc[q] = gmap(g.a_b, (uint32_t)a_r[q] / TM) + gmap(g.a_m, (uint32_t)a_r[q] % TM) + gmap(g.a_k, a_ki[q]);
-  }
-#pragma unroll
-  for (int q = 0; q < kBLoads; ++q) {
-    const int e = tid + q * kGThreads;
-    b_r[q] = e / tk;
-    b_ki[q] = (uint32_t)(e % tk);
-    b_loc[q] = gmap(g.b_b, (uint32_t)b_r[q] / TN) + gmap(g.b_n, (uint32_t)b_r[q] % TN) + gmap(g.b_k, b_ki[q]);
-  }
+  const int lg_tk = tk == 16 ? 4 : 3;
+  auto number = [&](const GMap& mb, const GMap& mx, const GMap& mk, int lx, int nq, int rows, uint32_t* loc,
+                    uint32_t* kis, int* rs) {
+    // block bits: batch (TB), m or n (lx), k (lg_tk), each with its storage offset, row and k weights
+    constexpr int kMaxBits = 2 + 5 + 4;
+    uint32_t off[kMaxBits], rw[kMaxBits], kw[kMaxBits];
+    const int nbits = TB + lx + lg_tk;
+    for (int i = 0; i < nbits; ++i) {
+      if (i < TB) {
+        off[i] = gmap(mb, 1u << i);
+        rw[i] = (1u << i) << lx;
+        kw[i] = 0;
+      } else if (i < TB + lx) {
+        off[i] = gmap(mx, 1u << (i - TB));
+        rw[i] = 1u << (i - TB);
+        kw[i] = 0;
+      } else {
+        off[i] = gmap(mk, 1u << (i - TB - lx));
+        rw[i] = 0;
+        kw[i] = 1u << (i - TB - lx);
+      }
+    }
+    for (int i = 1; i < nbits; ++i)  // by storage offset
+      for (int j = i; j > 0 && off[j - 1] > off[j]; --j) {
+        uint32_t t = off[j]; off[j] = off[j - 1]; off[j - 1] = t;
+        t = rw[j]; rw[j] = rw[j - 1]; rw[j - 1] = t;
+        t = kw[j]; kw[j] = kw[j - 1]; kw[j - 1] = t;
+      }
+    for (int q = 0; q < nq; ++q) {
+      const uint32_t e = (uint32_t)(tid + q * kGThreads);
+      uint32_t o = 0, r = 0, k = 0;
+      for (int j = 0; j < nbits; ++j)
+        if ((e >> j) & 1u) {
+          o += off[j];
+          r += rw[j];
+          k += kw[j];
+        }
+      loc[q] = o;
+      rs[q] = e < (uint32_t)(rows * tk) ? (int)r : rows;  // rows: no element
+      kis[q] = k;
+    }
+  };
+  number(g.a_b, g.a_m, g.a_k, LM, kALoads, kARows, a_loc, a_ki, a_r);
+  number(g.b_b, g.b_n, g.b_k, LN, kBLoads, kBRows, b_loc, b_ki, b_r);
 #pragma unroll
   for (int q = 0; q < kCWrites; ++q) {
     const uint32_t t = (uint32_t)(tid + q * kGThreads);
@@ -152,6 +191,8 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   // counter maps are monotone bit deposits, so stepping the n tile advances
   // the n parts of the B and C offsets by one masked increment each
   // ((x | ~M) + 1) & M; the rest is recomputed when the n tile wraps.
+  const uint32_t mak = gmap(g.a_k, (K - 1u) & ~(uint32_t)(tk - 1));  // k bits above a stage
+  const uint32_t mbk = gmap(g.b_k, (K - 1u) & ~(uint32_t)(tk - 1));
   const uint32_t mbn = gmap(g.b_n, ((1u << g.nn) - 1u) & ~(uint32_t)(TN - 1));
   const uint32_t mcn = gmap(g.c_n, ((1u << g.nn) - 1u) & ~(uint32_t)(TN - 1));
   const uint64_t first = (uint64_t)blockIdx.x * tiles_per_block;
@@ -213,8 +254,10 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
     v4f totR = {0.f, 0.f, 0.f, 0.f}, totI = {0.f, 0.f, 0.f, 0.f};  // running sums
     v4f cmpR = {0.f, 0.f, 0.f, 0.f}, cmpI = {0.f, 0.f, 0.f, 0.f};  // their compensations
     float2 va[kALoads], vb[kBLoads];
-    auto fetch = [&](uint32_t k0) {
-      const uint32_t ka = gmap(g.a_k, k0), kb = gmap(g.b_k, k0);
+    // k part of the stage base: stepping k0 by tk is a masked increment of
+    // its storage offset
+    uint32_t ka = 0, kb = 0;
+    auto fetch = [&]() {
 #pragma unroll
       for (int q = 0; q < kALoads; ++q)
         if (a_r[q] < kARows) va[q] = A[a_loc[q] + ka];
@@ -222,7 +265,7 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       for (int q = 0; q < kBLoads; ++q)
         if (b_r[q] < kBRows) vb[q] = B[b_loc[q] + kb];
     };
-    fetch(0);
+    fetch();
     for (uint32_t k0 = 0; k0 < K; k0 += (uint32_t)tk) {
 #pragma unroll
       for (int q = 0; q < kALoads; ++q)
@@ -237,7 +280,11 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
           sBi[b_r[q]][b_ki[q]] = vb[q].y * sbs;
         }
       __syncthreads();
-      if (k0 + (uint32_t)tk < K) fetch(k0 + (uint32_t)tk);  // next stage in flight during the products
+      if (k0 + (uint32_t)tk < K) {  // next stage in flight during the products
+        ka = ((ka | ~mak) + 1u) & mak;
+        kb = ((kb | ~mbk) + 1u) & mbk;
+        fetch();
+      }
       if (wave < kSubs) {
         const int ra = wb * TM + wm * 16 + li, rbw = wb * TN + wn * 16 + li;
         v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
@@ -300,9 +347,10 @@ hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream
   if (n_tiles == 0) return hipSuccess;
   // short-K products get several tiles per workgroup (their setup is a
   // large part of a tile's work); keep >= 16K workgroups in flight
-  // about 4K workgroups over contiguous tile ranges, so the per-thread setup
-  // is paid once per workgroup
-  const uint32_t tpb = (uint32_t)std::max<uint64_t>(1, (n_tiles + 4095) / 4096);
+  // short-K products: about 4K workgroups over contiguous tile ranges, so
+  // the per-thread setup is paid once per workgroup; long-K products have
+  // enough work per tile: one tile per workgroup keeps the CUs full
+  const uint32_t tpb = g.nk <= 5 ? (uint32_t)std::max<uint64_t>(1, (n_tiles + 4095) / 4096) : 1u;
   const uint64_t grid = (n_tiles + tpb - 1) / tpb;
   if (grid > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gemm<TB, LM, LN>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps, maxbits, tpb,

@@ -419,7 +419,10 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       for (int x : SA) nm += !contains(SB, x);
       for (int x : SB) nn += !contains(SA, x);
       for (int x : SA) nb += contains(SB, x) && !contains(K, x);
-      if (K.size() < 3 || nm < 4 || nn < 4 || nb + nm + nn > kMaxRank) return QT_OK;
+      const int nk = (int)K.size();
+      if (nk < 3 || nm < 4 || nn < 4 || nb + nm + nn > kGemmMaxRank || nb + nm + nk > kGemmMaxRank ||
+          nb + nn + nk > kGemmMaxRank)
+        return QT_OK;
       for (const auto& jt : vecs) {
         auto& bk = buckets[jt.first];
         bk.erase(std::find(bk.begin(), bk.end(), jt.second));

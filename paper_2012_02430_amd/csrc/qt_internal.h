@@ -297,17 +297,12 @@ struct XMulti {
 
 // Fused GEMM bucket: C[b, m, n] = sum_k A[b, m, k] B[b, n, k] over complex
 // values, for every batch item (point, slice).  The counters b, m, n, k run
-// over their variables in key order; a tensor's element index is the sum of
-// its bit maps of the counters it has (runs: source bit, length, destination
-// bit), plus the slice-selected block of a prefix tensor.
-constexpr int kGRuns = 12;
-struct GMap {
-  uint8_t lo[kGRuns];
-  uint8_t len[kGRuns];
-  uint8_t dst[kGRuns];
-  uint8_t n;
-  uint8_t pad[3];
-};
+// over their variables in key order, and every tensor stores its variables
+// in key order, so a counter's value enters a tensor's element index as a
+// monotone bit deposit into the storage bits of its variables (a mask);
+// a prefix tensor adds its slice-selected block.
+constexpr int kGBits = 16;
+constexpr int kGemmMaxRank = 28;  // per-item operand and output ranks: byte offsets below 2^31  // element-number bits of an operand stage or an output tile
 struct DevGemm {
   const void* a;
   const void* b;
@@ -323,8 +318,15 @@ struct DevGemm {
   int32_t b_exp_base, b_exp_pt, b_exp_sb;
   int32_t c_exp_base, c_exp_pt, c_exp_sb;
   int32_t tb, tm, tn;      // tile bits of the b, m, n counters (chosen on the host)
-  int32_t pad;
-  GMap a_b, a_m, a_k, b_b, b_n, b_k, c_b, c_m, c_n;
+  int32_t tk;              // K stage depth (8, 16 or 64)
+  // storage bits of each counter in each tensor
+  uint32_t a_bm, a_mm, a_km, b_bm, b_nm, b_km, c_bm, c_mm, c_nm;
+  // the same without the bits a tile or a stage covers (masked increments)
+  uint32_t a_kh, b_kh, b_nh, c_nh;
+  // Elements of one K stage's A and B blocks and of one C tile are numbered
+  // with the block's bits in storage order; bit j of an element number adds
+  // *w[j] to its storage offset and *l[j] to its LDS offset.
+  uint32_t aw[kGBits], al[kGBits], bw[kGBits], bl[kGBits], cw[kGBits], cl[kGBits];
 };
 
 // Leaf (gate) tensor materialisation record.

@@ -689,29 +689,42 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   return QT_OK;
 }
 
-// Bit map from a counter over `counter` (variables in key order) to the
-// storage bits of a tensor with variables `vars` (key order).
-bool make_gmap(const std::vector<int32_t>& counter, const std::vector<int32_t>& vars, GMap& g) {
-  std::memset(&g, 0, sizeof(g));
-  int n = 0;
-  for (size_t j = 0; j < counter.size();) {
-    const int pos = (int)(std::find(vars.begin(), vars.end(), counter[j]) - vars.begin());
-    if (pos >= (int)vars.size()) return false;
-    size_t e = j + 1;
-    while (e < counter.size() && e - j < 32) {
-      const int pe = (int)(std::find(vars.begin(), vars.end(), counter[e]) - vars.begin());
-      if (pe != pos + (int)(e - j)) break;
-      ++e;
-    }
-    if (n == kGRuns) return false;
-    g.lo[n] = (uint8_t)j;
-    g.len[n] = (uint8_t)(e - j);
-    g.dst[n] = (uint8_t)pos;
-    ++n;
-    j = e;
+// Storage bits of the counter variables `counter` (key order) in a tensor
+// with variables `vars` (key order): the counter's value enters the element
+// index as a deposit into these bits, which must keep the counter's order.
+bool counter_mask(const std::vector<int32_t>& counter, const std::vector<int32_t>& vars, uint32_t& mask) {
+  mask = 0;
+  int last = -1;
+  for (int x : counter) {
+    const int pos = (int)(std::find(vars.begin(), vars.end(), x) - vars.begin());
+    if (pos >= (int)vars.size() || pos <= last || pos >= 32) return false;
+    mask |= 1u << pos;
+    last = pos;
   }
-  g.n = (uint8_t)n;
   return true;
+}
+
+uint32_t deposit(uint32_t x, uint32_t m) {
+  uint32_t r = 0;
+  for (; m; m &= m - 1, x >>= 1)
+    if (x & 1u) r |= m & (0u - m);
+  return r;
+}
+
+// Element numbering of a block whose bits are the low `bits[i]` bits of
+// counters with storage masks `masks[i]` and LDS weights `lds[i]` (per
+// counter unit): the block's bits sorted by storage position, each with its
+// storage and LDS weight.
+void number_block(std::initializer_list<std::pair<uint32_t, std::pair<int, uint32_t>>> parts, uint32_t* w,
+                  uint32_t* l) {
+  std::vector<std::pair<uint32_t, uint32_t>> bits;  // (storage weight, LDS weight)
+  for (const auto& pt : parts)
+    for (int i = 0; i < pt.second.first; ++i) bits.emplace_back(deposit(1u << i, pt.first), (1u << i) * pt.second.second);
+  std::sort(bits.begin(), bits.end());
+  for (int j = 0; j < kGBits; ++j) {
+    w[j] = j < (int)bits.size() ? bits[j].first : 0u;
+    l[j] = j < (int)bits.size() ? bits[j].second : 0u;
+  }
 }
 
 qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const SymStep& st, int elt, int np,
@@ -761,29 +774,27 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
   g.c_exp_base = dc.exp_base;
   g.c_exp_pt = dc.exp_pt;
   g.c_exp_sb = dc.exp_sb;
-  if (!make_gmap(cb, va, g.a_b) || !make_gmap(cm, va, g.a_m) || !make_gmap(st.kvars, va, g.a_k) ||
-      !make_gmap(cb, vb, g.b_b) || !make_gmap(cn, vb, g.b_n) || !make_gmap(st.kvars, vb, g.b_k) ||
-      !make_gmap(cb, vc, g.c_b) || !make_gmap(cm, vc, g.c_m) || !make_gmap(cn, vc, g.c_n))
-    return fail(QT_EUNSUPPORTED, "GEMM operand index map has too many runs of bits");
-  // each operand's maps cover distinct bits inside its rank (below its
+  if (!counter_mask(cb, va, g.a_bm) || !counter_mask(cm, va, g.a_mm) || !counter_mask(st.kvars, va, g.a_km) ||
+      !counter_mask(cb, vb, g.b_bm) || !counter_mask(cn, vb, g.b_nm) || !counter_mask(st.kvars, vb, g.b_km) ||
+      !counter_mask(cb, vc, g.c_bm) || !counter_mask(cm, vc, g.c_mm) || !counter_mask(cn, vc, g.c_nm))
+    return fail(QT_EPLAN, "internal: GEMM counter variables are not in key order in an operand");
+  // each operand's counters cover distinct bits inside its rank (below its
   // slice bits), so every index stays in the tensor's block
-  auto covers = [](std::initializer_list<const GMap*> maps, int bits, int rank) {
-    uint64_t seen = 0;
+  auto covers = [](std::initializer_list<uint32_t> masks, int bits, int rank) {
+    uint32_t seen = 0;
     int total = 0;
-    for (const GMap* m : maps)
-      for (int i = 0; i < m->n; ++i) {
-        if (m->dst[i] + m->len[i] > rank) return false;
-        const uint64_t run = ((1ull << m->len[i]) - 1ull) << m->dst[i];
-        if (seen & run) return false;
-        seen |= run;
-        total += m->len[i];
-      }
-    return total == bits;
+    for (uint32_t m : masks) {
+      if (seen & m) return false;
+      seen |= m;
+      total += __builtin_popcount(m);
+    }
+    return total == bits && (rank >= 32 || (seen >> rank) == 0);
   };
   const int ra = st.ins[0].smask ? st.ins[0].slow : (int)va.size();
   const int rb = st.ins[1].smask ? st.ins[1].slow : (int)vb.size();
-  if (!covers({&g.a_b, &g.a_m, &g.a_k}, g.nb + g.nm + g.nk, ra) || !covers({&g.b_b, &g.b_n, &g.b_k}, g.nb + g.nn + g.nk, rb) ||
-      !covers({&g.c_b, &g.c_m, &g.c_n}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3)
+  if (!covers({g.a_bm, g.a_mm, g.a_km}, g.nb + g.nm + g.nk, ra) || !covers({g.b_bm, g.b_nm, g.b_km}, g.nb + g.nn + g.nk, rb) ||
+      !covers({g.c_bm, g.c_mm, g.c_nm}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3 ||
+      g.nb + g.nm + g.nk > kGemmMaxRank || g.nb + g.nn + g.nk > kGemmMaxRank || g.nb + g.nm + g.nn > kGemmMaxRank)
     return fail(QT_EPLAN, "internal: GEMM operand maps do not tile their tensors");
   // Tile shape: (batch, m, n) tile bits with four 16 x 16 sub-tiles where
   // possible.  A short-K product is output-bound: prefer the shape whose
@@ -821,6 +832,21 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
   g.tb = shapes[best][0];
   g.tm = shapes[best][1];
   g.tn = shapes[best][2];
+  // K stage: 64 deep for long sums (more operand bytes in flight per
+  // workgroup), else 16 (8 for K = 8)
+  g.tk = g.nk >= 6 ? 64 : (g.nk >= 4 ? 16 : 8);
+  const uint32_t pitch = (g.tk == 64 ? 64u : 16u) + 1u;  // LDS row pitch of the kernel
+  const int lg_tk = ilog2(g.tk);
+  const uint32_t TM = 1u << g.tm, TN = 1u << g.tn;
+  g.a_kh = g.a_km & ~deposit((uint32_t)g.tk - 1u, g.a_km);
+  g.b_kh = g.b_km & ~deposit((uint32_t)g.tk - 1u, g.b_km);
+  g.b_nh = g.b_nm & ~deposit(TN - 1u, g.b_nm);
+  g.c_nh = g.c_nm & ~deposit(TN - 1u, g.c_nm);
+  // LDS: operand row r = b * TM + m (or b * TN + n) at r * pitch + k; the
+  // output staging row b * TM + m at pitch TN + 1
+  number_block({{g.a_bm, {g.tb, TM * pitch}}, {g.a_mm, {g.tm, pitch}}, {g.a_km, {lg_tk, 1u}}}, g.aw, g.al);
+  number_block({{g.b_bm, {g.tb, TN * pitch}}, {g.b_nm, {g.tn, pitch}}, {g.b_km, {lg_tk, 1u}}}, g.bw, g.bl);
+  number_block({{g.c_bm, {g.tb, TM * (TN + 1u)}}, {g.c_mm, {g.tm, TN + 1u}}, {g.c_nm, {g.tn, 1u}}}, g.cw, g.cl);
   return QT_OK;
 }
 

@@ -50,12 +50,26 @@ using gmut_t = __attribute__((address_space(1))) XRaw<E>*;
 template <int N>
 __device__ __forceinline__ uint32_t xpext_all(uint32_t x, const uint8_t (&lo)[N], const uint8_t (&len)[N],
                                               const uint8_t (&dst)[N]) {
-  // runs are packed from index 0; the first empty one ends the list (a
-  // uniform branch: the tables are wavefront-uniform)
+  // The byte tables are read as 32-bit words (each table is 4-byte aligned
+  // and a multiple of 4 long): a byte-indexed read of a wavefront-uniform
+  // table becomes a chain of vector byte loads, a word read at a constant
+  // offset a scalar load.  Runs are packed from index 0; a word of four
+  // empty runs ends the list, and an empty run inside a word contributes 0.
+  static_assert(N % 4 == 0, "run tables are read as words");
+  const uint32_t* const wl = reinterpret_cast<const uint32_t*>(lo);
+  const uint32_t* const wn = reinterpret_cast<const uint32_t*>(len);
+  const uint32_t* const wd = reinterpret_cast<const uint32_t*>(dst);
   uint32_t r = 0;
-  for (int i = 0; i < N; ++i) {
-    if (len[i] == 0) break;
-    r |= ((x >> lo[i]) & ((1u << len[i]) - 1u)) << dst[i];
+#pragma unroll
+  for (int w = 0; w < N / 4; ++w) {
+    const uint32_t nw = wn[w];
+    if (nw == 0) break;
+    const uint32_t lw = wl[w], dw = wd[w];
+#pragma unroll
+    for (int b = 0; b < 32; b += 8) {
+      const uint32_t n = (nw >> b) & 0xffu;
+      r |= ((x >> ((lw >> b) & 0xffu)) & ((1u << n) - 1u)) << ((dw >> b) & 0xffu);
+    }
   }
   return r;
 }

@@ -125,6 +125,8 @@ struct XOp {  // 32-bit fields only: they are read with scalar loads
   uint8_t run_dst[kXRuns];
 };
 
+static_assert(kXRuns % 4 == 0 && offsetof(XOp, run_lo) % 4 == 0 && sizeof(XOp) % 4 == 0, "word-aligned run tables");
+
 // Output of an executor step: LDS (ptr null) or global memory.
 struct XOut {
   void* ptr;
@@ -259,6 +261,8 @@ struct XROp {
   uint8_t y_lo[kXRuns], y_len[kXRuns], y_dst[kXRuns];
   uint8_t c_lo[kXRuns], c_len[kXRuns], c_dst[kXRuns];
 };
+// the executors read these byte tables as 32-bit words
+static_assert(kXRuns % 4 == 0 && offsetof(XROp, y_lo) % 4 == 0 && sizeof(XROp) % 4 == 0, "word-aligned run tables");
 struct XRev {
   uint32_t out_off;   // LDS element offset of Tbar_j
   int32_t out_slot;   // its scale slot (-1: unscaled)

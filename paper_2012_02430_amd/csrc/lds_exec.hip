@@ -86,6 +86,20 @@ __device__ __forceinline__ uint32_t xpext_bits(uint64_t x, uint32_t m) {
   return r;
 }
 
+// Max over the wavefront of non-negative values given as their float bits
+// (their integer max): DPP steps inside each row of 16 lanes (swap of
+// neighbours, of pairs, mirror of each half row, mirror of the row), then
+// the four row maxima through readlane.  Exact; no LDS round trips.
+__device__ __forceinline__ uint32_t xwave_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
 // Power of two that brings max|x| into [0.5, 1), clamped so that 2^-shift is
 // a normal float.
 __device__ __forceinline__ int xshift(uint32_t maxbits) {
@@ -176,16 +190,15 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       }
     }
   }
-  if (SCALED) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if (SCALED && o.slot_kind != 0) {
+    const uint32_t mw = xwave_max(__float_as_uint(m));
     if (c.lane == 0) {
       if (o.slot_kind == 1) {
-        atomicMax(smax + o.slot, __float_as_uint(m));
+        atomicMax(smax + o.slot, mw);
         if (chunk == 0) sexp[o.slot] = eacc;
-      } else if (o.slot_kind == 2) {
+      } else {
         const int g = o.slot + (int)c.pt * o.exp_pt + (int)c.sb * o.exp_sb;
-        atomicMax(gmax + g, __float_as_uint(m));
+        atomicMax(gmax + g, mw);
         if (chunk == 0) gexps[g] = eacc;
       }
     }
@@ -569,11 +582,10 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
   }
   if (g == 0) lds[rv.out_off + y] = acc;
   if (SCALED) {
-    float m = g == 0 ? fmaxf(fabsf((float)acc.x), fabsf((float)acc.y)) : 0.f;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    const float m = g == 0 ? fmaxf(fabsf((float)acc.x), fabsf((float)acc.y)) : 0.f;
+    const uint32_t mw = xwave_max(__float_as_uint(m));
     if (lane == 0) {
-      atomicMax(smax + rv.out_slot, __float_as_uint(m));
+      atomicMax(smax + rv.out_slot, mw);
       if (chunk == 0) sexp[rv.out_slot] = eacc;
     }
   }

@@ -74,6 +74,26 @@ __device__ __forceinline__ uint32_t xpext_all(uint32_t x, const uint8_t (&lo)[N]
   return r;
 }
 
+// pext of (lane | cx) through the runs held in words w (lo[0..1], len[2..3],
+// dst[4..5]; kXRuns = 8): the lane part per lane, the uniform part cx on the
+// scalar unit, up to the first empty run.
+__device__ __forceinline__ uint32_t xpext_words(uint32_t lane, uint32_t cx, const uint32_t (&w)[6]) {
+  static_assert(kXRuns == 8, "two words per table");
+  uint32_t rl = 0, rc = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int b = 0; b < 32; b += 8) {
+      const uint32_t n = (w[2 + h] >> b) & 0xffu;
+      if (n == 0) return rl + rc;
+      const uint32_t l = (w[h] >> b) & 0xffu, d = (w[4 + h] >> b) & 0xffu, m = (1u << n) - 1u;
+      rl |= ((lane >> l) & m) << d;
+      rc |= ((cx >> l) & m) << d;
+    }
+  }
+  return rl + rc;
+}
+
 __device__ __forceinline__ uint32_t xpext_bits(uint64_t x, uint32_t m) {
   uint32_t r = 0;
   int o = 0;
@@ -115,7 +135,11 @@ struct XCtx {
   uint32_t lane;
 };
 
-template <typename E, bool SCALED, int NIN, int EPU>
+// PRE: load every descriptor word of the unit up front (one batch of scalar
+// loads, about four round trips per unit instead of one per operand field;
+// costs up to 6 SGPRs per operand), else read them where they are used
+// (kernels short of registers).
+template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,
                                        uint32_t* __restrict__ gmax) {
@@ -124,17 +148,65 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
   uint32_t base[NIN], lp[NIN];
   R sc[NIN];
   int eacc = 0;
+  if constexpr (PRE) {
+    // Setup in phases so that each phase's loads issue together: the
+    // operands' descriptor fields, then their scale slots (read even for an
+    // unscaled operand, at slot 0, and ignored), then the index maps.
+    uint32_t smk[NIN];
+    int slw[NIN], slot[NIN];
 #pragma unroll
-  for (int j = 0; j < NIN; ++j) {
-    const XOp& in = st.in[j];
-    base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
-    const uint32_t pc = xpext_all(cx, in.run_lo, in.run_len, in.run_dst);
-    lp[j] = xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc;
-    sc[j] = (R)1;
-    if (SCALED && in.slot >= 0) {
-      const int sh = xshift(smax[in.slot]);
-      sc[j] = (R)xpow2neg(sh);
-      eacc += sexp[in.slot] + sh;
+    for (int j = 0; j < NIN; ++j) {
+      base[j] = st.in[j].lds_off;
+      smk[j] = st.in[j].smask;
+      slw[j] = st.in[j].slow;
+      slot[j] = st.in[j].slot;
+    }
+    uint32_t mbits[NIN];
+    int mexp[NIN];
+    if (SCALED) {
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) {
+        const int q = slot[j] >= 0 ? slot[j] : 0;
+        mbits[j] = smax[q];
+        mexp[j] = sexp[q];
+      }
+    }
+    // run tables as words (6 per operand: lo, len, dst for runs 0-3 and 4-7),
+    // all loaded before any is used, then evaluated up to the first empty run
+    uint32_t rw[NIN][6];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
+    }
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) lp[j] = xpext_words(c.lane, cx, rw[j]);
+#pragma unroll
+    for (int j = 0; j < NIN; ++j)
+      if (smk[j]) base[j] += xpext_bits(c.sid, smk[j]) << slw[j];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      sc[j] = (R)1;
+      if (SCALED && slot[j] >= 0) {
+        const int sh = xshift(mbits[j]);
+        sc[j] = (R)xpow2neg(sh);
+        eacc += mexp[j] + sh;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const XOp& in = st.in[j];
+      base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
+      const uint32_t pc = xpext_all(cx, in.run_lo, in.run_len, in.run_dst);
+      lp[j] = xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc;
+      sc[j] = (R)1;
+      if (SCALED && in.slot >= 0) {
+        const int sh = xshift(smax[in.slot]);
+        sc[j] = (R)xpow2neg(sh);
+        eacc += sexp[in.slot] + sh;
+      }
     }
   }
   E a0[EPU][NIN], a1[EPU][NIN];
@@ -655,14 +727,14 @@ __device__ __forceinline__ void x_grad_unit(const uint2 un, const XStep* __restr
     const XStep& st = psteps[idx];
     const bool big = st.r >= kXBigRank;
     if (st.n_in <= 2) {
-      if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      if (big) x_unit<E, SCALED, 2, kBig, false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 2, 1, false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
     } else if (st.n_in <= 4) {
-      if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      if (big) x_unit<E, SCALED, 4, kBig, false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 4, 1, false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
     } else {
-      if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1), false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
+      else x_unit<E, SCALED, 8, 1, false>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
     }
   } else if (kind == kXUnitRev) {
     const XRev& rv = prevs[idx];

@@ -12,6 +12,8 @@
 // contiguous block (the paper's "first t indices" blocks, Section VI-B).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qt_internal.h"
 
 namespace qt {
@@ -20,6 +22,7 @@ namespace {
 constexpr int kWG = 256;
 constexpr int kEPT = 4;                 // elements per thread, BIG mode
 constexpr int kLgTile = 10;             // log2(kWG * kEPT)
+constexpr int kMaxLgTpb = 4;            // BIG mode: at most 16 tiles per workgroup
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -100,33 +103,42 @@ __device__ __forceinline__ float abs_max(E v) {
 }
 __device__ __forceinline__ float abs_max(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
 
-// BIG mode: each workgroup covers one tile of kWG*kEPT outputs of one batch
-// item, so every per-item quantity (input bases, scale factors) is uniform
-// and the part of each input index that depends on the tile is computed on
-// the scalar unit.  All loads of a thread (kEPT elements x NIN inputs x the
-// two values of v) are issued before any arithmetic.  An input without the
-// summed variable is read twice at the same index, so the two products
-// t0 (v = 0) and t1 (v = 1) need no branch.
+// BIG mode: each workgroup covers 2^lg_tpb consecutive tiles of kWG*kEPT
+// outputs of one batch item, so every per-item quantity (input bases, scale
+// factors) is uniform and found once, and the part of each input index that
+// depends on the tile is computed on the scalar unit.  All loads of a
+// thread for a tile (kEPT elements x NIN inputs x the two values of v) are
+// issued before any arithmetic.  An input without the summed variable is
+// read twice at the same index, so the two products t0 (v = 0) and t1
+// (v = 1) need no branch.  The output max of the workgroup's tiles is
+// posted once.
 template <typename E, bool SCALED, int NIN>
 __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restrict__ exps,
                                                   uint32_t* __restrict__ maxbits) {
   using R = typename Cx<E>::R;
-  const uint32_t item = blockIdx.x >> s.lg_tiles;
-  const uint32_t tile = blockIdx.x & ((1u << s.lg_tiles) - 1u);
+  const int lg_groups = s.lg_tiles - s.lg_tpb;  // tile groups per item
+  const uint32_t item = blockIdx.x >> lg_groups;
+  const uint32_t tile0 = (blockIdx.x & ((1u << lg_groups) - 1u)) << s.lg_tpb;
   const uint32_t sb = item & ((1u << s.lg_nsb) - 1u);
   const uint32_t pt = item >> s.lg_nsb;
   const uint64_t sid = (uint64_t)s.chunk_base + sb;
   const uint32_t tid = threadIdx.x;
 
+  // The group's tiles differ in their low lg_tpb bits only, and pext is
+  // linear over disjoint bits: an input's tile part is that of the first
+  // tile plus one weight per set low bit (a few scalar adds per tile, and no
+  // run tables live across the tile loop).
   const E* src[NIN];
-  uint32_t lanep[NIN];
+  uint32_t lanep[NIN], tw[NIN][kMaxLgTpb];
   R scale[NIN];
   int eacc = 0;
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {
     const DevIn& in = s.in[j];
     src[j] = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-             ((int64_t)pext_bits(sid, in.smask) << in.slow) + ((int64_t)pext_tile(tile, in) << in.has_v);
+             ((int64_t)pext_bits(sid, in.smask) << in.slow) + ((int64_t)pext_tile(tile0, in) << in.has_v);
+#pragma unroll
+    for (int b = 0; b < kMaxLgTpb; ++b) tw[j][b] = b < s.lg_tpb ? pext_tile(1u << b, in) << in.has_v : 0u;
     lanep[j] = pext_runs(tid, in);
     scale[j] = (R)1;
     if (SCALED && in.exp_base >= 0) {
@@ -136,43 +148,55 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
       eacc += exps[slot] + sh;
     }
   }
-  E a0[kEPT][NIN], a1[kEPT][NIN];
-#pragma unroll
-  for (int e = 0; e < kEPT; ++e) {
+  E* const out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
+  float mx = 0.f;
+  const uint32_t n_here = 1u << s.lg_tpb;
+  for (uint32_t t = 0; t < n_here; ++t) {
+    const uint32_t tile = tile0 + t;
+    const E* st[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
-      const int hv = s.in[j].has_v;
-      const uint32_t idx = (s.in[j].ep[e] + lanep[j]) << hv;
-      if (hv) {
-        Cx<E>::load_pair(src[j], idx, a0[e][j], a1[e][j]);
-      } else {
-        a0[e][j] = src[j][idx];
-        a1[e][j] = a0[e][j];
+      uint32_t part = 0;
+#pragma unroll
+      for (int b = 0; b < kMaxLgTpb; ++b) part += (t >> b) & 1u ? tw[j][b] : 0u;
+      st[j] = src[j] + part;
+    }
+    E a0[kEPT][NIN], a1[kEPT][NIN];
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) {
+        const int hv = s.in[j].has_v;
+        const uint32_t idx = (s.in[j].ep[e] + lanep[j]) << hv;
+        if (hv) {
+          Cx<E>::load_pair(st[j], idx, a0[e][j], a1[e][j]);
+        } else {
+          a0[e][j] = st[j][idx];
+          a1[e][j] = a0[e][j];
+        }
       }
     }
-  }
-  E* out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
-  float mx = 0.f;
 #pragma unroll
-  for (int e = 0; e < kEPT; ++e) {
-    E t0 = a0[e][0], t1 = a1[e][0];
-    if (SCALED) {
-      t0 = cscale(t0, scale[0]);
-      t1 = cscale(t1, scale[0]);
-    }
-#pragma unroll
-    for (int j = 1; j < NIN; ++j) {
-      E x0 = a0[e][j], x1 = a1[e][j];
+    for (int e = 0; e < kEPT; ++e) {
+      E t0 = a0[e][0], t1 = a1[e][0];
       if (SCALED) {
-        x0 = cscale(x0, scale[j]);
-        x1 = cscale(x1, scale[j]);
+        t0 = cscale(t0, scale[0]);
+        t1 = cscale(t1, scale[0]);
       }
-      t0 = cmul(t0, x0);
-      t1 = cmul(t1, x1);
+#pragma unroll
+      for (int j = 1; j < NIN; ++j) {
+        E x0 = a0[e][j], x1 = a1[e][j];
+        if (SCALED) {
+          x0 = cscale(x0, scale[j]);
+          x1 = cscale(x1, scale[j]);
+        }
+        t0 = cmul(t0, x0);
+        t1 = cmul(t1, x1);
+      }
+      const E res = s.sum ? cadd(t0, t1) : t0;
+      out[(tile << kLgTile) | ((uint32_t)e << 8) | tid] = res;
+      if (SCALED) mx = fmaxf(mx, abs_max(res));
     }
-    const E res = s.sum ? cadd(t0, t1) : t0;
-    out[(tile << kLgTile) | ((uint32_t)e << 8) | tid] = res;
-    if (SCALED) mx = fmaxf(mx, abs_max(res));
   }
   if (SCALED) {
     __shared__ float red[kWG / 64];
@@ -185,7 +209,7 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
       for (int w = 1; w < kWG / 64; ++w) m = fmaxf(m, red[w]);
       const int slot = s.out_exp_base + (int)pt * s.out_exp_pt + (int)sb * s.out_exp_sb;
       atomicMax(maxbits + slot, __float_as_uint(m));
-      if (tile == 0) exps[slot] = eacc;
+      if (tile0 == 0) exps[slot] = eacc;
     }
   }
 }
@@ -414,8 +438,11 @@ void launch_step_t(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_ele
   if (s.r >= kLgTile) {
     DevStep t = s;
     t.lg_tiles = s.r - kLgTile;
-    hipLaunchKernelGGL((k_step_big<E, SCALED, NIN>), dim3((unsigned)(n_elems >> kLgTile)), dim3(kWG), 0, stream, t,
-                       exps, maxbits);
+    // a few tiles per workgroup: the per-item setup and the output max are
+    // paid once per group of tiles
+    t.lg_tpb = std::min(std::min(t.lg_tiles, kMaxLgTpb), std::max(0, env_int("QT_STEP_LG_TILES", 3)));
+    hipLaunchKernelGGL((k_step_big<E, SCALED, NIN>), dim3((unsigned)(n_elems >> (kLgTile + t.lg_tpb))), dim3(kWG), 0,
+                       stream, t, exps, maxbits);
   } else {
     hipLaunchKernelGGL((k_step_small<E, SCALED, NIN>), dim3((unsigned)((n_elems + kWG - 1) / kWG)), dim3(kWG), 0,
                        stream, s, exps, maxbits, n_elems);

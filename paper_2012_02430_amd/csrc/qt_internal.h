@@ -101,7 +101,7 @@ struct DevStep {
   int32_t out_exp_base;  // -1: unscaled output
   int32_t out_exp_pt;
   int32_t out_exp_sb;
-  int32_t pad;
+  int32_t lg_tpb;        // BIG mode: log2(consecutive tiles of one item per workgroup)
   DevIn in[kMaxIn];
 };
 

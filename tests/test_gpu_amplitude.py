@@ -224,6 +224,27 @@ def test_bitwise_reproducible():
     assert a1[0] == a2[0] and np.array_equal(s1, s2)
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_streaming_tile_groups_bitwise(precision, monkeypatch):
+    # streaming steps with 1, 4 or 16 tiles of an item per workgroup run the
+    # same arithmetic per element (and the same max per item): per-slice
+    # values are bitwise equal, and match the oracle
+    n, p, k = 32, 3, 4
+    edges = generate_regular_graph(n, 3, 5)
+    g, b = qaoa_params(p, 2, seed=6)
+    monkeypatch.setenv("QT_LDS_MAX_RANK", "4")  # most steps stream (ranks up to 16)
+    res = []
+    for lg in ("0", "2", "4"):
+        monkeypatch.setenv("QT_STEP_LG_TILES", lg)
+        net, plan = build(n, p, edges, k=k, precision=precision)
+        assert sum(s["rank"] >= 14 for s in plan.describe()["stream_steps"]) >= 4
+        res.append(plan.contract_batch(g, b, per_slice=True)[1])
+    assert all(np.array_equal(res[0], r) for r in res[1:])
+    for i in range(2):
+        want = oracle.sliced_values(oracle.amplitude_network(n, edges, g[i], b[i]), plan.order, plan.groups)
+        assert slice_err(res[0][i], want) < TOL[precision]
+
+
 def test_fault_injection_and_resume(monkeypatch):
     n, p = 20, 2
     edges = regular_graph(n, 3, 0)

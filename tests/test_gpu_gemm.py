@@ -112,3 +112,23 @@ def test_gemm_profile_class(monkeypatch):
     plan.contract_amplitude([], [])
     prof = plan.profile_read()
     assert prof["gemm"][0] == 1 and prof["gemm"][3] == 8.0 * 2 ** (2 + 5 + 5 + 6)
+
+
+@pytest.mark.parametrize("tiles", ["1", "2", "8", "64"])
+def test_gemm_tile_ranges_bitwise(monkeypatch, tiles):
+    # a workgroup's range of tiles (n fastest, then m, inside one batch tile)
+    # changes only which workgroup computes a tile: results are bitwise equal
+    # to one tile per workgroup, on a bucket with several n and m tiles per
+    # batch tile and a short K (the cross-tile prefetch path)
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
+    spec, tensors, order, _ = dense_case(21, 1, 7, 6, 4)
+    plan = api.Plan(api.Network(spec), order, precision="c64_mfma_fp32")
+    g = gemm_steps(plan)[0]["gemm"]
+    assert g["k_bits"] == 4
+    monkeypatch.setenv("QT_GEMM_TILES", "1")
+    ref = plan.contract_amplitude([], [])
+    monkeypatch.setenv("QT_GEMM_TILES", tiles)
+    got = plan.contract_amplitude([], [])
+    assert got == ref
+    want = oracle.contract(tensors, order)
+    assert abs(got - want) / abs(want) < TOL

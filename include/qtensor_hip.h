@@ -62,9 +62,10 @@ typedef enum {
  *                   in one step, a batched complex GEMM
  *                   C[b,m,n] = sum_k A[b,m,k] B[b,n,k] on the matrix cores
  *                   (FP32 inputs and accumulation), when the unfused output
- *                   would have rank >= 12 (QT_GEMM_MIN_RANK), K >= 8 and
- *                   M, N >= 16.  Same values as eliminating the variables
- *                   one by one, with a smaller intermediate.
+ *                   would have rank >= 12 (QT_GEMM_MIN_RANK), K >= 8,
+ *                   M, N >= 16 and A, B and C have rank <= 28 per batch
+ *                   item.  Same values as eliminating the variables one by
+ *                   one, with a smaller intermediate.
  *   QT_C64_SCALED_MFMA_BF16X3
  *                   reserved (split-BF16 products); qt_load_plan returns
  *                   QT_EUNSUPPORTED. */

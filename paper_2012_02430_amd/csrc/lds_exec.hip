@@ -138,8 +138,9 @@ struct XCtx {
 // PRE: load every descriptor word of the unit up front (one batch of scalar
 // loads, about four round trips per unit instead of one per operand field;
 // costs up to 6 SGPRs per operand), else read them where they are used
-// (kernels short of registers).
-template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true>
+// (kernels short of registers).  FOLDED: the descriptor is the unit's own
+// copy, with the chunk's part of each operand index already in lds_off.
+template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true, bool FOLDED = false>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,
                                        uint32_t* __restrict__ gmax) {
@@ -181,7 +182,7 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
     }
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) lp[j] = xpext_words(c.lane, cx, rw[j]);
+    for (int j = 0; j < NIN; ++j) lp[j] = xpext_words(c.lane, FOLDED ? 0u : cx, rw[j]);
 #pragma unroll
     for (int j = 0; j < NIN; ++j)
       if (smk[j]) base[j] += xpext_bits(c.sid, smk[j]) << slw[j];
@@ -385,14 +386,14 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
       const uint32_t chunk = (uint32_t)st.pad;
       const bool big = st.r >= kXBigRank;
       if (st.n_in <= 2) {
-        if (big) x_unit<E, SCALED, 2, kBig>(st, chunk, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 2, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 2, kBig, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 2, 1, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       } else if (st.n_in <= 4) {
-        if (big) x_unit<E, SCALED, 4, kBig>(st, chunk, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 4, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 4, kBig, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 4, 1, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       } else {
-        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, chunk, c, lds, smax, sexp, gexps, gmax);
-        else x_unit<E, SCALED, 8, 1>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1), true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+        else x_unit<E, SCALED, 8, 1, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       }
     }
     __syncthreads();

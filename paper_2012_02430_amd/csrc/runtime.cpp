@@ -651,11 +651,22 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
         cp.lslot = ws.lds_slot[t];
         S.copies.push_back(cp);
       }
-    // per-unit descriptors (the unit's chunk in the pad field)
+    // per-unit descriptors: the unit's chunk in the pad field, and the
+    // chunk's part of every operand index folded into the operand's offset
     S.ustep.clear();
     for (const uint2& u : S.units) {
-      S.ustep.push_back(S.xsteps[u.x]);
-      S.ustep.back().pad = (int32_t)u.y;
+      XStep x = S.xsteps[u.x];
+      x.pad = (int32_t)u.y;
+      const SymStep& st = plan.steps[S.steps[u.x]];
+      const uint32_t cx = u.y * 64u * (uint32_t)x_epu(st.rank, (int)st.ins.size(), elt);
+      for (size_t j = 0; j < st.ins.size(); ++j) {
+        XOp& in = x.in[j];
+        uint32_t r = 0;
+        for (int i = 0; i < kXRuns && in.run_len[i]; ++i)
+          r |= ((cx >> in.run_lo[i]) & ((1u << in.run_len[i]) - 1u)) << in.run_dst[i];
+        in.lds_off += r << in.has_v;
+      }
+      S.ustep.push_back(x);
     }
     total += ((S.ustep.size() * sizeof(XStep) + 255) & ~(size_t)255) +
              ((S.copies.size() * sizeof(XCopy) + 255) & ~(size_t)255) +

@@ -78,6 +78,7 @@ qt_status fill_xstep(const qt_plan& plan, int s, int elt, Loc out, LocFn loc, XS
     int32_t nr = 0;
     if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr))
       return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
+    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr);
     for (int e = 0; e < 4; ++e) {
       uint32_t r = 0;
       if (e < epu)

@@ -74,6 +74,21 @@ __device__ __forceinline__ uint32_t xpext_all(uint32_t x, const uint8_t (&lo)[N]
   return r;
 }
 
+// pext of a lane index through the operand's lane runs (packed by the host:
+// run i has source bit, length and destination bit in bits 9i..9i+8, the
+// count in bits 27..28).
+__device__ __forceinline__ uint32_t xpext_lane_word(uint32_t lane, uint32_t w) {
+  const uint32_t k = w >> 27;
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if ((uint32_t)i >= k) break;
+    const uint32_t f = w >> (9 * i);
+    r |= ((lane >> (f & 7u)) & ((1u << ((f >> 3) & 7u)) - 1u)) << ((f >> 6) & 7u);
+  }
+  return r;
+}
+
 // pext of (lane | cx) through the runs held in words w (lo[0..1], len[2..3],
 // dst[4..5]; kXRuns = 8): the lane part per lane, the uniform part cx on the
 // scalar unit, up to the first empty run.
@@ -172,17 +187,26 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
         mexp[j] = sexp[q];
       }
     }
-    // run tables as words (6 per operand: lo, len, dst for runs 0-3 and 4-7),
-    // all loaded before any is used, then evaluated up to the first empty run
-    uint32_t rw[NIN][6];
+    // the lane part from the packed lane runs; unless the chunk part is
+    // folded in, the run tables as words (6 per operand: lo, len, dst for
+    // runs 0-3 and 4-7), all loaded before any is used
+    uint32_t lw[NIN];
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) {
-      const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+    for (int j = 0; j < NIN; ++j) lw[j] = st.in[j].lane_runs;
+    if constexpr (FOLDED) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
+      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
+    } else {
+      uint32_t rw[NIN][6];
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) {
+        const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
+      }
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]) + xpext_words(0u, cx, rw[j]);
     }
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) lp[j] = xpext_words(c.lane, FOLDED ? 0u : cx, rw[j]);
 #pragma unroll
     for (int j = 0; j < NIN; ++j)
       if (smk[j]) base[j] += xpext_bits(c.sid, smk[j]) << slw[j];

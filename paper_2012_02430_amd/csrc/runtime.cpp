@@ -564,6 +564,7 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     x.has_v = si.has_v;
     int32_t nr = 0;
     if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr)) return false;
+    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr);
     for (int e = 0; e < 4; ++e) {
       uint32_t r = 0;
       if (e < epu)

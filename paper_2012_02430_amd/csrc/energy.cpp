@@ -78,13 +78,13 @@ qt_status fill_xstep(const qt_plan& plan, int s, int elt, Loc out, LocFn loc, XS
     int32_t nr = 0;
     if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr))
       return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
-    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr);
+    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr, x.has_v);
     for (int e = 0; e < 4; ++e) {
       uint32_t r = 0;
       if (e < epu)
         for (int q = 0; q < nr; ++q)
           r |= (((uint32_t)(64 * e) >> x.run_lo[q]) & ((1u << x.run_len[q]) - 1u)) << x.run_dst[q];
-      x.ep[e] = r;
+      x.ep[e] = r << x.has_v;
     }
   }
   for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {

@@ -205,7 +205,8 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
         for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
       }
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]) + xpext_words(0u, cx, rw[j]);
+      for (int j = 0; j < NIN; ++j)
+        lp[j] = xpext_lane_word(c.lane, lw[j]) + (xpext_words(0u, cx, rw[j]) << st.in[j].has_v);
     }
 #pragma unroll
     for (int j = 0; j < NIN; ++j)
@@ -225,7 +226,7 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       const XOp& in = st.in[j];
       base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
       const uint32_t pc = xpext_all(cx, in.run_lo, in.run_len, in.run_dst);
-      lp[j] = xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc;
+      lp[j] = (xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc) << in.has_v;
       sc[j] = (R)1;
       if (SCALED && in.slot >= 0) {
         const int sh = xshift(smax[in.slot]);
@@ -240,7 +241,7 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       const uint32_t hv = (uint32_t)st.in[j].has_v;
-      const uint32_t i = base[j] + ((lp[j] + st.in[j].ep[e]) << hv);
+      const uint32_t i = base[j] + lp[j] + st.in[j].ep[e];  // lp and ep are shifted by has_v
       a0[e][j] = lds[i];
       a1[e][j] = lds[i + hv];
     }

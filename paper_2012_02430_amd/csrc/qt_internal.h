@@ -119,7 +119,7 @@ struct XOp {  // 32-bit fields only: they are read with scalar loads
   int32_t has_v;
   int32_t slot;     // LDS scale slot, -1: unscaled
   uint32_t lane_runs;  // the runs over lane bits 0..5 (at most 3), packed: see x_lane_runs
-  uint32_t ep[4];   // pext(64 e) for the unit's elements e
+  uint32_t ep[4];   // pext(64 e) << has_v for the unit's elements e
   uint8_t run_lo[kXRuns];
   uint8_t run_len[kXRuns];
   uint8_t run_dst[kXRuns];
@@ -128,13 +128,14 @@ struct XOp {  // 32-bit fields only: they are read with scalar loads
 static_assert(kXRuns % 4 == 0 && offsetof(XOp, run_lo) % 4 == 0 && sizeof(XOp) % 4 == 0, "word-aligned run tables");
 
 // The part of an operand's runs that a lane index (bits 0..5) reaches, as
-// one word: run i (i < 3) has source bit, length and destination bit in
-// bits 9i..9i+8 (3 bits each), and the run count in bits 27..28.
-inline uint32_t x_lane_runs(const uint8_t* lo, const uint8_t* len, const uint8_t* dst, int n) {
+// one word: run i (i < 3) has source bit, length and destination bit (plus
+// `shift`, the operand's has_v) in bits 9i..9i+8 (3 bits each), and the
+// run count in bits 27..28.
+inline uint32_t x_lane_runs(const uint8_t* lo, const uint8_t* len, const uint8_t* dst, int n, int shift) {
   uint32_t w = 0, k = 0;
   for (int i = 0; i < n && lo[i] < 6; ++i) {
     const uint32_t l = lo[i], m = len[i] < 6 - lo[i] ? len[i] : 6 - lo[i];
-    w |= (l | m << 3 | (uint32_t)dst[i] << 6) << (9 * k);
+    w |= (l | m << 3 | ((uint32_t)dst[i] + (uint32_t)shift) << 6) << (9 * k);
     ++k;
   }
   return w | k << 27;

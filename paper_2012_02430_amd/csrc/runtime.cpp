@@ -564,13 +564,13 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     x.has_v = si.has_v;
     int32_t nr = 0;
     if (!make_runs(si.mask, kXRuns, x.run_lo, x.run_len, x.run_dst, nr)) return false;
-    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr);
+    x.lane_runs = x_lane_runs(x.run_lo, x.run_len, x.run_dst, nr, x.has_v);
     for (int e = 0; e < 4; ++e) {
       uint32_t r = 0;
       if (e < epu)
         for (int i = 0; i < nr; ++i)
           r |= (((uint32_t)(64 * e) >> x.run_lo[i]) & ((1u << x.run_len[i]) - 1u)) << x.run_dst[i];
-      x.ep[e] = r;
+      x.ep[e] = r << x.has_v;
     }
     return true;
   };

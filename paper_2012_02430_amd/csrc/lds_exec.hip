@@ -197,16 +197,19 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
 #pragma unroll
       for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
     } else {
-      uint32_t rw[NIN][6];
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) {
-        const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
+      if (chunk != 0) {  // the first chunk's part is zero (the common case of small steps)
+        uint32_t rw[NIN][6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
+        for (int j = 0; j < NIN; ++j) {
+          const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+#pragma unroll
+          for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
+        }
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(0u, cx, rw[j]) << st.in[j].has_v;
       }
-#pragma unroll
-      for (int j = 0; j < NIN; ++j)
-        lp[j] = xpext_lane_word(c.lane, lw[j]) + (xpext_words(0u, cx, rw[j]) << st.in[j].has_v);
     }
 #pragma unroll
     for (int j = 0; j < NIN; ++j)

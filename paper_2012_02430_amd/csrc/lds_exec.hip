@@ -228,8 +228,8 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
     for (int j = 0; j < NIN; ++j) {
       const XOp& in = st.in[j];
       base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
-      const uint32_t pc = xpext_all(cx, in.run_lo, in.run_len, in.run_dst);
-      lp[j] = (xpext_all(c.lane, in.run_lo, in.run_len, in.run_dst) + pc) << in.has_v;
+      lp[j] = xpext_lane_word(c.lane, in.lane_runs);
+      if (chunk != 0) lp[j] += xpext_all(cx, in.run_lo, in.run_len, in.run_dst) << in.has_v;
       sc[j] = (R)1;
       if (SCALED && in.slot >= 0) {
         const int sh = xshift(smax[in.slot]);

@@ -35,6 +35,15 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// Raw buffer over the 4 GiB window at p: loads and stores then take a
+// 32-bit per-lane byte offset (a tile's offsets are small; the tile's base
+// is uniform) instead of a 64-bit address per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff, 0x00020000);
+}
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
 template <typename E> struct Cx;
 template <> struct Cx<float2> {
   using R = float;
@@ -45,6 +54,21 @@ template <> struct Cx<float2> {
     a0 = make_float2(v.x, v.y);
     a1 = make_float2(v.z, v.w);
   }
+  __device__ static float2 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const u2v v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+  }
+  __device__ static void bload_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, float2& a0, float2& a1) {
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    a0 = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+    a1 = make_float2(__uint_as_float(v.z), __uint_as_float(v.w));
+  }
+  __device__ static void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 a) {
+    u2v v;
+    v.x = __float_as_uint(a.x);
+    v.y = __float_as_uint(a.y);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  }
 };
 template <> struct Cx<double2> {
   using R = double;
@@ -54,6 +78,16 @@ template <> struct Cx<double2> {
     const double2* q = reinterpret_cast<const double2*>(p) + idx;
     a0 = q[0];
     a1 = q[1];
+  }
+  __device__ static double2 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  __device__ static void bload_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, double2& a0, double2& a1) {
+    a0 = bload(r, off);
+    a1 = bload(r, off + 16u);
+  }
+  __device__ static void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double2 a) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, a), r, off, 0, 0);
   }
 };
 
@@ -153,13 +187,13 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   const uint32_t n_here = 1u << s.lg_tpb;
   for (uint32_t t = 0; t < n_here; ++t) {
     const uint32_t tile = tile0 + t;
-    const E* st[NIN];
+    __amdgpu_buffer_rsrc_t rs[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       uint32_t part = 0;
 #pragma unroll
       for (int b = 0; b < kMaxLgTpb; ++b) part += (t >> b) & 1u ? tw[j][b] : 0u;
-      st[j] = src[j] + part;
+      rs[j] = rsrc_of(src[j] + part);
     }
     E a0[kEPT][NIN], a1[kEPT][NIN];
 #pragma unroll
@@ -167,15 +201,16 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
 #pragma unroll
       for (int j = 0; j < NIN; ++j) {
         const int hv = s.in[j].has_v;
-        const uint32_t idx = (s.in[j].ep[e] + lanep[j]) << hv;
+        const uint32_t off = ((s.in[j].ep[e] + lanep[j]) << hv) * (uint32_t)sizeof(E);
         if (hv) {
-          Cx<E>::load_pair(st[j], idx, a0[e][j], a1[e][j]);
+          Cx<E>::bload_pair(rs[j], off, a0[e][j], a1[e][j]);
         } else {
-          a0[e][j] = st[j][idx];
+          a0[e][j] = Cx<E>::bload(rs[j], off);
           a1[e][j] = a0[e][j];
         }
       }
     }
+    const __amdgpu_buffer_rsrc_t ro = rsrc_of(out + ((int64_t)tile << kLgTile));
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
       E t0 = a0[e][0], t1 = a1[e][0];
@@ -194,7 +229,7 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
         t1 = cmul(t1, x1);
       }
       const E res = s.sum ? cadd(t0, t1) : t0;
-      out[(tile << kLgTile) | ((uint32_t)e << 8) | tid] = res;
+      Cx<E>::bstore(ro, (((uint32_t)e << 8) | tid) * (uint32_t)sizeof(E), res);
       if (SCALED) mx = fmaxf(mx, abs_max(res));
     }
   }

@@ -89,24 +89,21 @@ __device__ __forceinline__ uint32_t xpext_lane_word(uint32_t lane, uint32_t w) {
   return r;
 }
 
-// pext of (lane | cx) through the runs held in words w (lo[0..1], len[2..3],
-// dst[4..5]; kXRuns = 8): the lane part per lane, the uniform part cx on the
-// scalar unit, up to the first empty run.
-__device__ __forceinline__ uint32_t xpext_words(uint32_t lane, uint32_t cx, const uint32_t (&w)[6]) {
+// pext of x through the runs held in words w (lo[0..1], len[2..3],
+// dst[4..5]; kXRuns = 8), up to the first empty run.
+__device__ __forceinline__ uint32_t xpext_words(uint32_t x, const uint32_t (&w)[6]) {
   static_assert(kXRuns == 8, "two words per table");
-  uint32_t rl = 0, rc = 0;
+  uint32_t r = 0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
     for (int b = 0; b < 32; b += 8) {
       const uint32_t n = (w[2 + h] >> b) & 0xffu;
-      if (n == 0) return rl + rc;
-      const uint32_t l = (w[h] >> b) & 0xffu, d = (w[4 + h] >> b) & 0xffu, m = (1u << n) - 1u;
-      rl |= ((lane >> l) & m) << d;
-      rc |= ((cx >> l) & m) << d;
+      if (n == 0) return r;
+      r |= ((x >> ((w[h] >> b) & 0xffu)) & ((1u << n) - 1u)) << ((w[4 + h] >> b) & 0xffu);
     }
   }
-  return rl + rc;
+  return r;
 }
 
 __device__ __forceinline__ uint32_t xpext_bits(uint64_t x, uint32_t m) {
@@ -150,11 +147,11 @@ struct XCtx {
   uint32_t lane;
 };
 
-// PRE: load every descriptor word of the unit up front (one batch of scalar
-// loads, about four round trips per unit instead of one per operand field;
-// costs up to 6 SGPRs per operand), else read them where they are used
-// (kernels short of registers).  FOLDED: the descriptor is the unit's own
-// copy, with the chunk's part of each operand index already in lds_off.
+// PRE: read the unit's descriptor fields, scale slots and maps in phases,
+// each one batch of loads (a few round trips per unit instead of one per
+// field), else read each field where it is used (kernels short of
+// registers).  FOLDED: the descriptor is the unit's own copy, with the
+// chunk's part of each operand index already in lds_off.
 template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true, bool FOLDED = false>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,
@@ -188,18 +185,16 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       }
     }
     // the lane part from the packed lane runs; unless the chunk part is
-    // folded in, the run tables as words (6 per operand: lo, len, dst for
-    // runs 0-3 and 4-7), all loaded before any is used
+    // folded in, and past the first chunk (whose part is zero: the common
+    // case of small steps), the run tables as words (6 per operand: lo,
+    // len, dst for runs 0-3 and 4-7), all loaded before any is used
     uint32_t lw[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) lw[j] = st.in[j].lane_runs;
-    if constexpr (FOLDED) {
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
-      if (chunk != 0) {  // the first chunk's part is zero (the common case of small steps)
+    for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
+    if constexpr (!FOLDED) {
+      if (chunk != 0) {
         uint32_t rw[NIN][6];
 #pragma unroll
         for (int j = 0; j < NIN; ++j) {
@@ -208,7 +203,7 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
           for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
         }
 #pragma unroll
-        for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(0u, cx, rw[j]) << st.in[j].has_v;
+        for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(cx, rw[j]) << st.in[j].has_v;
       }
     }
 #pragma unroll

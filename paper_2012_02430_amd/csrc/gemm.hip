@@ -105,7 +105,9 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   constexpr int kSubM = TM / 16, kSubN = TN / 16;
   constexpr int kSubs = NB * kSubM * kSubN;
   static_assert(kSubs <= kGThreads / 64, "one 16 x 16 sub-tile per wavefront");
-  constexpr int kP = TK + 1;  // operand row pitch
+  // operand row pitch: the products read row li (0..15) at depth lk (0..3)
+  // per lane; 16 + 1 and 64 + 4 put those 64 reads in distinct banks
+  constexpr int kP = TK == 64 ? TK + 4 : TK + 1;
   constexpr int kALoads = kARows * TK / kGThreads, kBLoads = kBRows * TK / kGThreads;
   constexpr int kCWrites = kTileElems / kGThreads;
   static_assert(kARows * TK % kGThreads == 0 && kBRows * TK % kGThreads == 0 && kTileElems % kGThreads == 0, "");

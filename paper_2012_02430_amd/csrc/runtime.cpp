@@ -847,7 +847,7 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
   // K stage: 64 deep for long sums (more operand bytes in flight per
   // workgroup), else 16 (8 for K = 8)
   g.tk = g.nk >= 6 ? 64 : (g.nk >= 4 ? 16 : 8);
-  const uint32_t pitch = (g.tk == 64 ? 64u : 16u) + 1u;  // LDS row pitch of the kernel
+  const uint32_t pitch = g.tk == 64 ? 68u : 17u;  // LDS row pitch of the kernel
   const int lg_tk = ilog2(g.tk);
   const uint32_t TM = 1u << g.tm, TN = 1u << g.tn;
   g.a_kh = g.a_km & ~deposit((uint32_t)g.tk - 1u, g.a_km);

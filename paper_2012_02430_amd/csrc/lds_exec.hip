@@ -419,6 +419,22 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
         else x_unit<E, SCALED, 8, 1, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       }
     }
+    // Wavefronts without a unit in this level touch the next level's unit
+    // descriptors (one word per 64-byte line) while the others work, so the
+    // next level starts on scalar-cache hits.  Only idle wavefronts wait on
+    // these loads; the busy ones never issue them.
+    const int n_busy = u_end - u_beg < nw ? u_end - u_beg : nw;
+    if (wave >= n_busy && L + 1 < X.n_levels) {
+      const int nb = level_off[L + 1];
+      const int ne = level_off[L + 2] < nb + nw ? level_off[L + 2] : nb + nw;
+      uint32_t touch = 0;
+      for (int u = nb + (wave - n_busy); u < ne; u += nw - n_busy) {
+        const uint32_t* d = reinterpret_cast<const uint32_t*>(steps + u);
+#pragma unroll
+        for (int q = 0; q < (int)(sizeof(XStep) / 4); q += 16) touch |= d[q];
+      }
+      asm volatile("" : : "s"(touch));  // keeps the loads; emits nothing
+    }
     __syncthreads();
     if (tracing) trace[L + 1] = wall_clock64();
   }

@@ -213,7 +213,14 @@ qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_po
  * OBS_CUT, ZZ_DAG and RX_DAG tensors, no slicing).  gammas/betas are
  * [n_points][p].  energy: [n_points] (required); dE_dgamma, dE_dbeta:
  * [n_points][p] or NULL (no gradient pass); per_edge: [n_points][n_edges]
- * or NULL.  Sums over edges run in FP64 in edge order. */
+ * or NULL.  Sums over edges run in FP64 in edge order.
+ * Precision: without gradient outputs the lightcones run in the plans'
+ * precision.  With them, the forward and reverse pass run in complex128
+ * whatever the plans' precision, and the energies returned are that pass's:
+ * a derivative is a sum of per-gate terms about as large as the edge energy
+ * that cancel to a far smaller value near stationary points, so complex64
+ * arithmetic loses the 1e-5 relative bound there (measured 1.2e-5 normwise
+ * on a 200-node, p = 2 point), at a cost in time of under 10 percent. */
 qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
                          const double* gammas, const double* betas,
                          double* energy, double* dE_dgamma, double* dE_dbeta,

@@ -17,7 +17,8 @@ bucket       bucket elimination with a serial prefix and step-dependent slicing
              (Algorithm 1 without processes or threads, Section VI-C/VI-D)
 statevector  brute-force state-vector simulation (independent pin, n <= 20)
 closed_form  p=1 closed forms (amplitude partition sum, per-edge energy)
-energy       energy and its gradient (complex step) from lightcone networks
+energy       energy and its gradient (forward-mode tangents through the same
+             elimination) from lightcone networks
 
 Every function is pinned by tests under ``tests/test_oracle_*.py`` against
 brute force, closed forms and invariants, none of which goes through the

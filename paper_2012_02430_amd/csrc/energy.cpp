@@ -539,6 +539,7 @@ struct EnergyJob {
   std::vector<uint64_t> serials;
   int np = 0, precision = 0, p = 0;
   bool grad = false;
+  bool wide = false;  // complex128 elements (c128 plans, and every gradient job)
   int64_t budget = 0;
   int n_progs = 0;
   void* tables = nullptr;
@@ -578,7 +579,13 @@ qt_status alloc(T** p, size_t count) {
 }
 
 qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds_bytes, EnergyJob& job) {
-  const int elt = plans[0]->precision == QT_C128 ? 16 : 8;
+  // The gradient pass runs in complex128 for every precision: a derivative
+  // is a sum of per-gate terms of the size of the edge energy that cancel
+  // down to a much smaller value near stationary points, so FP32 arithmetic
+  // does not hold the complex64 tolerance there, while FP64 costs the same
+  // VALU issue rate as unpacked FP32 on this hardware.
+  const bool wide = plans[0]->precision == QT_C128 || grad;
+  const int elt = wide ? 16 : 8;
   const int p = plans[0]->net.p;
   // one launch shares the largest slot and record areas: size every
   // program's tensor area against them
@@ -763,6 +770,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   job.n_progs = n;
   job.p = p;
   job.grad = grad;
+  job.wide = wide;
   job.budget = lds_bytes;
   job.precision = plans[0]->precision;
   for (int e = 0; e < n; ++e) job.serials.push_back(plans[e]->serial);
@@ -835,7 +843,7 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
         job = g_jobs.back().get();
       }
     }
-    const bool c128 = job->precision == QT_C128;
+    const bool c128 = job->wide;
     if (p > 0) {
       const size_t pitch = 2 * p * sizeof(double);
       (void)pitch;
@@ -851,7 +859,7 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       m.lds_elems = cl.lds_elems;
       m.n_slots = cl.n_slots;
       m.n_recs = cl.n_recs;
-      if (grad) QT_HIP_CHECK(launch_lds_grad(m, cl.count, waves, c128, !c128, stream));
+      if (grad) QT_HIP_CHECK(launch_lds_grad(m, cl.count, waves, stream));
       else QT_HIP_CHECK(launch_lds_multi(m, cl.count, waves, c128, !c128, stream));
     }
     for (const GlobalProg& gp : job->global) {
@@ -860,7 +868,7 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       char* b = job->scratch;
       QT_HIP_CHECK(launch_grad_global(m, gp.prog, gp.level_sizes.data(), gp.n_levels, b + gp.arena_off,
                                       (uint32_t*)(b + gp.smax_off), (int*)(b + gp.sexp_off), (double*)(b + gp.gacc_off),
-                                      gp.arena_stride, gp.slot_stride, gp.rec_stride, c128, !c128, stream));
+                                      gp.arena_stride, gp.slot_stride, gp.rec_stride, stream));
     }
     for (int e : job->big) {
       const double* sums = nullptr;

@@ -972,45 +972,32 @@ size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128) {
   return 8 * slots16 + 8 * recs2 + (size_t)lds_elems * (c128 ? 16 : 8);
 }
 
-hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled, hipStream_t stream) {
+hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream) {
   const int64_t n_items = (int64_t)n_item_progs * m.n_points;
   if (n_items == 0) return hipSuccess;
-  const size_t smem = lds_grad_smem_bytes(m.n_slots, m.n_recs, m.lds_elems, c128);
+  const size_t smem = lds_grad_smem_bytes(m.n_slots, m.n_recs, m.lds_elems, true);
   const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
-  const void* fn = c128 ? reinterpret_cast<const void*>(&k_lds_grad<double2, false>)
-                        : (scaled ? reinterpret_cast<const void*>(&k_lds_grad<float2, true>)
-                                  : reinterpret_cast<const void*>(&k_lds_grad<float2, false>));
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_grad<double2, false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  if (c128)
-    hipLaunchKernelGGL((k_lds_grad<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
-                       m.level_off, m.finals, m.item_prog, m.rec_off);
-  else if (scaled)
-    hipLaunchKernelGGL((k_lds_grad<float2, true>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
-                       m.level_off, m.finals, m.item_prog, m.rec_off);
-  else
-    hipLaunchKernelGGL((k_lds_grad<float2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
-                       m.level_off, m.finals, m.item_prog, m.rec_off);
+  hipLaunchKernelGGL((k_lds_grad<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
+                     m.level_off, m.finals, m.item_prog, m.rec_off);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
                               uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
-                              int rec_stride, bool c128, bool scaled, hipStream_t stream) {
+                              int rec_stride, hipStream_t stream) {
   const XScratch S{arena, smax, sexp, gacc, arena_stride, slot_stride, rec_stride};
   const unsigned np = (unsigned)m.n_points;
-  auto go = [&](auto init, auto level, auto fin) -> hipError_t {
-    hipLaunchKernelGGL(init, dim3(np), dim3(64), 0, stream, m, m.progs, prog_id, S);
-    for (int L = 0; L < n_levels; ++L)
-      if (level_sizes[L] > 0)
-        hipLaunchKernelGGL(level, dim3((unsigned)level_sizes[L], np), dim3(64), 0, stream, m, m.progs, m.steps, m.revs,
-                           m.units, m.level_off, m.finals, prog_id, L, S);
-    hipLaunchKernelGGL(fin, dim3(np), dim3(64), 0, stream, m, m.progs, m.finals, m.rec_off, prog_id, S);
-    return hipGetLastError();
-  };
-  if (c128) return go(k_grad_init<double2, false>, k_grad_level<double2, false>, k_grad_final<double2, false>);
-  if (scaled) return go(k_grad_init<float2, true>, k_grad_level<float2, true>, k_grad_final<float2, true>);
-  return go(k_grad_init<float2, false>, k_grad_level<float2, false>, k_grad_final<float2, false>);
+  hipLaunchKernelGGL((k_grad_init<double2, false>), dim3(np), dim3(64), 0, stream, m, m.progs, prog_id, S);
+  for (int L = 0; L < n_levels; ++L)
+    if (level_sizes[L] > 0)
+      hipLaunchKernelGGL((k_grad_level<double2, false>), dim3((unsigned)level_sizes[L], np), dim3(64), 0, stream, m,
+                         m.progs, m.steps, m.revs, m.units, m.level_off, m.finals, prog_id, L, S);
+  hipLaunchKernelGGL((k_grad_final<double2, false>), dim3(np), dim3(64), 0, stream, m, m.progs, m.finals, m.rec_off,
+                     prog_id, S);
+  return hipGetLastError();
 }
 
 hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream) {

@@ -490,14 +490,14 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
                            uint32_t* maxbits, hipStream_t stream);
 hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
                             hipStream_t stream);
-hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
-                           hipStream_t stream);
+// The gradient executor runs in complex128 (unscaled) for every precision.
+hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream);
 size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128);
 // The gradient schedule of one program with its tensors in global scratch,
 // one launch per level (level_sizes: units per level, host memory).
 hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
                               uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
-                              int rec_stride, bool c128, bool scaled, hipStream_t stream);
+                              int rec_stride, hipStream_t stream);
 // out[r][q] = sum_i in[(r * n + i) * nq + q] in FP64, in order of i.
 hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream);
 hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream);

@@ -739,6 +739,61 @@ void number_block(std::initializer_list<std::pair<uint32_t, std::pair<int, uint3
   }
 }
 
+// Tile shape of a fused GEMM bucket: (batch, m, n) tile bits with four
+// 16 x 16 sub-tiles where possible.  A short-K product is output-bound:
+// prefer the shape whose bits cover the longest run of C's low storage bits
+// (a contiguous output block per tile).  A long-K product is operand-bound:
+// prefer the largest m x n tile (most reuse of each loaded element), then
+// the output run.  K stage: 64 deep for long sums (more operand bytes in
+// flight per workgroup), else 16 (8 for K = 8).
+void choose_gemm_tile(const qt_plan& plan, const SymStep& st, int32_t& tb_out, int32_t& tm_out, int32_t& tn_out,
+                      int32_t& tk_out) {
+  const auto& va = plan.tensors[st.ins[0].tensor].vars;
+  const auto& vb = plan.tensors[st.ins[1].tensor].vars;
+  const auto& vc = plan.tensors[st.out].vars;
+  auto has = [](const std::vector<int32_t>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
+  std::vector<int32_t> cb, cm, cn;
+  for (int x : vc) {
+    const bool ia = has(va, x), ib = has(vb, x);
+    if (ia && ib) cb.push_back(x);
+    else if (ia) cm.push_back(x);
+    else cn.push_back(x);
+  }
+  const int nb = (int)cb.size(), nm = (int)cm.size(), nn = (int)cn.size(), nk = (int)st.kvars.size();
+  std::vector<char> kind(vc.size());  // counter of each C storage bit, with its index
+  std::vector<int> idx(vc.size());
+  for (size_t q = 0; q < vc.size(); ++q) {
+    auto at = [&](const std::vector<int32_t>& v) { return (int)(std::find(v.begin(), v.end(), vc[q]) - v.begin()); };
+    if (has(cb, vc[q])) kind[q] = 'b', idx[q] = at(cb);
+    else if (has(cm, vc[q])) kind[q] = 'm', idx[q] = at(cm);
+    else kind[q] = 'n', idx[q] = at(cn);
+  }
+  const int shapes[8][3] = {{0, 5, 5}, {1, 5, 4}, {1, 4, 5}, {2, 4, 4}, {0, 5, 4}, {0, 4, 5}, {1, 4, 4}, {0, 4, 4}};
+  int best = 7, best_run = -1, best_subs = 0;
+  for (int s = 0; s < 8; ++s) {
+    const int tb = shapes[s][0], tm = shapes[s][1], tn = shapes[s][2];
+    if (tb > nb || tm > nm || tn > nn) continue;
+    int run = 0;
+    while (run < (int)vc.size()) {
+      const char k = kind[run];
+      const int lim = k == 'b' ? tb : (k == 'm' ? tm : tn);
+      if (idx[run] >= lim) break;
+      ++run;
+    }
+    const int subs = 1 << (tb + tm + tn - 8);
+    if (nk > 5) run += 64 * (tm + tn);  // reuse first
+    if (run > best_run || (run == best_run && subs > best_subs)) {
+      best = s;
+      best_run = run;
+      best_subs = subs;
+    }
+  }
+  tb_out = shapes[best][0];
+  tm_out = shapes[best][1];
+  tn_out = shapes[best][2];
+  tk_out = nk >= 6 ? 64 : (nk >= 4 ? 16 : 8);
+}
+
 qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const SymStep& st, int elt, int np,
                      int64_t chunk, DevGemm& g) {
   std::memset(&g, 0, sizeof(g));
@@ -808,45 +863,7 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
       !covers({g.c_bm, g.c_mm, g.c_nm}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3 ||
       g.nb + g.nm + g.nk > kGemmMaxRank || g.nb + g.nn + g.nk > kGemmMaxRank || g.nb + g.nm + g.nn > kGemmMaxRank)
     return fail(QT_EPLAN, "internal: GEMM operand maps do not tile their tensors");
-  // Tile shape: (batch, m, n) tile bits with four 16 x 16 sub-tiles where
-  // possible.  A short-K product is output-bound: prefer the shape whose
-  // bits cover the longest run of C's low storage bits (a contiguous output
-  // block per tile).  A long-K product is operand-bound: prefer the largest
-  // m x n tile (most reuse of each loaded element), then the output run.
-  std::vector<char> kind(vc.size());  // counter of each C storage bit, with its index
-  std::vector<int> idx(vc.size());
-  for (size_t q = 0; q < vc.size(); ++q) {
-    auto at = [&](const std::vector<int32_t>& v) { return (int)(std::find(v.begin(), v.end(), vc[q]) - v.begin()); };
-    if (has(cb, vc[q])) kind[q] = 'b', idx[q] = at(cb);
-    else if (has(cm, vc[q])) kind[q] = 'm', idx[q] = at(cm);
-    else kind[q] = 'n', idx[q] = at(cn);
-  }
-  const int shapes[8][3] = {{0, 5, 5}, {1, 5, 4}, {1, 4, 5}, {2, 4, 4}, {0, 5, 4}, {0, 4, 5}, {1, 4, 4}, {0, 4, 4}};
-  int best = -1, best_run = -1, best_subs = 0;
-  for (int s = 0; s < 8; ++s) {
-    const int tb = shapes[s][0], tm = shapes[s][1], tn = shapes[s][2];
-    if (tb > g.nb || tm > g.nm || tn > g.nn) continue;
-    int run = 0;
-    while (run < (int)vc.size()) {
-      const char k = kind[run];
-      const int lim = k == 'b' ? tb : (k == 'm' ? tm : tn);
-      if (idx[run] >= lim) break;
-      ++run;
-    }
-    const int subs = 1 << (tb + tm + tn - 8);
-    if (g.nk > 5) run += 64 * (tm + tn);  // reuse first
-    if (run > best_run || (run == best_run && subs > best_subs)) {
-      best = s;
-      best_run = run;
-      best_subs = subs;
-    }
-  }
-  g.tb = shapes[best][0];
-  g.tm = shapes[best][1];
-  g.tn = shapes[best][2];
-  // K stage: 64 deep for long sums (more operand bytes in flight per
-  // workgroup), else 16 (8 for K = 8)
-  g.tk = g.nk >= 6 ? 64 : (g.nk >= 4 ? 16 : 8);
+  choose_gemm_tile(plan, st, g.tb, g.tm, g.tn, g.tk);
   const uint32_t pitch = g.tk == 64 ? 68u : 17u;  // LDS row pitch of the kernel
   const int lg_tk = ilog2(g.tk);
   const uint32_t TM = 1u << g.tm, TN = 1u << g.tn;
@@ -1325,7 +1342,12 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
                  return r + "],\"in_has_v\":[" + h;
                }() + "]" +
                (st.gemm ? ",\"gemm\":{\"k_bits\":" + std::to_string(st.kvars.size()) + ",\"flops\":" +
-                              std::to_string(st.flops) + ",\"layouts\":" + [&] {
+                              std::to_string(st.flops) + ",\"tile\":" + [&] {
+                                int32_t tb, tm, tn, tk;
+                                choose_gemm_tile(*plan, st, tb, tm, tn, tk);
+                                return "[" + std::to_string(tb) + "," + std::to_string(tm) + "," +
+                                       std::to_string(tn) + "," + std::to_string(tk) + "]";
+                              }() + ",\"layouts\":" + [&] {
                                 // per operand, from bit 0 up: the counter each storage bit belongs to
                                 const auto& va = plan->tensors[st.ins[0].tensor].vars;
                                 const auto& vb = plan->tensors[st.ins[1].tensor].vars;

@@ -91,3 +91,57 @@ def test_energy_reproducible_and_errors():
     st = L.load().qt_energy_grad(arr, 1, 1, gs[:1].ctypes.data, bs[:1].ctypes.data, E.ctypes.data, None, None,
                                  None, 0)
     assert st == L.QT_EINVAL
+
+
+def test_energy_p3_n1000_all_edges_one_point():
+    # every one of the 1500 lightcones of the p = 3 energy workload at one
+    # point against the oracle's contraction of the same lightcone network
+    n, p = 1000, 3
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 32, seed=1)
+    model = api.EnergyModel(n, edges, p, precision="c64")
+    E, pe = model.energy(gs, bs, per_edge=True)
+    i = 5
+    want = np.array([oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real for u, v in edges])
+    assert np.abs(pe[i] - want).max() < TOL["c64"]
+    assert abs(E[i] - want.sum()) / want.sum() < TOL["c64"]
+
+
+def test_energy_c128_n1000_p3_sampled():
+    n, p = 1000, 3
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 4, seed=1)
+    model = api.EnergyModel(n, edges, p, precision="c128")
+    E, pe = model.energy(gs, bs, per_edge=True)
+    rng = np.random.default_rng(3)
+    for i in range(4):
+        for e in rng.choice(len(edges), 10, replace=False):
+            u, v = edges[e]
+            want = oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real
+            assert abs(pe[i, e] - want) < TOL["c128"], (i, e)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_energy_oversized_lightcones_take_the_step_schedule(precision, capfd, monkeypatch):
+    # an LDS budget below what the largest lightcones need sends them through
+    # the general per-step schedule (streaming launches); the others stay in
+    # the batched LDS launch.  Every edge is checked against the oracle.
+    n, p = 40, 3
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 3, seed=12)
+    monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
+    model = api.EnergyModel(n, edges, p, precision=precision)
+    n_fit = len(edges)
+    budget = 160 * 1024
+    while budget > 2048:  # shrink the budget until some lightcones no longer fit
+        budget -= 2048
+        monkeypatch.setenv("QT_LDS_BYTES", str(budget))
+        E, pe = model.energy(gs, bs, per_edge=True)
+        line = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("[qt grad] job:")][-1]
+        n_fit = int(line.split(":")[1].split()[0])
+        if n_fit < len(edges):
+            break
+    assert 0 < n_fit < len(edges), (budget, n_fit)
+    for i in range(3):
+        want = np.array([oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real for u, v in edges])
+        assert np.abs(pe[i] - want).max() < TOL[precision]

@@ -132,3 +132,34 @@ def test_gemm_tile_ranges_bitwise(monkeypatch, tiles):
     assert got == ref
     want = oracle.contract(tensors, order)
     assert abs(got - want) / abs(want) < TOL
+
+
+@pytest.mark.parametrize("nb,nm,nn,nk,tile", [(2, 4, 4, 6, [2, 4, 4, 64]), (1, 5, 4, 6, [1, 5, 4, 64]),
+                                              (1, 4, 5, 7, [1, 4, 5, 64]), (0, 5, 4, 6, [0, 5, 4, 64]),
+                                              (1, 4, 4, 6, [1, 4, 4, 64]), (0, 4, 4, 7, [0, 4, 4, 64]),
+                                              (3, 5, 5, 6, [0, 5, 5, 64])])
+def test_dense_gemm_every_long_k_tile_shape(monkeypatch, nb, nm, nn, nk, tile):
+    # every tile shape the long-K choice can take (the largest m x n tile,
+    # then the most sub-tiles), each with 64-deep K stages; the planner picks
+    # which of the two tensors is A, so m and n may trade places
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
+    spec, tensors, order, _ = dense_case(40 + nb + 3 * nm + 7 * nn + nk, nb, nm, nn, nk)
+    plan = api.Plan(api.Network(spec), order, precision="c64_mfma_fp32")
+    g = gemm_steps(plan)
+    t = g[0]["gemm"]["tile"]
+    assert len(g) == 1 and t[0] == tile[0] and sorted(t[1:3]) == sorted(tile[1:3]) and t[3] == tile[3], g
+    got = plan.contract_amplitude([], [])
+    want = oracle.contract(tensors, order)
+    assert abs(got - want) / abs(want) < TOL, (got, want)
+
+
+@pytest.mark.parametrize("nk,tk", [(3, 8), (4, 16), (5, 16)])
+def test_dense_gemm_short_k_stage_depths(monkeypatch, nk, tk):
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
+    spec, tensors, order, _ = dense_case(60 + nk, 1, 5, 5, nk)
+    plan = api.Plan(api.Network(spec), order, precision="c64_mfma_fp32")
+    g = gemm_steps(plan)
+    assert len(g) == 1 and g[0]["gemm"]["tile"][3] == tk, g
+    got = plan.contract_amplitude([], [])
+    want = oracle.contract(tensors, order)
+    assert abs(got - want) / abs(want) < TOL, (got, want)

@@ -2,14 +2,12 @@
 
 dE/dgamma and dE/dbeta from ``qt_energy_grad`` against the oracle's
 forward-mode tangents, central finite differences of the GPU energy, and
-the complex step of the p = 1 closed form.  A gradient component is a sum
-over edges of per-edge derivatives; every edge's contraction uses the same
-gate entries, rounded once per point, so rounding errors are correlated
-across edges and add up linearly, and each per-edge derivative is itself a
-cancellation of terms of the size of the edge's energy.  Its error is
-therefore measured against the size of the terms that enter it,
-sum_e (|<C_e>| + |d<C_e>/dtheta|), times 1e-12 for complex128 and 1e-5 for
-complex64.
+the complex step of the p = 1 closed form.  The gradient of one point is
+compared normwise: ||g - g_ref||_2 / ||g_ref||_2, absolute when
+||g_ref||_2 < 1e-8.  The gradient pass runs in complex128 for every plan
+precision (a derivative is a cancellation of per-gate terms of the size of
+the edge energy, which complex64 arithmetic does not resolve to 1e-5 near
+stationary points), so the bound is the complex128 one, 1e-12, for both.
 """
 
 import numpy as np
@@ -22,13 +20,19 @@ from workloads import qaoa_params, regular_graph
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-12, "c64": 1e-5}
+TOL = {"c128": 1e-12, "c64": 1e-5}  # energies from the forward-only launch
+GRAD_TOL = 1e-12  # gradients (and the energies of a gradient call): complex128 for every precision
 
 
 def oracle_grad(n, edges, g, b):
     E, dg, db, pe, peg = oracle.energy_grad(n, edges, g, b)
-    scale = np.abs(pe).sum() + np.abs(peg).sum(axis=0)  # per parameter: gamma_1..p, beta_1..p
-    return E, np.concatenate([dg, db]), scale
+    return E, np.concatenate([dg, db])
+
+
+def normwise(got, want):
+    d = np.linalg.norm(np.asarray(got) - np.asarray(want))
+    w = np.linalg.norm(want)
+    return d / w if w >= 1e-8 else d
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
@@ -39,22 +43,29 @@ def test_grad_vs_oracle(precision, n, p):
     model = api.EnergyModel(n, edges, p, precision=precision)
     E, dg, db = model.energy(gs, bs, grad=True)
     for i in range(3):
-        Eo, go, scale = oracle_grad(n, edges, gs[i], bs[i])
+        Eo, go = oracle_grad(n, edges, gs[i], bs[i])
         got = np.concatenate([dg[i], db[i]])
-        assert abs(E[i] - Eo) / abs(Eo) < TOL[precision]
-        assert np.all(np.abs(got - go) <= TOL[precision] * scale), (got, go)
+        assert abs(E[i] - Eo) / abs(Eo) < GRAD_TOL
+        assert normwise(got, go) <= GRAD_TOL, (got, go)
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_grad_call_returns_forward_energies_bitwise(precision):
+    # a gradient call's energies are those of the complex128 forward-only
+    # launch, bitwise (same order, same arithmetic); for a complex64 model
+    # they agree with its own forward launch to the complex64 tolerance
     n, p = 12, 2
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, 5, seed=3)
     model = api.EnergyModel(n, edges, p, precision=precision)
-    E0, pe0 = model.energy(gs, bs, per_edge=True)
+    wide = model if precision == "c128" else api.EnergyModel(n, edges, p, precision="c128")
+    E0, pe0 = wide.energy(gs, bs, per_edge=True)
     E1, pe1, _, _ = model.energy(gs, bs, per_edge=True, grad=True)
     assert np.array_equal(E0, E1)
     assert np.array_equal(pe0, pe1)
+    E2, pe2 = model.energy(gs, bs, per_edge=True)
+    assert np.abs(E2 - E1).max() < TOL[precision] * np.abs(E1).max()
+    assert np.abs(pe2 - pe1).max() < TOL[precision]
 
 
 def test_grad_vs_central_differences():
@@ -77,42 +88,44 @@ def test_grad_vs_central_differences():
             assert np.all(np.abs(fd - d[:, k]) < 1e-7 * (1 + np.abs(fd))), (which, k, fd, d[:, k])
 
 
-def test_grad_p1_closed_form_n1000():
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_grad_p1_closed_form_n1000(precision):
     n = 1000
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(1, 3, seed=5)
-    model = api.EnergyModel(n, edges, 1, precision="c64")
+    model = api.EnergyModel(n, edges, 1, precision=precision)
     _, dg, db = model.energy(gs, bs, grad=True)
     h = 1e-20
     for i in range(3):
         g, b = gs[i, 0], bs[i, 0]
         e_g = np.array([oracle.edge_energy_p1(edges, u, v, g + 1j * h, b) for u, v in edges])
         e_b = np.array([oracle.edge_energy_p1(edges, u, v, g, b + 1j * h) for u, v in edges])
-        size = np.abs(e_g.real).sum()
-        assert abs(dg[i, 0] - (e_g.imag / h).sum()) <= 1e-5 * (size + np.abs(e_g.imag / h).sum())
-        assert abs(db[i, 0] - (e_b.imag / h).sum()) <= 1e-5 * (size + np.abs(e_b.imag / h).sum())
+        want = np.array([(e_g.imag / h).sum(), (e_b.imag / h).sum()])
+        assert normwise([dg[i, 0], db[i, 0]], want) <= GRAD_TOL, (i, dg[i, 0], db[i, 0], want)
 
 
 def test_grad_n200_p2_64_points_sampled_and_antisymmetry():
     # the configuration of the gradient workload: n=200, p=2, 300 lightcones,
-    # 64 seeded points in one launch
+    # 64 seeded points in one launch; 16 of them against the oracle,
+    # including point 0, the one with the smallest gradient (|g| = 2.2, where
+    # the per-gate terms cancel most)
     n, p = 200, 2
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, 64, seed=1)
     model = api.EnergyModel(n, edges, p, precision="c64")
     E, dg, db = model.energy(gs, bs, grad=True)
     assert dg.shape == (64, 2) and db.shape == (64, 2)
-    for i in (0, 9, 21, 30, 38, 47, 55, 63):
-        Eo, go, scale = oracle_grad(n, edges, gs[i], bs[i])
-        assert abs(E[i] - Eo) / abs(Eo) < TOL["c64"]
+    for i in range(0, 64, 4):
+        Eo, go = oracle_grad(n, edges, gs[i], bs[i])
+        assert abs(E[i] - Eo) / abs(Eo) < GRAD_TOL
         got = np.concatenate([dg[i], db[i]])
-        assert np.all(np.abs(got - go) <= TOL["c64"] * scale), (i, got, go)
+        assert normwise(got, go) <= GRAD_TOL, (i, got, go)
     # E(-gamma, -beta) = E(gamma, beta) (complex conjugation of the circuit),
     # so the gradient is odd
     E2, dg2, db2 = model.energy(-gs, -bs, grad=True)
-    assert np.abs(E2 - E).max() < 1e-5 * np.abs(E).max()
-    assert np.abs(dg2 + dg).max() < 1e-5 * max(1.0, np.abs(dg).max())
-    assert np.abs(db2 + db).max() < 1e-5 * max(1.0, np.abs(db).max())
+    assert np.abs(E2 - E).max() < GRAD_TOL * np.abs(E).max()
+    for i in range(64):
+        assert normwise(-np.concatenate([dg2[i], db2[i]]), np.concatenate([dg[i], db[i]])) <= GRAD_TOL
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
@@ -148,7 +161,7 @@ def test_checkpoint_recompute_under_forced_budget(precision, capfd, monkeypatch)
     full = model.energy(gs, bs, grad=True)
     need, n_global = _job_line(capfd.readouterr().err)
     assert n_global == 0
-    elt = 16 if precision == "c128" else 8
+    elt = 16  # the gradient pass runs in complex128 for both precisions
     dropped_any = global_any = False
     for k in range(1, 400):
         budget = need - elt * 4 * k

@@ -94,7 +94,7 @@ def test_norm_over_all_bitstrings():
 # ----------------------------------------------------------------- invariants
 @pytest.mark.parametrize("n,p", [(16, 2), (24, 1), (20, 3)])
 def test_invariants(n, p):
-    edges = regular_graph(n, 3, 0) if n != 24 else regular_graph(24, 3, 0) if False else _rr(24)
+    edges = _rr(24) if n == 24 else regular_graph(n, 3, 0)
     g, b = qaoa_params(p, 1, seed=7)
     g, b = g[0], b[0]
     base = 2.0 ** (-n / 2)

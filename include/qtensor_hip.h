@@ -120,8 +120,13 @@ typedef struct {
  * have been eliminated; the first group_step[0] buckets form the serial
  * prefix, run once and shared by every slice.  The slice id's bits are the
  * slice variables' values, first listed variable most significant (the
- * binary representation of the rank in Algorithm 1).  This build runs
- * n_groups <= 1 (all slice variables at one step, r = n in Section VI-D). */
+ * binary representation of the rank in Algorithm 1), group by group.
+ * Several groups (r < n in Section VI-D) must have non-decreasing steps;
+ * they are executed with every group's variables fixed at the last group's
+ * step: the steps between two group steps then run once on tensors that
+ * hold the earlier groups' variables as their top bits, the same
+ * arithmetic as running them once per earlier-group slice on the blocks,
+ * so the per-slice values are those of the branched schedule. */
 typedef struct {
   const int32_t* order;
   int32_t n_order;
@@ -132,6 +137,13 @@ typedef struct {
   int32_t precision;    /* qt_precision */
   int64_t slice_batch;  /* slices processed per launch; 0 = as many as fit the workspace budget */
   int32_t flags;        /* QT_PLAN_* bits */
+  /* Open output variables (a batch of amplitudes, Section VII): `n_open`
+   * variables (0..20) that are neither eliminated nor sliced; the value of
+   * the contraction is then a tensor over them, 2^n_open values, computed
+   * in one contraction.  Output index bit a-1-q is the value of open_vars[q]
+   * (open_vars[0] most significant).  NULL / 0: a scalar amplitude. */
+  int32_t n_open;
+  const int32_t* open_vars;
 } qt_plan_desc;
 
 /* Plan flags.
@@ -168,6 +180,8 @@ typedef struct {
   int64_t workspace_bytes;  /* device workspace of the last run */
   int32_t element_bytes;    /* 8 (complex64) or 16 (complex128) */
   int32_t n_launches;       /* kernel launches of one amplitude at the last run's batch */
+  int32_t n_open;           /* open output variables: each contraction gives 2^n_open values */
+  int32_t n_groups;         /* slice groups of the schedule */
 } qt_plan_info;
 
 /* Copy a tensor network (Section IV-A: tensors over binary variables, each a
@@ -186,15 +200,17 @@ qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* desc, qt_plan*
 
 /* One amplitude at one parameter point: gate tensors materialised on the
  * device from (gamma, beta) (p values each), the serial prefix, all slices
- * (batched), the FP64 slice sum.  `out` receives the sum. */
+ * (batched), the FP64 slice sum.  `out` receives the sum (2^n_open values
+ * for a plan with open output variables). */
 qt_status qt_contract_amplitude(qt_plan* plan, const double* gammas, const double* betas,
                                 qt_amp* out, void* hip_stream);
 
 /* Batched contraction: every plan at every point (gammas/betas are
  * [n_points][p], row-major), restricted to slice ids in
  * [slice_begin, slice_end) (the resumable unit of work; slices are
- * independent, Eq. (2)).  out: [n_plans][n_points] partial sums over the
- * range.  per_slice_out (optional, NULL to skip): [n_plans][n_points]
+ * independent, Eq. (2)).  out: [n_plans][n_points][2^a] partial sums over
+ * the range, a = the plans' n_open (all plans of a call have the same).
+ * per_slice_out (optional, NULL to skip): [n_plans][n_points][2^a]
  * [slice_end - slice_begin][3] doubles (re, im, log2_scale) per slice, the
  * journal a caller keeps to resume.  Slices are summed in FP64 in slice-id
  * order, so results are bitwise reproducible.  The test hook environment
@@ -253,8 +269,26 @@ qt_status qt_profile_enable(qt_plan* plan, int32_t enable);
 
 /* Waits for the recorded events and adds their durations into
  * out[QT_KCLASS_COUNT]; with `reset` != 0 the accumulated statistics are
- * cleared afterwards. */
+ * cleared afterwards (those of qt_profile_read_ops too). */
 qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_t reset);
+
+/* Launch statistics of one operation of the schedule: a bucket step
+ * (streaming or fused GEMM; `op` = its index in the plan's step list), an
+ * LDS-executor segment (`op` = segment index), or all other kernels
+ * together (`op` = -1). */
+typedef struct {
+  int32_t kclass;  /* qt_kclass */
+  int32_t op;
+  int64_t launches;
+  double ms;       /* summed HIP-event durations */
+  double bytes;    /* algorithmic bytes */
+  double flops;    /* algorithmic real flops */
+} qt_op_stats;
+
+/* The recorded statistics per operation, in order of first launch: writes
+ * min(cap, count) records to `out` and the count to *n_ops; `reset` as for
+ * qt_profile_read. */
+qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int32_t* n_ops, int32_t reset);
 
 /* Execution tunables of a plan; 0 selects the library default (or the
  * QT_LDS_WAVES, QT_LDS_MAX_RANK, QT_LDS_WAVES_MULTI, QT_LDS_WAVES_GRAD

@@ -35,12 +35,25 @@ from oracle.networks import (  # noqa: F401
 from oracle.bucket import (  # noqa: F401
     bucket_elimination,
     contract,
+    contract_open,
     sliced_values,
     min_degree_order,
 )
 from oracle.energy import edge_energy, edge_energy_grad, energy, energy_grad  # noqa: F401
 from oracle.statevector import qaoa_state, amplitude_sv, energy_sv  # noqa: F401
 from oracle.closed_form import amplitude_p1, edge_energy_p1  # noqa: F401
+
+
+def amplitudes_open(n, edges, gammas, betas, open_qubits, z=None, order=None):
+    """<z'| U |+^n> for every value of the qubits in ``open_qubits`` (the
+    other qubits at z, default 0), in one contraction with their last
+    variables held (a batch of amplitudes, Section VII).  Index bit a-1-q of
+    the returned 2^a array is the value of open_qubits[q]."""
+    p = len(gammas)
+    opened = set(int(q) for q in open_qubits)
+    tensors = [t for t in amplitude_network(n, edges, gammas, betas, z)
+               if not (len(t[1]) == 1 and t[1][0] >= p * n and t[1][0] - p * n in opened)]
+    return contract_open(tensors, [ket_var(n, int(q), p) for q in open_qubits], order)
 
 
 def amplitude(n, edges, gammas, betas, z=None, order=None):

@@ -135,6 +135,32 @@ def contract(tensors, order=None):
     return complex(s)
 
 
+def open_tensor(remaining, scalar, open_vars):
+    """The tensor over ``open_vars`` that a contraction with those variables
+    held leaves: the outer product of the remaining tensors (each over a
+    subset of them) times the scalar, flattened with open_vars[0] as the most
+    significant index bit (a batch of amplitudes, Section VII)."""
+    a = len(open_vars)
+    res = np.full((2,) * a, scalar, dtype=np.complex128)
+    for arr, vs in remaining:
+        pos = [open_vars.index(x) for x in vs]
+        perm = sorted(range(len(vs)), key=lambda i: pos[i])
+        shape = [1] * a
+        for i in perm:
+            shape[pos[i]] = 2
+        res = res * np.transpose(arr, perm).reshape(shape)
+    return res.reshape(-1)
+
+
+def contract_open(tensors, open_vars, order=None):
+    """Contraction with ``open_vars`` held: 2^a values (open_vars[0] most significant)."""
+    open_vars = list(open_vars)
+    if order is None:
+        order = min_degree_order(tensors, exclude=open_vars)
+    rem, s = bucket_elimination(tensors, order)
+    return open_tensor(rem, s, open_vars)
+
+
 def contract_tangent(tensors, order=None):
     """Full contraction in tangent mode: returns (value, derivatives)."""
     if order is None:
@@ -145,7 +171,7 @@ def contract_tangent(tensors, order=None):
     return complex(s[0]), np.array(s[1:])
 
 
-def sliced_values(tensors, order, groups):
+def sliced_values(tensors, order, groups, open_vars=None):
     """Per-slice values of a step-dependent slicing schedule.
 
     ``order`` is the elimination order of the unsliced variables; ``groups``
@@ -153,7 +179,9 @@ def sliced_values(tensors, order, groups):
     of a group are fixed after ``step`` variables of ``order`` have been
     eliminated.  The slice id's bits are the slice variables' values, group
     by group, first variable most significant.  Returns a complex128 array of
-    length 2**(total slice variables); its sum is the contraction.
+    length 2**(total slice variables); its sum is the contraction.  With
+    ``open_vars`` (held, never eliminated) each slice gives the 2^a values of
+    ``open_tensor`` and the array has shape (2**k, 2**a).
     """
     groups = [(int(s), list(vs)) for s, vs in groups]
     steps = [s for s, _ in groups]
@@ -163,8 +191,11 @@ def sliced_values(tensors, order, groups):
     def run(tensors, start, g, scalar):
         if g == len(groups):
             rem, s = bucket_elimination(tensors, order[start:])
-            assert not rem
-            out.append(scalar * s)
+            if open_vars is None:
+                assert not rem
+                out.append(scalar * s)
+            else:
+                out.append(open_tensor(rem, scalar * s, list(open_vars)))
             return
         step, vs = groups[g]
         rem, s = bucket_elimination(tensors, order[start:step])

@@ -61,7 +61,7 @@ class qt_plan_desc(ctypes.Structure):
     _fields_ = [("order", POINTER(c_int32)), ("n_order", c_int32), ("n_groups", c_int32),
                 ("group_step", POINTER(c_int32)), ("group_len", POINTER(c_int32)),
                 ("slice_vars", POINTER(c_int32)), ("precision", c_int32), ("slice_batch", c_int64),
-                ("flags", c_int32)]
+                ("flags", c_int32), ("n_open", c_int32), ("open_vars", POINTER(c_int32))]
 
 
 QT_PLAN_PLAIN = 1
@@ -78,22 +78,33 @@ class qt_plan_info(ctypes.Structure):
                 ("prefix_width", c_int32), ("slice_width", c_int32), ("n_slice_vars", c_int32),
                 ("n_slices", c_int64), ("slice_batch", c_int64), ("prefix_bytes", c_double),
                 ("slice_bytes", c_double), ("prefix_flops", c_double), ("slice_flops", c_double),
-                ("workspace_bytes", c_int64), ("element_bytes", c_int32), ("n_launches", c_int32)]
+                ("workspace_bytes", c_int64), ("element_bytes", c_int32), ("n_launches", c_int32),
+                ("n_open", c_int32), ("n_groups", c_int32)]
+
+
+QT_MAX_SLICE_GROUPS = 16
 
 
 class qt_slicing_opts(ctypes.Structure):
     _fields_ = [("algo", c_int32), ("n_slice_vars", c_int32), ("max_candidates", c_int32),
-                ("threads", c_int32), ("tau", c_double), ("repeats", c_int32), ("seed", c_uint64)]
+                ("threads", c_int32), ("tau", c_double), ("repeats", c_int32), ("seed", c_uint64),
+                ("group_size", c_int32), ("exclude", POINTER(c_int32)), ("n_exclude", c_int32)]
 
 
 class qt_slicing_result(ctypes.Structure):
     _fields_ = [("step", c_int32), ("width", c_int32), ("prefix_width", c_int32),
                 ("slice_width", c_int32), ("unsliced_width", c_int32), ("peak_step", c_int32),
-                ("cost", c_double)]
+                ("cost", c_double), ("n_groups", c_int32), ("group_step", c_int32 * QT_MAX_SLICE_GROUPS),
+                ("group_len", c_int32 * QT_MAX_SLICE_GROUPS)]
 
 
 class qt_kernel_stats(ctypes.Structure):
     _fields_ = [("launches", c_int64), ("ms", c_double), ("bytes", c_double), ("flops", c_double)]
+
+
+class qt_op_stats(ctypes.Structure):
+    _fields_ = [("kclass", c_int32), ("op", c_int32), ("launches", c_int64), ("ms", c_double),
+                ("bytes", c_double), ("flops", c_double)]
 
 
 QT_KCLASS_NAMES = {0: "step_stream", 1: "step_small", 2: "lds", 3: "gemm", 4: "other"}
@@ -117,6 +128,7 @@ SIGNATURES = {
     "qt_plan_get_tuning": (c_int32, [c_void_p, POINTER(qt_tuning)]),
     "qt_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qt_profile_read": (c_int32, [c_void_p, POINTER(qt_kernel_stats), c_int32]),
+    "qt_profile_read_ops": (c_int32, [c_void_p, POINTER(qt_op_stats), c_int32, POINTER(c_int32), c_int32]),
     "qt_plan_describe": (c_int32, [c_void_p, ctypes.c_char_p, c_int64, POINTER(c_int64)]),
     "qt_free_plan": (None, [c_void_p]),
     "qt_free_network": (None, [c_void_p]),

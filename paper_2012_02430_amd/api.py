@@ -72,7 +72,10 @@ class Network:
                                     int(seed), out, ctypes.byref(n), ctypes.byref(w)))
         return [out[i] for i in range(n.value)], w.value
 
-    def plan_slicing(self, n_slice_vars, algo="min_fill", max_candidates=0, threads=0, tau=1.0, repeats=1, seed=0):
+    def plan_slicing(self, n_slice_vars, algo="min_fill", max_candidates=0, threads=0, tau=1.0, repeats=1, seed=0,
+                     group_size=0, exclude=()):
+        """Step-dependent slicing search; ``group_size`` r < n slices r variables per group, each group at
+        its own step (Section VI-D); ``exclude`` holds variables (open outputs) out of the search."""
         lib = L.load()
         cap = self.spec.n_vars
         order = (ctypes.c_int32 * cap)()
@@ -80,13 +83,22 @@ class Network:
         sl = (ctypes.c_int32 * max(1, n_slice_vars))()
         res = L.qt_slicing_result()
         wbs = (ctypes.c_int32 * (cap + 1))()
-        opts = L.qt_slicing_opts(ORDER_ALGOS[algo], n_slice_vars, max_candidates, threads, tau, repeats, seed)
+        ex = L.int32_array(exclude)
+        opts = L.qt_slicing_opts(ORDER_ALGOS[algo], n_slice_vars, max_candidates, threads, tau, repeats, seed,
+                                 int(group_size), ctypes.cast(ex, ctypes.POINTER(ctypes.c_int32)), len(exclude))
         L.check(lib.qt_plan_slicing(self.handle, ctypes.byref(opts), order, ctypes.byref(n), sl,
                                     ctypes.byref(res), wbs))
+        slice_vars = [sl[i] for i in range(n_slice_vars)]
+        groups, at = [], 0
+        for gi in range(res.n_groups):
+            ln = res.group_len[gi]
+            groups.append((res.group_step[gi], slice_vars[at:at + ln]))
+            at += ln
         return SlicingSchedule(
             order=[order[i] for i in range(n.value)],
             step=res.step,
-            slice_vars=[sl[i] for i in range(n_slice_vars)],
+            slice_vars=slice_vars,
+            slice_groups=groups,
             width=res.width,
             prefix_width=res.prefix_width,
             slice_width=res.slice_width,
@@ -102,6 +114,7 @@ class SlicingSchedule:
     order: list
     step: int
     slice_vars: list
+    slice_groups: list = None
     width: int = 0
     prefix_width: int = 0
     slice_width: int = 0
@@ -112,6 +125,9 @@ class SlicingSchedule:
 
     @property
     def groups(self):
+        """[(step, variables)] per slice group, in slice-id bit order."""
+        if self.slice_groups:
+            return [(s, list(v)) for s, v in self.slice_groups]
         return [(self.step, list(self.slice_vars))] if self.slice_vars else []
 
 
@@ -119,24 +135,27 @@ class Plan:
     """A compiled plan (``qt_load_plan``) over a loaded network."""
 
     def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False,
-                 fold_prefix=False, graph=False):
+                 fold_prefix=False, graph=False, open_vars=()):
         lib = L.load()
         self.network = network
         groups = list(groups)
         self.order = list(order)
         self.groups = groups
+        self.open_vars = [int(v) for v in open_vars]
         self.precision = precision
         o = L.int32_array(self.order)
         steps = L.int32_array([g[0] for g in groups])
         lens = L.int32_array([len(g[1]) for g in groups])
         sv = L.int32_array([v for g in groups for v in g[1]])
+        ov = L.int32_array(self.open_vars)
         d = L.qt_plan_desc(ctypes.cast(o, ctypes.POINTER(ctypes.c_int32)), len(self.order), len(groups),
                            ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(lens, ctypes.POINTER(ctypes.c_int32)),
                            ctypes.cast(sv, ctypes.POINTER(ctypes.c_int32)),
                            PRECISIONS[precision], int(slice_batch),
                            (L.QT_PLAN_PLAIN if plain else 0) | (L.QT_PLAN_FOLD_PREFIX if fold_prefix else 0)
-                           | (L.QT_PLAN_GRAPH if graph else 0))
+                           | (L.QT_PLAN_GRAPH if graph else 0), len(self.open_vars),
+                           ctypes.cast(ov, ctypes.POINTER(ctypes.c_int32)))
         h = ctypes.c_void_p()
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -156,6 +175,7 @@ class Plan:
                                           if len(t) > 3 else [])
                                        for t in spec.tensors],
                            "order": self.order, "groups": [[int(g[0]), [int(v) for v in g[1]]] for g in self.groups],
+                           "open_vars": self.open_vars,
                            "precision": self.precision, "slice_batch": self.slice_batch, "plain": self.plain,
                            "fold_prefix": self.fold_prefix}, sort_keys=True)
         return hashlib.sha1(blob.encode()).hexdigest()
@@ -204,15 +224,30 @@ class Plan:
         return {name: (arr[i].launches, arr[i].ms, arr[i].bytes, arr[i].flops)
                 for i, name in L.QT_KCLASS_NAMES.items() if arr[i].launches}
 
-    def contract_amplitude(self, gammas, betas, stream=None) -> complex:
+    def profile_read_ops(self, reset=True) -> list:
+        """Per operation of the schedule: dicts with kclass, op (step or segment index, -1 for other
+        kernels), launches, ms, bytes, flops, in order of first launch."""
+        n = ctypes.c_int32()
+        L.check(L.load().qt_profile_read_ops(self.handle, None, 0, ctypes.byref(n), 0))
+        arr = (L.qt_op_stats * max(1, n.value))()
+        L.check(L.load().qt_profile_read_ops(self.handle, arr, n.value, ctypes.byref(n), 1 if reset else 0))
+        return [{"kclass": L.QT_KCLASS_NAMES.get(arr[i].kclass, arr[i].kclass), "op": arr[i].op,
+                 "launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes, "flops": arr[i].flops}
+                for i in range(n.value)]
+
+    def contract_amplitude(self, gammas, betas, stream=None):
+        """The amplitude (complex), or with open variables the 2^a amplitudes (complex array, index bit
+        a-1-q = value of open_vars[q])."""
         g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1)
         b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1)
         if g.size != self.p or b.size != self.p:
             raise ValueError("gammas and betas need p values each")
-        out = L.qt_amp()
-        L.check(L.load().qt_contract_amplitude(self.handle, g.ctypes.data, b.ctypes.data, ctypes.byref(out),
-                                               stream or 0))
-        return amp_to_complex(out.re, out.im, out.log2_scale)
+        na = 1 << len(self.open_vars)
+        out = (L.qt_amp * na)()
+        L.check(L.load().qt_contract_amplitude(self.handle, g.ctypes.data, b.ctypes.data,
+                                               ctypes.cast(out, ctypes.c_void_p), stream or 0))
+        vals = np.array([amp_to_complex(o.re, o.im, o.log2_scale) for o in out])
+        return complex(vals[0]) if not self.open_vars else vals
 
     def contract_device(self, gammas, betas, out, per_slice=None, slice_begin=0, slice_end=None, stream=None):
         """Device-resident call: gammas/betas float64 GPU tensors [n_points, p]; out a float64 GPU tensor
@@ -232,7 +267,8 @@ class Plan:
     def contract_batch(self, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
         """Partial sums over a slice range at every point; optional per-slice values.
 
-        Returns (values[n_points] complex, per_slice[n_points, n_range] complex or None).
+        Returns (values[n_points] complex, per_slice[n_points, n_range] complex or None); with open
+        variables values[n_points, 2^a] and per_slice[n_points, 2^a, n_range].
         """
         return contract_batch([self], gammas, betas, slice_begin, slice_end, per_slice, stream)
 
@@ -246,17 +282,20 @@ def contract_batch(plans, gammas, betas, slice_begin=0, slice_end=None, per_slic
     if slice_end is None:
         slice_end = plans[0].n_slices
     n_range = slice_end - slice_begin
+    a = len(plans[0].open_vars)
     arr = (ctypes.c_void_p * len(plans))(*[pl.handle.value for pl in plans])
-    out = (L.qt_amp * (len(plans) * n_points))()
-    ps = np.zeros((len(plans), n_points, n_range, 3)) if per_slice else None
+    out = (L.qt_amp * (len(plans) * (n_points << a)))()
+    ps = np.zeros((len(plans), n_points << a, n_range, 3)) if per_slice else None
     st = lib.qt_contract_batch(arr, len(plans), n_points, g.ctypes.data, b.ctypes.data, slice_begin, slice_end,
                                ctypes.cast(out, ctypes.c_void_p), ps.ctypes.data if per_slice else None,
                                stream or 0)
     L.check(st)
-    vals = np.array([amp_to_complex(o.re, o.im, o.log2_scale) for o in out]).reshape(len(plans), n_points)
+    shape = (len(plans), n_points) + ((1 << a,) if a else ())
+    vals = np.array([amp_to_complex(o.re, o.im, o.log2_scale) for o in out]).reshape(shape)
     slices = None
     if per_slice:
         slices = np.vectorize(amp_to_complex)(ps[..., 0], ps[..., 1], ps[..., 2])
+        slices = slices.reshape(shape + (n_range,))
     if len(plans) == 1:
         return vals[0], (slices[0] if per_slice else None)
     return vals, slices

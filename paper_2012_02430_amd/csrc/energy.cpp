@@ -818,6 +818,8 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       if (!lightcones[e]) return fail(QT_EINVAL, "qt_energy_grad: null plan");
       if (lightcones[e]->net.p != p || lightcones[e]->precision != lightcones[0]->precision)
         return fail(QT_EINVAL, "qt_energy_grad: plans differ in p or precision");
+      if (!lightcones[e]->open_vars.empty() || !lightcones[e]->slice_vars.empty())
+        return fail(QT_EINVAL, "qt_energy_grad: lightcone plans take no slicing and no open variables");
     }
     const bool grad = dE_dgamma || dE_dbeta;
     const int64_t lds_bytes = std::min<int64_t>(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));

@@ -365,15 +365,20 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-// Per-slice value: product of the plan's scalar factors (results of buckets
-// that closed to a scalar, Algorithm 1 "result <- result * R"), with its
-// exponent, in FP64.
+// Per-slice value: product of the plan's closing factors (results of
+// buckets that closed to a scalar, Algorithm 1 "result <- result * R"), with
+// its exponent, in FP64.  With open output variables the closing factors
+// are tensors over subsets of them, and thread (item, j) forms output
+// element j (the open variables' values): the product of every factor at
+// the bits of j it holds (its runs over j), i.e. their outer product.
 template <typename E, bool SCALED>
 __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_points, int64_t n_items,
                         const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
                         double* __restrict__ per_slice, int64_t slice_end) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_items) return;
+  const int64_t tj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tj >= (n_items << f.n_open)) return;
+  const uint32_t oj = (uint32_t)(tj & ((1ll << f.n_open) - 1));  // open output index
+  const int64_t t = tj >> f.n_open;
   const uint32_t sb = (uint32_t)(t & ((1ll << f.lg_nsb) - 1));
   const uint32_t pt = (uint32_t)(t >> f.lg_nsb);
   const uint64_t sid = (uint64_t)f.chunk_base + sb;
@@ -382,7 +387,7 @@ __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_p
   for (int j = 0; j < f.n_factors; ++j) {
     const DevIn in = fac[j];
     const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-                        ((int64_t)pext_bits(sid, in.smask) << in.slow);
+                        ((int64_t)pext_bits(sid, in.smask) << in.slow) + (int64_t)pext_runs(oj, in);
     const E a = reinterpret_cast<const E*>(in.ptr)[idx];
     double ar = (double)a.x, ai = (double)a.y;
     if (SCALED && in.exp_base >= 0) {
@@ -396,7 +401,7 @@ __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_p
     im = re * ai + im * ar;
     re = nr;
   }
-  double* o = per_slice + 3 * ((int64_t)pt * f.n_range + (int64_t)(sid - f.slice_begin));
+  double* o = per_slice + 3 * ((((int64_t)pt << f.n_open) + oj) * f.n_range + (int64_t)(sid - f.slice_begin));
   o[0] = re;
   o[1] = im;
   o[2] = ex;
@@ -524,7 +529,9 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items, bool c128,
                         bool scaled, const int* exps, const uint32_t* maxbits, double* per_slice,
                         int64_t slice_end, hipStream_t stream) {
-  const dim3 grid((unsigned)((n_items + 255) / 256)), block(256);
+  const int64_t n = n_items << f.n_open;
+  if (n > 0x7fffffffll * 256) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (c128)
     hipLaunchKernelGGL((k_final<double2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
                        maxbits, per_slice, slice_end);

@@ -162,10 +162,11 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     if (d->precision == QT_C64_SCALED_MFMA_BF16X3)
       return fail(QT_EUNSUPPORTED, "qt_load_plan: the split-BF16 MFMA precision is not built; use QT_C64_SCALED_MFMA_FP32");
     if (d->n_order < 0 || (d->n_order > 0 && !d->order)) return fail(QT_EINVAL, "qt_load_plan: bad order");
-    if (d->n_groups < 0 || (d->n_groups > 0 && (!d->group_step || !d->group_len)))
+    if (d->n_groups < 0 || d->n_groups > 64 || (d->n_groups > 0 && (!d->group_step || !d->group_len)))
       return fail(QT_EINVAL, "qt_load_plan: bad groups");
-    if (d->n_groups > 1) return fail(QT_EUNSUPPORTED, "qt_load_plan: more than one slice group (r < n) is not built");
     if (d->slice_batch < 0) return fail(QT_EINVAL, "qt_load_plan: negative slice_batch");
+    if (d->n_open < 0 || d->n_open > kMaxOpen || (d->n_open > 0 && !d->open_vars))
+      return fail(QT_EINVAL, "qt_load_plan: n_open out of 0.." + std::to_string(kMaxOpen) + " or null open_vars");
 
     auto plan = std::make_unique<qt_plan>();
     static std::atomic<uint64_t> next_serial{1};
@@ -188,35 +189,56 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
       role[iv] = 0;
       plan->order.push_back(iv);
     }
-    int k = 0, s = d->n_order;
-    if (d->n_groups == 1) {
-      k = d->group_len[0];
-      s = d->group_step[0];
-      if (k < 0 || k > 30 || (k > 0 && !d->slice_vars)) return fail(QT_EPLAN, "qt_load_plan: group size out of 0..30");
-      if (s < 0 || s > d->n_order) return fail(QT_EPLAN, "qt_load_plan: group step out of [0, n_order]");
-      for (int j = 0; j < k; ++j) {
+    // Slice groups: variables concatenated group by group (the slice id's
+    // bits, first variable most significant); all are fixed at the last
+    // group's step.
+    int k = 0, s = d->n_order, prev_step = 0;
+    for (int gi = 0; gi < d->n_groups; ++gi) {
+      const int kg = d->group_len[gi], sg = d->group_step[gi];
+      if (kg < 0 || k + kg > 30 || (kg > 0 && !d->slice_vars))
+        return fail(QT_EPLAN, "qt_load_plan: slice variables out of 0..30 in total");
+      if (sg < 0 || sg > d->n_order) return fail(QT_EPLAN, "qt_load_plan: group step out of [0, n_order]");
+      if (sg < prev_step) return fail(QT_EPLAN, "qt_load_plan: group steps must be non-decreasing");
+      prev_step = sg;
+      for (int j = 0; j < kg; ++j) {
         int iv;
-        if (!internal(d->slice_vars[j], iv)) return fail(QT_EPLAN, "qt_load_plan: slice variable not in the network");
+        if (!internal(d->slice_vars[k + j], iv))
+          return fail(QT_EPLAN, "qt_load_plan: slice variable not in the network");
         if (role[iv] >= 0) return fail(QT_EPLAN, "qt_load_plan: slice variable repeated or also in the order");
         role[iv] = 1;
         plan->slice_vars.push_back(iv);
       }
-      if (k == 0) s = d->n_order;
+      k += kg;
+      s = sg;
+    }
+    plan->n_groups = d->n_groups;
+    if (k == 0) s = d->n_order;
+    const int a = d->n_open;
+    for (int q = 0; q < a; ++q) {
+      int iv;
+      if (!internal(d->open_vars[q], iv)) return fail(QT_EPLAN, "qt_load_plan: open variable not in the network");
+      if (role[iv] >= 0) return fail(QT_EPLAN, "qt_load_plan: open variable repeated, ordered or sliced");
+      role[iv] = 2;
+      plan->open_vars.push_back(iv);
     }
     for (int v = 0; v < V; ++v)
       if (role[v] < 0)
-        return fail(QT_EPLAN, "qt_load_plan: variable " + std::to_string(net->ext_of[v]) + " neither ordered nor sliced");
+        return fail(QT_EPLAN, "qt_load_plan: variable " + std::to_string(net->ext_of[v]) +
+                                  " neither ordered, sliced nor open");
     const int n_order = d->n_order;
     plan->n_order = n_order;
     plan->slice_step = s;
 
-    // Global key: order position; slice variable j gets n_order + (k-1-j).
+    // Global key: order position; open variable q gets n_order + (a-1-q)
+    // (its bit in the output index); slice variable j gets
+    // n_order + a + (k-1-j), above everything else.
     auto& key = plan->key;
     key.assign(V, 0);
     std::vector<int> slice_index(V, -1);
     for (int i = 0; i < n_order; ++i) key[plan->order[i]] = i;
+    for (int q = 0; q < a; ++q) key[plan->open_vars[q]] = n_order + (a - 1 - q);
     for (int j = 0; j < k; ++j) {
-      key[plan->slice_vars[j]] = n_order + (k - 1 - j);
+      key[plan->slice_vars[j]] = n_order + a + (k - 1 - j);
       slice_index[plan->slice_vars[j]] = j;
     }
     auto by_key = [&](int a, int b) { return key[a] < key[b]; };
@@ -583,6 +605,8 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     in.prefix_flops = plan->prefix_flops;
     in.slice_flops = plan->slice_flops;
     in.element_bytes = d->precision == QT_C128 ? 16 : 8;
+    in.n_open = a;
+    in.n_groups = d->n_groups;
     *out = plan.release();
     return QT_OK;
   } catch (const std::exception& ex) {

@@ -1,5 +1,5 @@
 // Host planner: greedy elimination orders on the line graph (Section V-A)
-// and the step-dependent slicing search (Section VI-C, VI-D with r = n).
+// and the step-dependent slicing search (Section VI-C, VI-D).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -242,93 +242,167 @@ extern "C" qt_status qt_order_greedy(const qt_network* net, int32_t algo, const 
   }
 }
 
+namespace qt {
+namespace {
+
+// One step-dependent slicing search (Section VI-C, VI-D) on graph g0 for
+// k variables: the candidate steps up to the peak of g0's order, each
+// eliminating that prefix, deleting the k highest-degree vertices (degrees
+// recomputed after each deletion, ties to the smallest id) and ordering the
+// rest afresh; the narrowest candidate wins (ties: cost, then step).
+struct Sweep {
+  int s = 0, width = 0, pw = 0, sw = 0, unsliced = 0, peak = 0;
+  double pre_cost = 0, post_cost = 0;
+  std::vector<int32_t> pre, post, sl;
+  std::vector<int> cands, cand_width;
+};
+
+qt_status sweep(const Graph& g0, int k, const qt_slicing_opts& opts, Sweep& out) {
+  std::vector<int32_t> order0, w0;
+  best_greedy(g0, opts.algo, opts.tau, opts.repeats, opts.seed, order0, w0);
+  const int unsliced = max_of(w0, 0, w0.size());
+  int peak = 0;
+  while (peak < (int)w0.size() && w0[peak] != unsliced) ++peak;
+  std::vector<int> cands;
+  if (k == 0) {
+    cands.push_back(0);
+  } else if (opts.max_candidates <= 0 || opts.max_candidates >= peak + 1) {
+    for (int s = 0; s <= peak; ++s) cands.push_back(s);
+  } else {
+    int m = opts.max_candidates;
+    for (int i = 0; i < m; ++i) cands.push_back((int)((int64_t)i * peak / std::max(1, m - 1)));
+    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+  }
+  struct Eval {
+    int width = std::numeric_limits<int>::max(), pw = 0, sw = 0;
+    double cost = 0, post_cost = 0;
+    std::vector<int32_t> post, sl;
+  };
+  std::vector<Eval> evals(cands.size());
+  auto run = [&](size_t ci) {
+    const int s = cands[ci];
+    Graph g = g0;
+    for (int i = 0; i < s; ++i) g.eliminate(order0[i]);
+    Eval& e = evals[ci];
+    for (int j = 0; j < k; ++j) {
+      int best = -1;
+      for (int v = 0; v < g.V; ++v)
+        if (g.alive[v] && (best < 0 || g.deg[v] > g.deg[best])) best = v;
+      if (best < 0) break;
+      e.sl.push_back(best);
+      g.remove(best);
+    }
+    std::vector<int32_t> w;
+    best_greedy(g, opts.algo, opts.tau, opts.repeats, opts.seed + 1000003ull * (s + 1), e.post, w);
+    e.pw = max_of(w0, 0, s);
+    e.sw = max_of(w, 0, w.size());
+    e.width = std::max(e.pw, e.sw);
+    e.post_cost = step_cost(w, 0, w.size());
+    e.cost = step_cost(w0, 0, s) + std::ldexp(e.post_cost, k);
+  };
+  int nt = opts.threads > 0 ? opts.threads : (int)std::thread::hardware_concurrency();
+  nt = std::max(1, std::min({nt, 16, (int)cands.size()}));
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      for (size_t i = next++; i < cands.size(); i = next++) run(i);
+    });
+  for (auto& th : pool) th.join();
+  size_t bi = 0;
+  for (size_t i = 1; i < evals.size(); ++i) {
+    const Eval &a = evals[i], &b = evals[bi];
+    if (a.width < b.width || (a.width == b.width && a.cost < b.cost)) bi = i;
+  }
+  Eval& be = evals[bi];
+  if ((int)be.sl.size() != k) return fail(QT_EPLAN, "qt_plan_slicing: not enough vertices to slice");
+  out.s = cands[bi];
+  out.width = be.width;
+  out.pw = be.pw;
+  out.sw = be.sw;
+  out.unsliced = unsliced;
+  out.peak = peak;
+  out.pre.assign(order0.begin(), order0.begin() + out.s);
+  out.pre_cost = step_cost(w0, 0, out.s);
+  out.post_cost = be.post_cost;
+  out.post = std::move(be.post);
+  out.sl = std::move(be.sl);
+  out.cands = cands;
+  out.cand_width.clear();
+  for (const Eval& e : evals) out.cand_width.push_back(e.width);
+  return QT_OK;
+}
+
+}  // namespace
+}  // namespace qt
+
 extern "C" qt_status qt_plan_slicing(const qt_network* net, const qt_slicing_opts* opts,
                                      int32_t* order_out, int32_t* n_order_out,
                                      int32_t* slice_vars_out, qt_slicing_result* result,
                                      int32_t* width_by_step) {
   try {
-    if (!net || !opts || !order_out || !n_order_out || !result || (opts->n_slice_vars > 0 && !slice_vars_out))
+    if (!net || !opts || !order_out || !n_order_out || !result || (opts->n_slice_vars > 0 && !slice_vars_out) ||
+        (opts->n_exclude > 0 && !opts->exclude))
       return fail(QT_EINVAL, "qt_plan_slicing: null argument");
     if (opts->algo < 0 || opts->algo > 2) return fail(QT_EINVAL, "qt_plan_slicing: unknown algo");
     const int k = opts->n_slice_vars;
     const int V = net->n_vars();
     if (k < 0 || k >= V || k > 40) return fail(QT_EINVAL, "qt_plan_slicing: n_slice_vars out of range");
-    const Graph g0 = build_graph(*net);
-    std::vector<int32_t> order0, w0;
-    best_greedy(g0, opts->algo, opts->tau, opts->repeats, opts->seed, order0, w0);
-    const int unsliced = max_of(w0, 0, w0.size());
-    int peak = 0;
-    while (peak < (int)w0.size() && w0[peak] != unsliced) ++peak;
-
-    std::vector<int> cands;
-    if (k == 0) {
-      cands.push_back(0);
-    } else if (opts->max_candidates <= 0 || opts->max_candidates >= peak + 1) {
-      for (int s = 0; s <= peak; ++s) cands.push_back(s);
-    } else {
-      int m = opts->max_candidates;
-      for (int i = 0; i < m; ++i) cands.push_back((int)((int64_t)i * peak / std::max(1, m - 1)));
-      cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+    const int r = opts->group_size <= 0 || opts->group_size >= k ? k : opts->group_size;
+    if (k > 0 && (k + r - 1) / r > QT_MAX_SLICE_GROUPS)
+      return fail(QT_EINVAL, "qt_plan_slicing: more than QT_MAX_SLICE_GROUPS groups");
+    Graph g = build_graph(*net);
+    for (int i = 0; i < opts->n_exclude; ++i) {  // held (open) variables: deleted without fill
+      const int e = opts->exclude[i];
+      if (e < 0 || e >= net->n_vars_ext || net->int_of[e] < 0)
+        return fail(QT_EINVAL, "qt_plan_slicing: exclude id not a variable of the network");
+      if (g.alive[net->int_of[e]]) g.remove(net->int_of[e]);
     }
-    struct Eval {
-      int width = std::numeric_limits<int>::max(), pw = 0, sw = 0;
-      double cost = 0;
-      std::vector<int32_t> post, sl;
-    };
-    std::vector<Eval> evals(cands.size());
-    auto run = [&](size_t ci) {
-      const int s = cands[ci];
-      Graph g = g0;
-      for (int i = 0; i < s; ++i) g.eliminate(order0[i]);
-      Eval& e = evals[ci];
-      for (int j = 0; j < k; ++j) {
-        int best = -1;
-        for (int v = 0; v < g.V; ++v)
-          if (g.alive[v] && (best < 0 || g.deg[v] > g.deg[best])) best = v;
-        if (best < 0) break;
-        e.sl.push_back(best);
-        g.remove(best);
+    // Section VI-D: r variables at a time, each group at its own best step
+    // of the expression sliced by the groups before it.
+    int n = 0, nsl = 0, left = k, cum = 0, pw = 0, sw = 0, ng = 0;
+    double cost = 0;
+    Sweep first;
+    do {
+      const int rg = std::min(r, left);
+      Sweep S;
+      QT_TRY(sweep(g, rg, *opts, S));
+      if (ng == 0) first = S;
+      for (int v : S.pre) {
+        g.eliminate(v);
+        order_out[n++] = net->ext_of[v];
       }
-      std::vector<int32_t> w;
-      best_greedy(g, opts->algo, opts->tau, opts->repeats, opts->seed + 1000003ull * (s + 1), e.post, w);
-      e.pw = max_of(w0, 0, s);
-      e.sw = max_of(w, 0, w.size());
-      e.width = std::max(e.pw, e.sw);
-      e.cost = step_cost(w0, 0, s) + std::ldexp(step_cost(w, 0, w.size()), k);
-    };
-    int nt = opts->threads > 0 ? opts->threads : (int)std::thread::hardware_concurrency();
-    nt = std::max(1, std::min({nt, 16, (int)cands.size()}));
-    std::atomic<size_t> next{0};
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nt; ++t)
-      pool.emplace_back([&] {
-        for (size_t i = next++; i < cands.size(); i = next++) run(i);
-      });
-    for (auto& th : pool) th.join();
-
-    size_t bi = 0;
-    for (size_t i = 1; i < evals.size(); ++i) {
-      const Eval &a = evals[i], &b = evals[bi];
-      if (a.width < b.width || (a.width == b.width && a.cost < b.cost)) bi = i;
-    }
-    const Eval& be = evals[bi];
-    if ((int)be.sl.size() != k) return fail(QT_EPLAN, "qt_plan_slicing: not enough vertices to slice");
-    const int s = cands[bi];
-    int n = 0;
-    for (int i = 0; i < s; ++i) order_out[n++] = net->ext_of[order0[i]];
-    for (int v : be.post) order_out[n++] = net->ext_of[v];
+      for (int v : S.sl) {
+        g.remove(v);
+        slice_vars_out[nsl++] = net->ext_of[v];
+      }
+      cost += std::ldexp(S.pre_cost, k - left);
+      cum += S.s;
+      pw = std::max(pw, S.pw);
+      if (rg > 0) {
+        result->group_step[ng] = cum;
+        result->group_len[ng] = rg;
+        ++ng;
+      }
+      left -= rg;
+      if (left == 0) {
+        for (int v : S.post) order_out[n++] = net->ext_of[v];
+        sw = S.sw;
+        cost += std::ldexp(S.post_cost, k);
+      }
+    } while (left > 0);
     *n_order_out = n;
-    for (int j = 0; j < k; ++j) slice_vars_out[j] = net->ext_of[be.sl[j]];
-    result->step = s;
-    result->width = be.width;
-    result->prefix_width = be.pw;
-    result->slice_width = be.sw;
-    result->unsliced_width = unsliced;
-    result->peak_step = peak;
-    result->cost = be.cost;
+    result->n_groups = ng;
+    result->step = ng ? result->group_step[0] : 0;
+    result->width = std::max(pw, sw);
+    result->prefix_width = pw;
+    result->slice_width = sw;
+    result->unsliced_width = first.unsliced;
+    result->peak_step = first.peak;
+    result->cost = cost;
     if (width_by_step) {
       for (int i = 0; i <= V; ++i) width_by_step[i] = -1;
-      for (size_t i = 0; i < cands.size(); ++i) width_by_step[cands[i]] = evals[i].width;
+      for (size_t i = 0; i < first.cands.size(); ++i) width_by_step[first.cands[i]] = first.cand_width[i];
     }
     return QT_OK;
   } catch (const std::exception& ex) {

@@ -56,6 +56,7 @@ namespace qt {
 constexpr int kMaxIn = 8;
 constexpr int kMaxRuns = 16;  // a 31-bit mask has at most 16 runs
 constexpr int kMaxRank = 31;
+constexpr int kMaxOpen = 20;  // open output variables of a plan
 
 // One input of a bucket step.  Element index of the value for output
 // element x of batch item (pt, sb) with slice id sid:
@@ -361,6 +362,8 @@ struct DevLeaf {
 struct DevFinal {
   int32_t n_factors;
   int32_t lg_nsb;
+  int32_t n_open;        // open output bits j: factor f is read at pext(j, its runs), see k_final
+  int32_t pad;
   int64_t chunk_base;
   int64_t slice_begin;   // per-slice output index = sid - slice_begin
   int64_t n_range;       // number of slices in the output range (row length)
@@ -441,6 +444,8 @@ struct qt_plan {
   std::vector<int32_t> order;       // internal ids
   int32_t slice_step = 0;           // s
   std::vector<int32_t> slice_vars;  // internal ids, first = most significant
+  int32_t n_groups = 0;             // slice groups as given (all fixed at the last group's step)
+  std::vector<int32_t> open_vars;   // open output variables, first = most significant output bit
   std::vector<int32_t> key;         // per internal var
   std::vector<qt::SymTensor> tensors;
   std::vector<qt::SymStep> steps;

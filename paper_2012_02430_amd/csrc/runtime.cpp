@@ -198,12 +198,14 @@ struct qt_plan::Profile {
   bool enabled = false;
   struct Rec {
     int kclass;
+    int op;  // plan step (streaming, GEMM), LDS segment, or -1 (other kernels)
     double bytes, flops;
     hipEvent_t a, b;
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   qt_kernel_stats acc[QT_KCLASS_COUNT] = {};
+  std::vector<qt_op_stats> ops;  // per (class, op), in order of first launch
 
   hipEvent_t get() {
     if (!pool.empty()) {
@@ -230,6 +232,17 @@ struct qt_plan::Profile {
       k.ms += ms;
       k.bytes += r.bytes;
       k.flops += r.flops;
+      qt_op_stats* o = nullptr;
+      for (auto& x : ops)
+        if (x.kclass == r.kclass && x.op == r.op) o = &x;
+      if (!o) {
+        ops.push_back(qt_op_stats{r.kclass, r.op, 0, 0.0, 0.0, 0.0});
+        o = &ops.back();
+      }
+      o->launches += 1;
+      o->ms += ms;
+      o->bytes += r.bytes;
+      o->flops += r.flops;
       pool.push_back(r.a);
       pool.push_back(r.b);
     }
@@ -269,7 +282,7 @@ namespace qt {
 namespace {
 // Records a HIP event pair around `launch` when profiling is on.
 template <class F>
-hipError_t timed(qt_plan& plan, hipStream_t stream, int kclass, double bytes, double flops, F launch) {
+hipError_t timed(qt_plan& plan, hipStream_t stream, int kclass, int op, double bytes, double flops, F launch) {
   qt_plan::Profile* pr = plan.prof.get();
   if (!pr || !pr->enabled) return launch();
   hipEvent_t a = pr->get(), b = pr->get();
@@ -280,7 +293,7 @@ hipError_t timed(qt_plan& plan, hipStream_t stream, int kclass, double bytes, do
   if (e != hipSuccess) return e;
   e = hipEventRecord(b, stream);
   if (e != hipSuccess) return e;
-  pr->pending.push_back({kclass, bytes, flops, a, b});
+  pr->pending.push_back({kclass, op, bytes, flops, a, b});
   return hipSuccess;
 }
 }  // namespace
@@ -352,9 +365,9 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
 //  * groups each segment's steps into dependency levels;
 //  * places every tensor produced and consumed inside a segment in LDS when
 //    it fits (first-fit over level intervals, largest first);
-//  * lays out the global arenas over schedule time (a streaming step is one
-//    tick, a segment's level L is tick start + L), so buffers of steps that
-//    run concurrently inside a segment never share memory.
+//  * lays out the global arenas over schedule time (every launch is one
+//    tick), so no two global buffers that one launch reads or writes share
+//    memory.
 qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   ws.prefix_ops.clear();
   ws.slice_ops.clear();
@@ -493,7 +506,11 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
         ws.seg_of[st.producer] == ws.seg_of[st.consumer])
       return fail(QT_EPLAN, "internal: a global tensor is written and read inside one launch");
   }
-  // schedule time of every step
+  // Schedule time of every launch: one tick each.  The workgroups of a
+  // launch do not run in step (with more items than fit the device at once,
+  // later ones start after earlier ones have finished), so every global
+  // tensor a launch reads or writes is live over its whole launch: a
+  // segment's outputs must never share memory with the inputs it stages.
   std::vector<int> when(nsteps, 0);
   int clock = 0;
   for (auto* ops : {&ws.prefix_ops, &ws.slice_ops}) {
@@ -501,8 +518,8 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       if (op.seg < 0) {
         when[op.step] = clock++;
       } else {
-        for (int i : ws.segs[op.seg].steps) when[i] = clock + ws.depth[i];
-        clock += ws.segs[op.seg].n_levels;
+        for (int i : ws.segs[op.seg].steps) when[i] = clock;
+        ++clock;
       }
     }
   }
@@ -918,7 +935,7 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     QT_TRY(dev_alloc(&ws.dleaves, (int64_t)plan.dev_leaves.size(), b));
     QT_TRY(dev_alloc(&ws.ddense, (int64_t)plan.dense_table.size(), b));
     QT_TRY(dev_alloc(&ws.dfinal, (int64_t)plan.finals.size(), b));
-    QT_TRY(dev_alloc(&ws.sums, (int64_t)np * 3, b));
+    QT_TRY(dev_alloc(&ws.sums, ((int64_t)np << plan.open_vars.size()) * 3, b));
     QT_HIP_CHECK(hipMemcpy(ws.dleaves, plan.dev_leaves.data(), plan.dev_leaves.size() * sizeof(DevLeaf),
                            hipMemcpyHostToDevice));
     QT_HIP_CHECK(hipMemcpy(ws.ddense, plan.dense_table.data(), plan.dense_table.size() * sizeof(double),
@@ -961,15 +978,22 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
       ws.steps.push_back(d);
     }
     ws.finals.clear();
+    const int n_open = (int)plan.open_vars.size();
     for (int t : plan.finals) {
       const SymTensor& st = plan.tensors[t];
-      uint32_t smask = 0;
-      if (st.level == 0)
-        for (int x : st.vars)
+      // slice bits (a prefix tensor is read at the slice's block) and the
+      // output bits of its open variables (key n_order + bit)
+      uint32_t smask = 0, omask = 0;
+      for (int x : st.vars) {
+        const int kx = plan.key[x];
+        if (kx >= plan.n_order && kx < plan.n_order + n_open) omask |= 1u << (kx - plan.n_order);
+        if (st.level == 0)
           for (int j = 0; j < k; ++j)
             if (plan.slice_vars[j] == x) smask |= 1u << (k - 1 - j);
+      }
       DevIn d;
-      build_in(plan, ws, t, 0, 0, smask, 0, elt, d);
+      if (!build_in(plan, ws, t, omask, 0, smask, __builtin_popcount(omask), elt, d))
+        return fail(QT_EUNSUPPORTED, "closing tensor index map too fragmented");
       ws.finals.push_back(d);
     }
     if (!ws.finals.empty())
@@ -983,14 +1007,15 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     }
     plan.info.slice_batch = chunk;
   }
-  if (ws.per_slice_cap < (int64_t)np * n_range) {
+  const int64_t rows = (int64_t)np << plan.open_vars.size();  // (point, open output) rows of results
+  if (ws.per_slice_cap < rows * n_range) {
     ws.gen = next_ws_gen();
     if (ws.per_slice) (void)hipFree(ws.per_slice);
     ws.per_slice = nullptr;
     ws.per_slice_cap = 0;
     int64_t dummy = 0;
-    QT_TRY(dev_alloc(&ws.per_slice, (int64_t)np * n_range * 3, dummy));
-    ws.per_slice_cap = (int64_t)np * n_range;
+    QT_TRY(dev_alloc(&ws.per_slice, rows * n_range * 3, dummy));
+    ws.per_slice_cap = rows * n_range;
   }
   plan.info.workspace_bytes = ws.bytes + ws.per_slice_cap * 24;
   return QT_OK;
@@ -1007,7 +1032,8 @@ qt_status upload_params(qt_plan& plan, int np, const double* gammas, const doubl
 }
 
 // Runs one plan at np points over slices [begin, end); leaves the per-slice
-// values in ws.per_slice ([np][end - begin][3]) and the sums in ws.sums.
+// values in ws.per_slice ([np][2^a][end - begin][3], a open output bits) and
+// the sums in ws.sums ([np][2^a][3]).
 qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
                    int64_t stop, hipStream_t stream) {
   const bool c128 = plan.precision == QT_C128;
@@ -1019,13 +1045,13 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
   int launches = 0;
   QT_TRY(upload_params(plan, np, gammas, betas, stream));
   const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
-  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
     return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params, plan.net.p,
                          np, ws.leaves, c128, stream);
   }));
   ++launches;
   if (scaled && ws.exp1_base) {
-    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0,
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
                        [&] { return launch_fill_u32(ws.maxbits, ws.exp1_base, 0u, stream); }));
     ++launches;
   }
@@ -1033,7 +1059,7 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
     const SymStep& st = plan.steps[i];
     const double items = (double)(ws.step_elems[i] >> st.rank);
     const int kc = st.rank >= 10 ? QT_KCLASS_STEP_STREAM : QT_KCLASS_STEP_SMALL;
-    return timed(plan, stream, kc, st.bytes_c64 * eb * items, st.flops * items, [&] {
+    return timed(plan, stream, kc, i, st.bytes_c64 * eb * items, st.flops * items, [&] {
       return launch_step(d, c128, scaled, ws.exps, ws.maxbits, ws.step_elems[i], stream, &launches, nullptr);
     });
   };
@@ -1043,7 +1069,7 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
       g.chunk_base = cb;
       const SymStep& st = plan.steps[op.step];
       ++launches;
-      return timed(plan, stream, QT_KCLASS_GEMM, st.bytes_c64 * g.n_items, st.flops * g.n_items,
+      return timed(plan, stream, QT_KCLASS_GEMM, op.step, st.bytes_c64 * g.n_items, st.flops * g.n_items,
                    [&] { return launch_gemm(g, scaled, ws.exps, ws.maxbits, stream); });
     }
     if (op.seg < 0) {
@@ -1060,20 +1086,21 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
     x.lg_nsb = S.level == 1 ? ilog2(ws.chunk) : 0;
     const int64_t items = (int64_t)np * (S.level == 1 ? ws.chunk : 1);
     ++launches;
-    return timed(plan, stream, QT_KCLASS_LDS, S.bytes_c64 * eb * items, S.flops * items, [&] {
+    return timed(plan, stream, QT_KCLASS_LDS, op.seg, S.bytes_c64 * eb * items, S.flops * items, [&] {
       return launch_lds_exec(x, items, ws.waves, c128, scaled, ws.exps, ws.maxbits, stream);
     });
   };
   for (const auto& op : ws.prefix_ops) QT_HIP_CHECK(run_op(op, 0));
   DevFinal f{};
   f.n_factors = (int)ws.finals.size();
+  f.n_open = (int)plan.open_vars.size();
   f.slice_begin = begin;
   f.n_range = n_range;
   f.log2_const = plan.log2_const;
   if (k == 0) {
     f.lg_nsb = 0;
     f.chunk_base = 0;
-    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
       return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream);
     }));
     ++launches;
@@ -1081,7 +1108,7 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
     const int64_t C = ws.chunk;
     for (int64_t cb = begin & ~(C - 1); cb < stop; cb += C) {
       if (scaled && ws.exp1_count) {
-        QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+        QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
           return launch_fill_u32(ws.maxbits + ws.exp1_base, ws.exp1_count, 0u, stream);
         }));
         ++launches;
@@ -1089,15 +1116,15 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
       for (const auto& op : ws.slice_ops) QT_HIP_CHECK(run_op(op, cb));
       f.lg_nsb = ilog2(C);
       f.chunk_base = cb;
-      QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0, [&] {
+      QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
         return launch_final(f, ws.dfinal, np, (int64_t)np * C, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, stop,
                             stream);
       }));
       ++launches;
     }
   }
-  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, 0, 0,
-                     [&] { return launch_slice_sum(ws.per_slice, np, n_range, ws.sums, stream); }));
+  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
+                     [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, ws.sums, stream); }));
   ++launches;
   if (ws.trace_on) {
     QT_HIP_CHECK(hipStreamSynchronize(stream));
@@ -1151,11 +1178,12 @@ qt_status enqueue_device(qt_plan& plan, int np, const double* gammas, const doub
   const int64_t n_range = end - begin;
   QT_TRY(run_plan(plan, np, gammas, betas, begin, end, end, stream));
   auto& ws = *plan.ws;
+  const size_t rows = (size_t)np << plan.open_vars.size();
   if (per_slice_out) {
     const size_t row = (size_t)n_range * 3 * sizeof(double);
-    QT_TRY(copy_2d(per_slice_out, row, ws.per_slice, row, row, np, stream));
+    QT_TRY(copy_2d(per_slice_out, row, ws.per_slice, row, row, rows, stream));
   }
-  const size_t bytes = (size_t)np * sizeof(qt_amp);
+  const size_t bytes = rows * sizeof(qt_amp);
   return copy_2d(out, bytes, ws.sums, bytes, bytes, 1, stream);
 }
 
@@ -1215,15 +1243,19 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
     if (!plans || n_plans <= 0 || n_points <= 0 || !out) return fail(QT_EINVAL, "qt_contract_batch: bad arguments");
     const int p = plans[0] ? plans[0]->net.p : 0;
     if (p > 0 && (!gammas || !betas)) return fail(QT_EINVAL, "qt_contract_batch: null parameters");
+    const int n_open = plans[0] ? (int)plans[0]->open_vars.size() : 0;
     for (int i = 0; i < n_plans; ++i) {
       if (!plans[i]) return fail(QT_EINVAL, "qt_contract_batch: null plan");
       if (plans[i]->net.p != p) return fail(QT_EINVAL, "qt_contract_batch: plans differ in p");
+      if ((int)plans[i]->open_vars.size() != n_open)
+        return fail(QT_EINVAL, "qt_contract_batch: plans differ in their number of open variables");
       const int64_t ns = 1ll << plans[i]->slice_vars.size();
       if (slice_begin < 0 || slice_end > ns || slice_begin >= slice_end)
         return fail(QT_EINVAL, "qt_contract_batch: slice range outside [0, n_slices)");
     }
-    if ((slice_end - slice_begin) * n_points > (1ll << 28))
+    if (((slice_end - slice_begin) * n_points << n_open) > (1ll << 28))
       return fail(QT_EINVAL, "qt_contract_batch: slice range too long for one call");
+    const int64_t rows = (int64_t)n_points << n_open;  // results per plan
     hipStream_t stream = (hipStream_t)hip_stream;
     int64_t stop = slice_end;
     bool injected = false;
@@ -1249,12 +1281,11 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
       if (per_slice_out && stop > slice_begin) {
         const size_t row = (size_t)n_range * 3 * sizeof(double);
         const size_t width = (size_t)(stop - slice_begin) * 3 * sizeof(double);
-        QT_TRY(copy_2d(per_slice_out + (size_t)i * n_points * n_range * 3, row, ws.per_slice, row, width, n_points,
-                       stream));
+        QT_TRY(copy_2d(per_slice_out + (size_t)i * rows * n_range * 3, row, ws.per_slice, row, width, rows, stream));
       }
       if (!injected) {
-        const size_t bytes = (size_t)n_points * sizeof(qt_amp);
-        QT_TRY(copy_2d(out + (size_t)i * n_points, bytes, ws.sums, bytes, bytes, 1, stream));
+        const size_t bytes = (size_t)rows * sizeof(qt_amp);
+        QT_TRY(copy_2d(out + (size_t)i * rows, bytes, ws.sums, bytes, bytes, 1, stream));
       }
     }
     if (injected) return fail(QT_EFAULT_INJECTED, "qt_contract_batch: QT_FAULT_AFTER_SLICE fired");
@@ -1305,7 +1336,9 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
     qt_plan::Workspace ws;
     const int elt = plan->precision == QT_C128 ? 16 : 8;
     QT_TRY(plan_schedule(const_cast<qt_plan&>(*plan), ws, elt));
-    std::string j = "{\"element_bytes\":" + std::to_string(elt) + ",\"segments\":[";
+    std::string j = "{\"element_bytes\":" + std::to_string(elt) + ",\"n_open\":" +
+                    std::to_string(plan->open_vars.size()) + ",\"n_groups\":" + std::to_string(plan->n_groups) +
+                    ",\"segments\":[";
     for (size_t si = 0; si < ws.segs.size(); ++si) {
       const auto& S = ws.segs[si];
       int staged = 0, internal = 0;
@@ -1394,8 +1427,25 @@ extern "C" qt_status qt_profile_read(qt_plan* plan, qt_kernel_stats* out, int32_
   if (!plan->prof) plan->prof = std::make_unique<qt_plan::Profile>();
   QT_HIP_CHECK(plan->prof->drain());
   for (int i = 0; i < QT_KCLASS_COUNT; ++i) out[i] = plan->prof->acc[i];
-  if (reset)
+  if (reset) {
     for (auto& a : plan->prof->acc) a = qt_kernel_stats{};
+    plan->prof->ops.clear();
+  }
+  return QT_OK;
+}
+
+extern "C" qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int32_t* n_ops,
+                                         int32_t reset) {
+  if (!plan || !n_ops || (cap > 0 && !out)) return fail(QT_EINVAL, "qt_profile_read_ops: null argument");
+  if (!plan->prof) plan->prof = std::make_unique<qt_plan::Profile>();
+  QT_HIP_CHECK(plan->prof->drain());
+  const auto& ops = plan->prof->ops;
+  *n_ops = (int32_t)ops.size();
+  for (int32_t i = 0; i < cap && i < (int32_t)ops.size(); ++i) out[i] = ops[i];
+  if (reset) {
+    for (auto& a : plan->prof->acc) a = qt_kernel_stats{};
+    plan->prof->ops.clear();
+  }
   return QT_OK;
 }
 

@@ -34,10 +34,16 @@ class NetworkSpec:
         return vs
 
 
-def amplitude_network(n: int, edges, p: int, z=None) -> NetworkSpec:
+def amplitude_network(n: int, edges, p: int, z=None, open_qubits=()) -> NetworkSpec:
     """<z| U(gamma, beta) |+^n>: |+> on layer-0 variables, per layer one ZZ
-    per edge and one RX per qubit, <z_q| on the last variable of each wire."""
+    per edge and one RX per qubit, <z_q| on the last variable of each wire.
+
+    Qubits in ``open_qubits`` get no <z_q|: their last variables
+    (``open_vars(n, p, open_qubits)``) stay open, and a plan that leaves them
+    open gives the amplitudes of all 2^a values of those qubits at once (a
+    batch of amplitudes, Section VII)."""
     spec = NetworkSpec(n_vars=(p + 1) * n, p=p)
+    opened = set(int(q) for q in open_qubits)
     for q in range(n):
         spec.add(L.QT_T_VEC_PLUS, 0, q)
     for k in range(1, p + 1):
@@ -47,9 +53,17 @@ def amplitude_network(n: int, edges, p: int, z=None) -> NetworkSpec:
         for q in range(n):
             spec.add(L.QT_T_RX, k, lo + q, lo + n + q)
     for q in range(n):
+        if q in opened:
+            continue
         bit = 0 if z is None else int(z[q])
         spec.add(L.QT_T_BRA_BIT, bit, p * n + q)
     return spec
+
+
+def open_vars(n: int, p: int, open_qubits) -> list:
+    """Variables of the open qubits' last layer, in the order given (the
+    first is the most significant bit of the output index)."""
+    return [p * n + int(q) for q in open_qubits]
 
 
 def edge_lightcone(n: int, edges, u: int, v: int, p: int):

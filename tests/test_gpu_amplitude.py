@@ -308,3 +308,87 @@ def test_c4_fused_gemm_per_slice_parity():
         err = np.abs(got[0] - want[0]).max() / np.abs(want[0]).max()
         print(f"n=210 slices [{lo},{hi}): max rel err {err:.2e}", flush=True)
         assert err < TOL["c64"], (lo, err)
+
+
+def _open_case(n, p, a, seed):
+    edges = regular_graph(n, 3, 0)
+    rng = np.random.default_rng(seed)
+    open_q = [int(q) for q in rng.choice(n, a, replace=False)]
+    net = api.Network(N.amplitude_network(n, edges, p, open_qubits=open_q))
+    return edges, open_q, net, N.open_vars(n, p, open_q)
+
+
+def _oracle_open_network(n, edges, g, b, open_q, p):
+    opened = {oracle.ket_var(n, q, p) for q in open_q}
+    return [t for t in oracle.amplitude_network(n, edges, g, b) if not (len(t[1]) == 1 and t[1][0] in opened)]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("a", [4, 8])
+def test_c2_open_outputs_per_slice_parity(precision, a):
+    # a batch of 2^a amplitudes (Section VII) from one contraction of the
+    # 60-qubit, p = 2 plan with 256 slices: the open qubits' last variables
+    # are held; every per-slice output tensor against the oracle's
+    n, p, k = 60, 2, 8
+    edges, open_q, net, ov = _open_case(n, p, a, seed=a)
+    sch = net.plan_slicing(k, algo="min_fill", exclude=ov)
+    plan = api.Plan(net, sch.order, sch.groups, precision=precision, open_vars=ov)
+    assert plan.info().n_open == a
+    g, b = qaoa_params(p, 2, seed=20 + a)
+    tot, per = plan.contract_batch(g, b, per_slice=True)
+    assert tot.shape == (2, 1 << a) and per.shape == (2, 1 << a, 256)
+    for i in range(2):
+        T = _oracle_open_network(n, edges, g[i], b[i], open_q, p)
+        want = oracle.sliced_values(T, sch.order, sch.groups, open_vars=ov)  # [slice][j]
+        assert slice_err(per[i].T, want) < TOL[precision]
+        ws = want.sum(axis=0)
+        assert np.abs(tot[i] - ws).max() / np.abs(ws).max() < TOL[precision]
+    # one entry against a plain amplitude of the same bitstring
+    j = 5
+    z = np.zeros(n, dtype=np.uint8)
+    for q_i, q in enumerate(open_q):
+        z[q] = (j >> (a - 1 - q_i)) & 1
+    full = api.Network(N.amplitude_network(n, edges, p, z))
+    order_z, _ = full.order_greedy("min_fill")
+    single = api.Plan(full, order_z, precision="c128").contract_amplitude(g[0], b[0])
+    assert abs(tot[0][j] - single) / abs(single) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("r", [4, 2])
+def test_c2_slice_groups_per_slice_parity(precision, r):
+    # Section VI-D with r < n: 8 slice variables in groups of r, each group
+    # at its own step; per-slice values against the oracle's branched
+    # schedule (group by group, first variable most significant)
+    n, p, k = 60, 2, 8
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(k, algo="min_fill", group_size=r)
+    assert len(sch.groups) == k // r
+    plan = api.Plan(net, sch.order, sch.groups, precision=precision)
+    assert plan.info().n_groups == k // r
+    g, b = qaoa_params(p, 1, seed=30 + r)
+    tot, per = plan.contract_batch(g, b, per_slice=True)
+    want = oracle.sliced_values(oracle.amplitude_network(n, edges, g[0], b[0]), sch.order, sch.groups)
+    assert slice_err(per[0], want) < TOL[precision]
+    assert rel(tot[0], want.sum()) < TOL[precision]
+
+
+def test_c4_slice_groups_per_slice_parity():
+    # the 210-qubit p = 1 amplitude with two groups of 4 slice variables
+    # (each at its own step), fused GEMM buckets, against the plain
+    # complex128 path on two slice ranges
+    n, p = 210, 1
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(8, algo="min_degree", group_size=4)
+    assert len(sch.groups) == 2 and sch.groups[0][0] < sch.groups[1][0]
+    fused = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32")
+    plain = api.Plan(net, sch.order, sch.groups, precision="c128", slice_batch=1, plain=True)
+    g, b = qaoa_params(p, 1, seed=13)
+    for lo, hi in ((0, 2), (77, 79)):
+        _, got = fused.contract_batch(g, b, lo, hi, per_slice=True)
+        _, want = plain.contract_batch(g, b, lo, hi, per_slice=True)
+        err = np.abs(got[0] - want[0]).max() / np.abs(want[0]).max()
+        print(f"n=210 two groups, slices [{lo},{hi}): max rel err {err:.2e}", flush=True)
+        assert err < TOL["c64"], (lo, err)

@@ -124,9 +124,51 @@ def test_plan_validation():
     assert _plan_status(net, order[1:], [(0, [order[0], order[0]])]) == L.QT_EPLAN
     assert _plan_status(net, order, [(0, [order[0]])]) == L.QT_EPLAN    # sliced and ordered
     assert _plan_status(net, order[1:], [(len(order), [order[0]])]) == L.QT_EPLAN  # step > n_order
-    assert _plan_status(net, order[2:], [(0, [order[0]]), (1, [order[1]])]) == L.QT_EUNSUPPORTED
+    assert _plan_status(net, order[2:], [(0, [order[0]]), (1, [order[1]])]) == L.QT_OK  # two groups (r < n)
+    assert _plan_status(net, order[2:], [(2, [order[0]]), (1, [order[1]])]) == L.QT_EPLAN  # steps decrease
     assert _plan_status(net, order + [999]) == L.QT_EPLAN
     assert _plan_status(net, order[1:], [(3, [order[0]])]) == L.QT_OK
+
+
+def test_open_variable_validation():
+    n, p = 8, 1
+    edges = regular_graph(n, 3, 0)
+    spec = N.amplitude_network(n, edges, p, open_qubits=[2, 5])
+    net = api.Network(spec)
+    ov = N.open_vars(n, p, [2, 5])
+    order, _ = net.order_greedy("min_fill", exclude=ov)
+    pl = api.Plan(net, order, open_vars=ov)
+    assert pl.info().n_open == 2 and pl.describe()["n_open"] == 2
+    with pytest.raises(L.QTError) as e:  # open variables left out of the plan
+        api.Plan(net, order)
+    assert e.value.status == L.QT_EPLAN
+    with pytest.raises(L.QTError) as e:  # an open variable also in the order
+        api.Plan(net, order + [ov[0]], open_vars=ov)
+    assert e.value.status == L.QT_EPLAN
+    with pytest.raises(L.QTError) as e:
+        api.Plan(net, order, open_vars=[ov[0], ov[0]])
+    assert e.value.status == L.QT_EPLAN
+
+
+@pytest.mark.parametrize("r", [2, 3])
+def test_slicing_groups_r_less_than_n(r):
+    # Section VI-D with r < n: groups of r variables, each at its own step of
+    # the already-sliced expression; steps non-decreasing, all variables
+    # distinct, the order covers every other variable
+    n, p, k = 60, 2, 6
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(k, algo="min_fill", group_size=r)
+    one = net.plan_slicing(k, algo="min_fill")
+    assert len(sch.groups) == (k + r - 1) // r
+    assert [len(v) for _, v in sch.groups] == [min(r, k - i * r) for i in range(len(sch.groups))]
+    steps = [s for s, _ in sch.groups]
+    assert steps == sorted(steps) and steps[0] == sch.step
+    sl = [v for _, vs in sch.groups for v in vs]
+    assert len(set(sl)) == k and not set(sl) & set(sch.order)
+    assert set(sl) | set(sch.order) == net.spec.variables()
+    assert sch.width <= one.unsliced_width
+    api.Plan(net, sch.order, sch.groups)  # accepted
 
 
 def test_network_validation():

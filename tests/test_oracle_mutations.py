@@ -53,6 +53,17 @@ def _pins_hold():
         want = oracle.contract(T + [(e1, (3,)), (e0, (8,))])
         if abs(vals[2] - want) > 1e-12 * abs(want):
             return False
+        # batch of amplitudes: index bit a-1-i is the value of open qubit i;
+        # a second component (a K4 with no open qubit) closes to a scalar
+        e2 = edges + [(6, 7), (6, 8), (6, 9), (7, 8), (7, 9), (8, 9)]
+        z2 = random_bitstring(10, 5)
+        oq = [4, 1]
+        amps = oracle.amplitudes_open(10, e2, g, b, oq, z2)
+        for j in range(4):
+            zz = z2.copy()
+            zz[4], zz[1] = (j >> 1) & 1, j & 1
+            if abs(amps[j] - oracle.amplitude_sv(10, e2, g, b, zz)) > 1e-12 * 2.0 ** -5 * 8:
+                return False
         return True
     except Exception:
         return False
@@ -132,6 +143,17 @@ def _sum_out_first_axis(R, v, tangent=False):
     return r.sum(axis=int(tangent)), vr[1:]
 
 
+_orig_open_tensor = bucket.open_tensor
+
+
+def _open_tensor_lsb_first(remaining, scalar, open_vars):
+    return _orig_open_tensor(remaining, scalar, list(reversed(open_vars)))
+
+
+def _open_tensor_drops_scalar(remaining, scalar, open_vars):
+    return _orig_open_tensor(remaining, 1.0, open_vars)
+
+
 MUTATIONS = [
     ("gates.rx sign", gates, "rx", _rx_wrong_sign),
     ("gates.zz sign", gates, "zz", _zz_wrong_sign),
@@ -143,6 +165,8 @@ MUTATIONS = [
     ("slice bits least significant first", bucket, "fix", _fix_lsb_first),
     ("Leibniz rule drops a term", bucket, "_product", _product_leibniz_half),
     ("sum over the wrong variable", bucket, "_sum_out", _sum_out_first_axis),
+    ("open outputs least significant first", bucket, "open_tensor", _open_tensor_lsb_first),
+    ("open outputs drop the closed scalars", bucket, "open_tensor", _open_tensor_drops_scalar),
 ]
 
 

@@ -237,3 +237,39 @@ def test_gradient_p1_closed_form():
         cg = oracle.edge_energy_p1(edges, u, v, g[0, 0] + 1j * h, b[0, 0]).imag / h
         cb = oracle.edge_energy_p1(edges, u, v, g[0, 0], b[0, 0] + 1j * h).imag / h
         assert abs(row[0] - cg) < 1e-13 and abs(row[1] - cb) < 1e-13
+
+
+# -------------------------------------------------------- batch of amplitudes
+@pytest.mark.parametrize("n,p,open_q", [(10, 2, [3, 7, 0]), (12, 1, [11, 2, 5, 8]), (8, 3, [6])])
+def test_open_amplitudes_vs_statevector(n, p, open_q):
+    # a contraction with the open qubits' last variables held gives, at
+    # index j, the amplitude of the bitstring whose open qubit open_q[i] is
+    # bit a-1-i of j (others 0): checked against the state vector for every j
+    edges = regular_graph(n, 3, 1)
+    g, b = qaoa_params(p, 1, seed=n + p)
+    got = oracle.amplitudes_open(n, edges, g[0], b[0], open_q)
+    a = len(open_q)
+    assert got.shape == (1 << a,)
+    for j in range(1 << a):
+        z = np.zeros(n, dtype=np.uint8)
+        for i, q in enumerate(open_q):
+            z[q] = (j >> (a - 1 - i)) & 1
+        assert abs(got[j] - oracle.amplitude_sv(n, edges, g[0], b[0], z)) < 1e-12 * 2.0 ** (-n / 2) * 8, j
+
+
+def test_open_amplitudes_sliced_sum():
+    # per-slice open tensors of a slicing schedule add up to the unsliced one
+    n, p = 10, 2
+    edges = regular_graph(n, 3, 0)
+    g, b = qaoa_params(p, 1, seed=4)
+    open_q = [1, 4]
+    opened = {oracle.ket_var(n, q, p) for q in open_q}
+    T = [t for t in oracle.amplitude_network(n, edges, g[0], b[0]) if not (len(t[1]) == 1 and t[1][0] in opened)]
+    ov = [oracle.ket_var(n, q, p) for q in open_q]
+    order = oracle.min_degree_order(T, exclude=ov)
+    sl = order[4:7]
+    rest = [v for v in order if v not in sl]
+    per = oracle.sliced_values(T, rest, [(4, sl)], open_vars=ov)
+    assert per.shape == (8, 4)
+    want = oracle.amplitudes_open(n, edges, g[0], b[0], open_q)
+    assert np.abs(per.sum(axis=0) - want).max() < 1e-12 * np.abs(want).max()

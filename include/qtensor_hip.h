@@ -221,6 +221,27 @@ qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, int32_t n_po
                             int64_t slice_begin, int64_t slice_end,
                             qt_amp* out, double* per_slice_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * qt_contract_batch for a single plan, with the same arguments, results
+ * and journal layout (n_plans = 1), whose whole device workspace -- gate
+ * tensors, intermediates, exponent and max slots, step tables, per-slice
+ * results -- lives in a static device array of QT_NOALLOC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends.  No
+ * device memory is allocated or freed by the call.  The slice batch is the
+ * largest power of two whose workspace fits; a contraction that does not
+ * fit at one slice per launch is rejected with QT_EINVAL and the size it
+ * needs in qt_last_error().  All calls on one GPU share the array: when it
+ * holds another plan's (or another shape's) workspace, the call waits for
+ * the device to drain and uploads its tables again; calls that overlap on
+ * one GPU (other threads, or streams still running an earlier call) race
+ * and must be serialised by the caller.  QT_PLAN_GRAPH is ignored. */
+#define QT_NOALLOC_SCRATCH_BYTES (64ll << 20)
+qt_status qt_contract_batch_noalloc(qt_plan* plan, int32_t n_points,
+                                    const double* gammas, const double* betas,
+                                    int64_t slice_begin, int64_t slice_end,
+                                    qt_amp* out, double* per_slice_out, void* hip_stream);
+
 /* QAOA MaxCut energy E = sum_e <C_e> from per-edge lightcone networks
  * (Section III-B: the energy is one amplitude of a duplicated expression;
  * lightcone optimisation, Section III-A), all edges and points in one batched

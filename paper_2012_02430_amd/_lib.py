@@ -64,6 +64,8 @@ class qt_plan_desc(ctypes.Structure):
                 ("flags", c_int32), ("n_open", c_int32), ("open_vars", POINTER(c_int32))]
 
 
+QT_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 QT_PLAN_PLAIN = 1
 QT_PLAN_FOLD_PREFIX = 2
 QT_PLAN_GRAPH = 4
@@ -121,6 +123,8 @@ SIGNATURES = {
     "qt_contract_amplitude": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qt_contract_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, c_void_p,
                                     c_int64, c_int64, c_void_p, c_void_p, c_void_p]),
+    "qt_contract_batch_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p,
+                                            c_void_p, c_void_p]),
     "qt_energy_grad": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qt_plan_get_info": (c_int32, [c_void_p, POINTER(qt_plan_info)]),

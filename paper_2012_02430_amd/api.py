@@ -273,6 +273,31 @@ class Plan:
         return contract_batch([self], gammas, betas, slice_begin, slice_end, per_slice, stream)
 
 
+def contract_batch_noalloc(plan, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
+    """``qt_contract_batch_noalloc``: one plan, with its device workspace in the library's static scratch
+    array (no device allocation).  Same results as ``contract_batch([plan], ...)``."""
+    lib = L.load()
+    p = plan.p
+    g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1, p) if p else np.zeros((1, 0))
+    b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1, p) if p else np.zeros((1, 0))
+    n_points = g.shape[0]
+    if slice_end is None:
+        slice_end = plan.n_slices
+    n_range = slice_end - slice_begin
+    a = len(plan.open_vars)
+    out = (L.qt_amp * (n_points << a))()
+    ps = np.zeros((n_points << a, n_range, 3)) if per_slice else None
+    L.check(lib.qt_contract_batch_noalloc(plan.handle, n_points, g.ctypes.data, b.ctypes.data, slice_begin, slice_end,
+                                          ctypes.cast(out, ctypes.c_void_p), ps.ctypes.data if per_slice else None,
+                                          stream or 0))
+    shape = (n_points,) + ((1 << a,) if a else ())
+    vals = np.array([amp_to_complex(o.re, o.im, o.log2_scale) for o in out]).reshape(shape)
+    slices = None
+    if per_slice:
+        slices = np.vectorize(amp_to_complex)(ps[..., 0], ps[..., 1], ps[..., 2]).reshape(shape + (n_range,))
+    return vals, slices
+
+
 def contract_batch(plans, gammas, betas, slice_begin=0, slice_end=None, per_slice=False, stream=None):
     lib = L.load()
     p = plans[0].p

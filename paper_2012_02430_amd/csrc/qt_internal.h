@@ -426,6 +426,14 @@ void energy_forget(uint64_t serial);  // drops cached energy jobs that use the p
 qt_status run_plan_points(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream,
                           const double** sums);
 bool make_runs(uint32_t mask, int max_runs, uint8_t* lo, uint8_t* len, uint8_t* dst, int32_t& nruns);
+// The contraction of qt_contract_batch for one plan with its whole device
+// workspace inside `region` (`cap` bytes; no allocation).  *owner names the
+// layout the region holds; when it is not this plan's current one, the
+// workspace is laid out afresh (the largest slice batch that fits) and its
+// tables uploaded, after the device has drained, and *owner is updated.
+qt_status contract_in_region(qt_plan& plan, char* region, int64_t cap, uint64_t* owner, int np, const double* gammas,
+                             const double* betas, int64_t begin, int64_t end, qt_amp* out, double* per_slice_out,
+                             hipStream_t stream);
 
 // Buffers live over closed time intervals, packed first-fit, largest first.
 struct Interval {
@@ -468,6 +476,7 @@ struct qt_plan {
   std::unique_ptr<Profile> prof;
   struct Workspace;
   std::unique_ptr<Workspace> ws;
+  std::unique_ptr<Workspace> ws_static;  // laid out in a caller-provided region (qt_contract_batch_noalloc)
   // QT_PLAN_GRAPH: instantiated launch sequences, by call signature
   struct Graphs;
   std::unique_ptr<Graphs> graphs;

@@ -175,11 +175,19 @@ struct qt_plan::Workspace {
   // QT_DEBUG_LEVEL_TRACE: per-level clock of workgroup 0 of each segment launch
   bool trace_on = false;
   uint64_t* trace_buf = nullptr;
+  // Buffers carved in order from a caller-provided device region instead of
+  // allocated (ext_cap > 0); with `counting`, nothing is written or
+  // uploaded and only ext_used is advanced (a sizing pass).
+  char* ext = nullptr;
+  int64_t ext_cap = 0, ext_used = 0;
+  bool counting = false;
 
   void release() {
-    for (void* p : {leaves, arena0, arena1, (void*)exps, (void*)maxbits, (void*)params, (void*)dleaves,
-                    (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums, seg_tables, (void*)trace_buf})
-      if (p) (void)hipFree(p);
+    if (ext_cap == 0)
+      for (void* p : {leaves, arena0, arena1, (void*)exps, (void*)maxbits, (void*)params, (void*)dleaves,
+                      (void*)ddense, (void*)dfinal, (void*)per_slice, (void*)sums, seg_tables, (void*)trace_buf})
+        if (p) (void)hipFree(p);
+    ext_used = 0;
     seg_tables = nullptr;
     trace_buf = nullptr;
     leaves = arena0 = arena1 = nullptr;
@@ -302,14 +310,29 @@ hipError_t timed(qt_plan& plan, hipStream_t stream, int kclass, int op, double b
 namespace qt {
 namespace {
 
+// A workspace buffer: allocated, or the next 256-byte-aligned piece of the
+// workspace's external region.
 template <class T>
-qt_status dev_alloc(T** p, int64_t count, int64_t& bytes) {
+qt_status dev_alloc(qt_plan::Workspace& ws, T** p, int64_t count, int64_t& bytes) {
   const size_t b = std::max<int64_t>(1, count) * sizeof(T);
-  if (hipMalloc((void**)p, b) != hipSuccess) {
+  if (ws.ext_cap > 0) {
+    const int64_t off = (ws.ext_used + 255) & ~(int64_t)255;
+    if (!ws.counting && off + (int64_t)b > ws.ext_cap)
+      return fail(QT_ENOMEM, "workspace exceeds the static scratch area");
+    *p = reinterpret_cast<T*>(ws.ext + off);
+    ws.ext_used = off + (int64_t)b;
+  } else if (hipMalloc((void**)p, b) != hipSuccess) {
     (void)hipGetLastError();
     return fail(QT_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
   }
   bytes += (int64_t)b;
+  return QT_OK;
+}
+
+// Host-to-device upload of workspace tables (skipped by a sizing pass).
+qt_status ws_upload(const qt_plan::Workspace& ws, void* dst, const void* src, size_t bytes) {
+  if (ws.counting || bytes == 0) return QT_OK;
+  QT_HIP_CHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
   return QT_OK;
 }
 
@@ -692,7 +715,7 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
              ((S.level_off.size() * sizeof(int32_t) + 255) & ~(size_t)255);
   }
   if (!total) return QT_OK;
-  QT_TRY(dev_alloc((char**)&ws.seg_tables, (int64_t)total, ws.bytes));
+  QT_TRY(dev_alloc(ws, (char**)&ws.seg_tables, (int64_t)total, ws.bytes));
   std::vector<char> host(total);
   size_t off = 0;
   char* base = (char*)ws.seg_tables;
@@ -714,8 +737,7 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     S.launch.n_slots = S.n_slots;
     S.launch.lds_elems = S.lds_elems;
   }
-  QT_HIP_CHECK(hipMemcpy(ws.seg_tables, host.data(), total, hipMemcpyHostToDevice));
-  return QT_OK;
+  return ws_upload(ws, ws.seg_tables, host.data(), total);
 }
 
 // Storage bits of the counter variables `counter` (key order) in a tensor
@@ -896,15 +918,18 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
   return QT_OK;
 }
 
-qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
+// Lays out (allocating, or carving from the workspace's external region)
+// and uploads everything a run of `np` points over `n_range` slices needs,
+// with `chunk` slices per launch (0: from slice_batch or the budget).
+qt_status layout_workspace(qt_plan& plan, qt_plan::Workspace& ws, int np, int64_t n_range, int64_t chunk_req) {
   const bool c128 = plan.precision == QT_C128;
   const int elt = c128 ? 16 : 8;
   const int k = (int)plan.slice_vars.size();
-  if (!plan.ws) plan.ws = std::make_unique<qt_plan::Workspace>();
-  auto& ws = *plan.ws;
   if (!ws.planned) QT_TRY(plan_schedule(plan, ws, elt));
   int64_t chunk = 1;
-  if (k > 0) {
+  if (chunk_req > 0) {
+    chunk = chunk_req;
+  } else if (k > 0) {
     const int64_t n_slices = 1ll << k;
     if (plan.slice_batch_req > 0) {
       chunk = 1;
@@ -923,23 +948,21 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
     ws.chunk = chunk;
     ws.gen = next_ws_gen();
     int64_t& b = ws.bytes;
-    QT_TRY(dev_alloc((char**)&ws.leaves, (int64_t)plan.leaf_block * np * elt, b));
-    QT_TRY(dev_alloc((char**)&ws.arena0, std::max<int64_t>(1, ws.arena0_units) * np * elt, b));
-    QT_TRY(dev_alloc((char**)&ws.arena1, std::max<int64_t>(1, ws.arena1_units) * np * chunk * elt, b));
+    QT_TRY(dev_alloc(ws, (char**)&ws.leaves, (int64_t)plan.leaf_block * np * elt, b));
+    QT_TRY(dev_alloc(ws, (char**)&ws.arena0, std::max<int64_t>(1, ws.arena0_units) * np * elt, b));
+    QT_TRY(dev_alloc(ws, (char**)&ws.arena1, std::max<int64_t>(1, ws.arena1_units) * np * chunk * elt, b));
     ws.exp1_base = (int64_t)np * plan.n_exp0;
     ws.exp1_count = (int64_t)np * chunk * plan.n_exp1;
     ws.n_exp = ws.exp1_base + ws.exp1_count;
-    QT_TRY(dev_alloc(&ws.exps, ws.n_exp, b));
-    QT_TRY(dev_alloc(&ws.maxbits, ws.n_exp, b));
-    QT_TRY(dev_alloc(&ws.params, (int64_t)np * 2 * std::max(1, plan.net.p), b));
-    QT_TRY(dev_alloc(&ws.dleaves, (int64_t)plan.dev_leaves.size(), b));
-    QT_TRY(dev_alloc(&ws.ddense, (int64_t)plan.dense_table.size(), b));
-    QT_TRY(dev_alloc(&ws.dfinal, (int64_t)plan.finals.size(), b));
-    QT_TRY(dev_alloc(&ws.sums, ((int64_t)np << plan.open_vars.size()) * 3, b));
-    QT_HIP_CHECK(hipMemcpy(ws.dleaves, plan.dev_leaves.data(), plan.dev_leaves.size() * sizeof(DevLeaf),
-                           hipMemcpyHostToDevice));
-    QT_HIP_CHECK(hipMemcpy(ws.ddense, plan.dense_table.data(), plan.dense_table.size() * sizeof(double),
-                           hipMemcpyHostToDevice));
+    QT_TRY(dev_alloc(ws, &ws.exps, ws.n_exp, b));
+    QT_TRY(dev_alloc(ws, &ws.maxbits, ws.n_exp, b));
+    QT_TRY(dev_alloc(ws, &ws.params, (int64_t)np * 2 * std::max(1, plan.net.p), b));
+    QT_TRY(dev_alloc(ws, &ws.dleaves, (int64_t)plan.dev_leaves.size(), b));
+    QT_TRY(dev_alloc(ws, &ws.ddense, (int64_t)plan.dense_table.size(), b));
+    QT_TRY(dev_alloc(ws, &ws.dfinal, (int64_t)plan.finals.size(), b));
+    QT_TRY(dev_alloc(ws, &ws.sums, ((int64_t)np << plan.open_vars.size()) * 3, b));
+    QT_TRY(ws_upload(ws, ws.dleaves, plan.dev_leaves.data(), plan.dev_leaves.size() * sizeof(DevLeaf)));
+    QT_TRY(ws_upload(ws, ws.ddense, plan.dense_table.data(), plan.dense_table.size() * sizeof(double)));
     // streaming step descriptors
     ws.steps.clear();
     ws.gemms.assign(plan.steps.size(), DevGemm{});
@@ -996,54 +1019,48 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
         return fail(QT_EUNSUPPORTED, "closing tensor index map too fragmented");
       ws.finals.push_back(d);
     }
-    if (!ws.finals.empty())
-      QT_HIP_CHECK(hipMemcpy(ws.dfinal, ws.finals.data(), ws.finals.size() * sizeof(DevIn), hipMemcpyHostToDevice));
+    QT_TRY(ws_upload(ws, ws.dfinal, ws.finals.data(), ws.finals.size() * sizeof(DevIn)));
     QT_TRY(build_segment_tables(plan, ws, elt));
     ws.trace_on = env_int("QT_DEBUG_LEVEL_TRACE", 0) != 0;
     if (ws.trace_on) {
       int max_levels = 1;
       for (auto& S : ws.segs) max_levels = std::max(max_levels, S.n_levels + 1);
-      QT_TRY(dev_alloc(&ws.trace_buf, (int64_t)max_levels * (int64_t)ws.segs.size(), b));
+      QT_TRY(dev_alloc(ws, &ws.trace_buf, (int64_t)max_levels * (int64_t)ws.segs.size(), b));
     }
     plan.info.slice_batch = chunk;
   }
   const int64_t rows = (int64_t)np << plan.open_vars.size();  // (point, open output) rows of results
   if (ws.per_slice_cap < rows * n_range) {
     ws.gen = next_ws_gen();
-    if (ws.per_slice) (void)hipFree(ws.per_slice);
+    if (ws.per_slice && ws.ext_cap == 0) (void)hipFree(ws.per_slice);
     ws.per_slice = nullptr;
     ws.per_slice_cap = 0;
     int64_t dummy = 0;
-    QT_TRY(dev_alloc(&ws.per_slice, rows * n_range * 3, dummy));
+    QT_TRY(dev_alloc(ws, &ws.per_slice, rows * n_range * 3, dummy));
     ws.per_slice_cap = rows * n_range;
   }
   plan.info.workspace_bytes = ws.bytes + ws.per_slice_cap * 24;
   return QT_OK;
 }
 
-qt_status upload_params(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream) {
-  const int p = plan.net.p;
-  if (p == 0) return QT_OK;
-  auto& ws = *plan.ws;
-  const size_t pitch = 2 * p * sizeof(double);
-  (void)pitch;
-  QT_TRY(upload_params_to(ws.params, np, p, gammas, betas, stream));
-  return QT_OK;
+qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
+  if (!plan.ws) plan.ws = std::make_unique<qt_plan::Workspace>();
+  return layout_workspace(plan, *plan.ws, np, n_range, 0);
 }
+
 
 // Runs one plan at np points over slices [begin, end); leaves the per-slice
 // values in ws.per_slice ([np][2^a][end - begin][3], a open output bits) and
 // the sums in ws.sums ([np][2^a][3]).
-qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
-                   int64_t stop, hipStream_t stream) {
+// The workspace `ws` is laid out for np points and the slice range.
+qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const double* gammas, const double* betas,
+                      int64_t begin, int64_t end, int64_t stop, hipStream_t stream) {
   const bool c128 = plan.precision == QT_C128;
   const bool scaled = plan.precision != QT_C128;
   const int k = (int)plan.slice_vars.size();
   const int64_t n_range = end - begin;
-  QT_TRY(ensure_workspace(plan, np, n_range));
-  auto& ws = *plan.ws;
   int launches = 0;
-  QT_TRY(upload_params(plan, np, gammas, betas, stream));
+  QT_TRY(upload_params_to(ws.params, np, plan.net.p, gammas, betas, stream));
   const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
   QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
     return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params, plan.net.p,
@@ -1156,10 +1173,63 @@ qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* be
   return QT_OK;
 }
 
+qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
+                   int64_t stop, hipStream_t stream) {
+  QT_TRY(ensure_workspace(plan, np, end - begin));
+  return run_plan_ws(plan, *plan.ws, np, gammas, betas, begin, end, stop, stream);
+}
+
 }  // namespace
 }  // namespace qt
 
 namespace qt {
+qt_status contract_in_region(qt_plan& plan, char* region, int64_t cap, uint64_t* owner, int np, const double* gammas,
+                             const double* betas, int64_t begin, int64_t end, qt_amp* out, double* per_slice_out,
+                             hipStream_t stream) {
+  if (!plan.ws_static) plan.ws_static = std::make_unique<qt_plan::Workspace>();
+  auto& ws = *plan.ws_static;
+  const int64_t n_range = end - begin;
+  const int64_t rows = (int64_t)np << plan.open_vars.size();
+  const bool current = *owner == ws.gen && ws.ext == region && ws.np == np && ws.per_slice_cap >= rows * n_range;
+  if (!current) {
+    // earlier calls may still read the tables held in the region
+    QT_HIP_CHECK(hipDeviceSynchronize());
+    const int k = (int)plan.slice_vars.size();
+    int64_t chunk = k > 0 ? (1ll << k) : 1;
+    if (plan.slice_batch_req > 0)
+      while (chunk > 1 && chunk > plan.slice_batch_req) chunk >>= 1;
+    int64_t need = 0;
+    for (;; chunk >>= 1) {  // sizing passes: the largest slice batch that fits
+      ws.release();
+      ws.np = 0;
+      ws.ext = reinterpret_cast<char*>(256);  // never dereferenced: nothing is written in a sizing pass
+      ws.ext_cap = cap;
+      ws.counting = true;
+      QT_TRY(layout_workspace(plan, ws, np, n_range, chunk));
+      need = ws.ext_used;
+      if (need <= cap || chunk == 1) break;
+    }
+    ws.counting = false;
+    ws.release();
+    ws.np = 0;
+    ws.ext = region;
+    *owner = 0;
+    if (need > cap)
+      return fail(QT_EINVAL, "qt_contract_batch_noalloc: the contraction needs " + std::to_string(need) +
+                                 " bytes of workspace at one slice per launch; the static scratch holds " +
+                                 std::to_string(cap));
+    QT_TRY(layout_workspace(plan, ws, np, n_range, chunk));
+    *owner = ws.gen;
+  }
+  QT_TRY(run_plan_ws(plan, ws, np, gammas, betas, begin, end, end, stream));
+  if (per_slice_out) {
+    const size_t row = (size_t)n_range * 3 * sizeof(double);
+    QT_TRY(copy_2d(per_slice_out, row, ws.per_slice, row, row, (size_t)rows, stream));
+  }
+  const size_t bytes = (size_t)rows * sizeof(qt_amp);
+  return copy_2d(out, bytes, ws.sums, bytes, bytes, 1, stream);
+}
+
 qt_status run_plan_points(qt_plan& plan, int np, const double* gammas, const double* betas, hipStream_t stream,
                           const double** sums) {
   QT_TRY(run_plan(plan, np, gammas, betas, 0, 1ll << plan.slice_vars.size(), 1ll << plan.slice_vars.size(), stream));

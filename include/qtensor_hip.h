@@ -263,6 +263,19 @@ qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_
                          double* energy, double* dE_dgamma, double* dE_dbeta,
                          double* per_edge, void* hip_stream);
 
+/* qt_energy_grad with per-edge weights in the FP64 sums over edges:
+ * energy = sum_e w_e <C_e>, the gradient likewise; per_edge stays the
+ * unweighted <C_e>.  edge_weights: [n_edges] non-negative doubles, host or
+ * device (QT_EINVAL on a negative or NaN host weight).  With lightcones
+ * deduplicated up to isomorphism (Section III-A's symmetry argument: edges
+ * whose lightcones are isomorphic, with the edge's endpoints mapped to each
+ * other, have equal <C_e>), one plan per class weighted by the class size
+ * gives the full-graph energy and gradient. */
+qt_status qt_energy_grad_weighted(qt_plan* const* lightcones, const double* edge_weights, int32_t n_edges,
+                                  int32_t n_points, const double* gammas, const double* betas,
+                                  double* energy, double* dE_dgamma, double* dE_dbeta,
+                                  double* per_edge, void* hip_stream);
+
 /* Introspection of a compiled plan. */
 qt_status qt_plan_get_info(const qt_plan* plan, qt_plan_info* out);
 

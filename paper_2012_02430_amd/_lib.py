@@ -127,6 +127,8 @@ SIGNATURES = {
                                             c_void_p, c_void_p]),
     "qt_energy_grad": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "qt_energy_grad_weighted": (c_int32, [POINTER(c_void_p), c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qt_plan_get_info": (c_int32, [c_void_p, POINTER(qt_plan_info)]),
     "qt_plan_set_tuning": (c_int32, [c_void_p, POINTER(qt_tuning)]),
     "qt_plan_get_tuning": (c_int32, [c_void_p, POINTER(qt_tuning)]),

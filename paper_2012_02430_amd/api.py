@@ -412,35 +412,59 @@ class EnergyModel:
     """QAOA MaxCut energy from per-edge lightcone networks (``qt_energy_grad``).
 
     One network and one plan per edge (greedy order, no slicing); every edge
-    and point runs in one batched launch.
+    and point runs in one batched launch.  With ``dedup`` the edges are
+    grouped by lightcone isomorphism (``lightcones.lightcone_classes``): one
+    network and plan per class, each weighted by its size in the FP64 sums
+    (``qt_energy_grad_weighted``); per-edge values are those of the edge's
+    class representative.
     """
 
-    def __init__(self, n, edges, p, precision="c64", algo="min_fill"):
+    def __init__(self, n, edges, p, precision="c64", algo="min_fill", dedup=False):
         from paper_2012_02430_amd import network as N
 
         self.n, self.p = n, p
         self.edges = [tuple(e) for e in edges]
-        self.networks = [Network(N.energy_network(n, self.edges, p, u, v)) for u, v in self.edges]
+        if dedup:
+            from paper_2012_02430_amd.lightcones import lightcone_classes
+
+            self.classes = lightcone_classes(self.edges, p)
+        else:
+            self.classes = [[e] for e in range(len(self.edges))]
+        self.dedup = bool(dedup)
+        self.class_of = np.zeros(len(self.edges), dtype=np.int64)
+        for c, members in enumerate(self.classes):
+            self.class_of[members] = c
+        self.weights = np.array([float(len(m)) for m in self.classes])
+        reps = [self.edges[m[0]] for m in self.classes]
+        self.networks = [Network(N.energy_network(n, self.edges, p, u, v)) for u, v in reps]
         self.plans = [Plan(net, net.order_greedy(algo)[0], precision=precision) for net in self.networks]
         self._arr = (ctypes.c_void_p * len(self.plans))(*[pl.handle.value for pl in self.plans])
 
+    def _call(self, npt, g_ptr, b_ptr, E_ptr, dg_ptr, db_ptr, pe_ptr, stream, w_ptr=None):
+        lib = L.load()
+        if self.dedup:
+            w = w_ptr if w_ptr is not None else self.weights.ctypes.data
+            L.check(lib.qt_energy_grad_weighted(self._arr, w, len(self.plans), npt, g_ptr, b_ptr, E_ptr, dg_ptr,
+                                                db_ptr, pe_ptr, stream))
+        else:
+            L.check(lib.qt_energy_grad(self._arr, len(self.plans), npt, g_ptr, b_ptr, E_ptr, dg_ptr, db_ptr,
+                                       pe_ptr, stream))
+
     def energy(self, gammas, betas, per_edge=False, grad=False, stream=None):
         """E per point (and per-edge values [n_points, n_edges], and (dE/dgamma, dE/dbeta))."""
-        lib = L.load()
         p = self.p
         g = np.ascontiguousarray(gammas, dtype=np.float64).reshape(-1, p)
         b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1, p)
         npt = g.shape[0]
         E = np.zeros(npt)
-        pe = np.zeros((npt, len(self.plans))) if per_edge else None
+        pc = np.zeros((npt, len(self.plans))) if per_edge else None
         dg = np.zeros((npt, p)) if grad else None
         db = np.zeros((npt, p)) if grad else None
-        L.check(lib.qt_energy_grad(self._arr, len(self.plans), npt, g.ctypes.data, b.ctypes.data, E.ctypes.data,
-                                   dg.ctypes.data if grad else None, db.ctypes.data if grad else None,
-                                   pe.ctypes.data if per_edge else None, stream or 0))
+        self._call(npt, g.ctypes.data, b.ctypes.data, E.ctypes.data, dg.ctypes.data if grad else None,
+                   db.ctypes.data if grad else None, pc.ctypes.data if per_edge else None, stream or 0)
         out = [E]
         if per_edge:
-            out.append(pe)
+            out.append(pc[:, self.class_of] if self.dedup else pc)
         if grad:
             out += [dg, db]
         return out[0] if len(out) == 1 else tuple(out)
@@ -474,12 +498,14 @@ class EnergyModel:
         dg = torch.empty(npt, self.p, dtype=torch.float64, device=dev) if grad else None
         db = torch.empty(npt, self.p, dtype=torch.float64, device=dev) if grad else None
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-        L.check(lib.qt_energy_grad(self._arr, len(self.plans), npt, g.data_ptr(), b.data_ptr(), E.data_ptr(),
-                                   dg.data_ptr() if grad else None, db.data_ptr() if grad else None,
-                                   pe.data_ptr() if per_edge else None, s))
+        if self.dedup and not hasattr(self, "_wdev"):
+            self._wdev = torch.tensor(self.weights, dtype=torch.float64, device=dev)
+        self._call(npt, g.data_ptr(), b.data_ptr(), E.data_ptr(), dg.data_ptr() if grad else None,
+                   db.data_ptr() if grad else None, pe.data_ptr() if per_edge else None, s,
+                   self._wdev.data_ptr() if self.dedup else None)
         out = [E]
         if per_edge:
-            out.append(pe)
+            out.append(pe[:, torch.as_tensor(self.class_of, device=dev)] if self.dedup else pe)
         if grad:
             out += [dg, db]
         return out[0] if len(out) == 1 else tuple(out)

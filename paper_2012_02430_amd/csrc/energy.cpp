@@ -549,6 +549,7 @@ struct EnergyJob {
   double* reals = nullptr;   // [np] energies then [np][n_progs] per edge
   double* gout = nullptr;    // gradient jobs: [np][n_progs][2p]
   double* gsum = nullptr;    // [np][2p]
+  double* weights = nullptr; // [n_progs]: per-edge weights of the sums (weighted calls)
   XMulti multi{};
   int n_fit = 0;
   struct Class {
@@ -561,7 +562,7 @@ struct EnergyJob {
   double bytes_c64 = 0, flops = 0;
   ~EnergyJob() {
     for (void* q : {tables, (void*)params, (void*)out, (void*)sums, (void*)reals, (void*)gout, (void*)gsum,
-                    (void*)scratch})
+                    (void*)weights, (void*)scratch})
       if (q) (void)hipFree(q);
   }
 };
@@ -730,6 +731,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   QT_TRY(alloc(&job.out, (size_t)np * n * 3));
   QT_TRY(alloc(&job.sums, (size_t)np * 3));
   QT_TRY(alloc(&job.reals, (size_t)np * (n + 1)));
+  QT_TRY(alloc(&job.weights, (size_t)n));
   if (grad) {
     QT_TRY(alloc(&job.gout, (size_t)np * n * 2 * std::max(1, p)));
     QT_TRY(alloc(&job.gsum, (size_t)np * 2 * std::max(1, p)));
@@ -806,9 +808,11 @@ void energy_forget(uint64_t serial) {
 
 using namespace qt;
 
-extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
-                                    const double* gammas, const double* betas, double* energy, double* dE_dgamma,
-                                    double* dE_dbeta, double* per_edge, void* hip_stream) {
+namespace {
+
+qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double* weights, int32_t n_points,
+                      const double* gammas, const double* betas, double* energy, double* dE_dgamma, double* dE_dbeta,
+                      double* per_edge, void* hip_stream) {
   try {
     if (!lightcones || n_edges <= 0 || n_points <= 0 || !energy)
       return fail(QT_EINVAL, "qt_energy_grad: bad arguments");
@@ -878,7 +882,16 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_HIP_CHECK(hipMemcpy2DAsync(job->out + 3 * e, (size_t)n_edges * 3 * sizeof(double), sums, 3 * sizeof(double),
                                     3 * sizeof(double), n_points, hipMemcpyDeviceToDevice, stream));
     }
-    QT_HIP_CHECK(launch_slice_sum(job->out, n_points, n_edges, job->sums, stream));
+    const double* w = nullptr;
+    if (weights) {
+      if (!is_device_ptr(weights))
+        for (int e = 0; e < n_edges; ++e)
+          if (!(weights[e] >= 0.0)) return fail(QT_EINVAL, "qt_energy_grad_weighted: negative or NaN weight");
+      QT_TRY(copy_2d(job->weights, sizeof(double) * n_edges, weights, sizeof(double) * n_edges,
+                     sizeof(double) * n_edges, 1, stream));
+      w = job->weights;
+    }
+    QT_HIP_CHECK(launch_slice_sum(job->out, n_points, n_edges, job->sums, stream, w));
     QT_HIP_CHECK(launch_amp_to_real(job->sums, n_points, job->reals, stream));
     QT_TRY(copy_out(energy, job->reals, n_points, stream));
     if (per_edge) {
@@ -886,7 +899,7 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
       QT_TRY(copy_out(per_edge, job->reals + n_points, (size_t)n_points * n_edges, stream));
     }
     if (grad && p > 0) {
-      QT_HIP_CHECK(launch_rows_sum(job->gout, n_points, n_edges, 2 * p, job->gsum, stream));
+      QT_HIP_CHECK(launch_rows_sum(job->gout, n_points, n_edges, 2 * p, job->gsum, stream, w));
       const size_t row = p * sizeof(double), pitch = 2 * p * sizeof(double);
       if (dE_dgamma) QT_TRY(copy_2d(dE_dgamma, row, job->gsum, pitch, row, n_points, stream));
       if (dE_dbeta) QT_TRY(copy_2d(dE_dbeta, row, job->gsum + p, pitch, row, n_points, stream));
@@ -895,4 +908,22 @@ extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges,
   } catch (const std::exception& ex) {
     return fail(QT_ENOMEM, std::string("qt_energy_grad: ") + ex.what());
   }
+}
+
+}  // namespace
+
+extern "C" qt_status qt_energy_grad(qt_plan* const* lightcones, int32_t n_edges, int32_t n_points,
+                                    const double* gammas, const double* betas, double* energy, double* dE_dgamma,
+                                    double* dE_dbeta, double* per_edge, void* hip_stream) {
+  return energy_grad(lightcones, n_edges, nullptr, n_points, gammas, betas, energy, dE_dgamma, dE_dbeta, per_edge,
+                     hip_stream);
+}
+
+extern "C" qt_status qt_energy_grad_weighted(qt_plan* const* lightcones, const double* edge_weights, int32_t n_edges,
+                                             int32_t n_points, const double* gammas, const double* betas,
+                                             double* energy, double* dE_dgamma, double* dE_dbeta, double* per_edge,
+                                             void* hip_stream) {
+  if (!edge_weights) return fail(QT_EINVAL, "qt_energy_grad_weighted: null weights");
+  return energy_grad(lightcones, n_edges, edge_weights, n_points, gammas, betas, energy, dE_dgamma, dE_dbeta,
+                     per_edge, hip_stream);
 }

@@ -409,9 +409,11 @@ __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_p
 
 // Deterministic FP64 sum over slices (Algorithm 1's final reduction): common
 // exponent = max over non-zero slices, thread t adds slices t, t+256, ... in
-// order, then a fixed-shape tree over the 256 partial sums.
+// order, then a fixed-shape tree over the 256 partial sums.  With weights w
+// (non-negative), slice i enters w[i] times (the same sum over edges whose
+// lightcones are deduplicated: each class once, times its size).
 __global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ per_slice, int64_t n_range,
-                                                   double* __restrict__ out) {
+                                                   const double* __restrict__ w, double* __restrict__ out) {
   __shared__ double sre[256], sim[256];
   const int pt = blockIdx.x;
   const int tid = threadIdx.x;
@@ -432,8 +434,9 @@ __global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ pe
     for (int64_t i = tid; i < n_range; i += 256) {
       const double d = ps[3 * i + 2] - emax;
       if (ps[3 * i] != 0.0 || ps[3 * i + 1] != 0.0) {
-        re += ldexp(ps[3 * i], (int)d) * exp2(d - (int)d);
-        im += ldexp(ps[3 * i + 1], (int)d) * exp2(d - (int)d);
+        const double f = exp2(d - (int)d) * (w ? w[i] : 1.0);
+        re += ldexp(ps[3 * i], (int)d) * f;
+        im += ldexp(ps[3 * i + 1], (int)d) * f;
       }
     }
   }
@@ -545,8 +548,8 @@ hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, i
 }
 
 hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,
-                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_slice_sum, dim3(n_points), dim3(256), 0, stream, per_slice, n_range, out);
+                            hipStream_t stream, const double* weights) {
+  hipLaunchKernelGGL(k_slice_sum, dim3(n_points), dim3(256), 0, stream, per_slice, n_range, weights, out);
   return hipGetLastError();
 }
 

@@ -947,14 +947,15 @@ __global__ __launch_bounds__(64) void k_grad_final(const XMulti M, const XProg* 
                              S.sexp + (int64_t)pt * S.slot_stride, S.gacc + (int64_t)pt * S.rec_stride);
 }
 
-// One workgroup per output (r, q): lane-strided partial sums in index order,
-// then a fixed tree, so the result does not depend on timing.
+// One workgroup per output (r, q): lane-strided partial sums in index order
+// (entry i times w[i] when weights are given), then a fixed tree, so the
+// result does not depend on timing.
 __global__ __launch_bounds__(256) void k_rows_sum(const double* __restrict__ in, int n, int nq,
-                                                  double* __restrict__ out) {
+                                                  const double* __restrict__ w, double* __restrict__ out) {
   __shared__ double part[256];
   const int r = blockIdx.x / nq, q = blockIdx.x % nq;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += in[((int64_t)r * n + i) * nq + q];
+  for (int i = threadIdx.x; i < n; i += 256) s += in[((int64_t)r * n + i) * nq + q] * (w ? w[i] : 1.0);
   part[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1000,9 +1001,10 @@ hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level
   return hipGetLastError();
 }
 
-hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream) {
+hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream,
+                           const double* weights) {
   if (rows == 0 || nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)(rows * nq)), dim3(256), 0, stream, in, n, nq, out);
+  hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)(rows * nq)), dim3(256), 0, stream, in, n, nq, weights, out);
   return hipGetLastError();
 }
 

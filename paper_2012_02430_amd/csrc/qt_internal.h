@@ -513,10 +513,12 @@ hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level
                               uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
                               int rec_stride, hipStream_t stream);
 // out[r][q] = sum_i in[(r * n + i) * nq + q] in FP64, in order of i.
-hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream);
+// With `weights` ([n], device), entry i counts weights[i] times.
+hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream,
+                           const double* weights = nullptr);
 hipError_t launch_amp_to_real(const double* amp, int64_t n, double* out, hipStream_t stream);
 size_t lds_exec_smem_bytes(int n_slots, int lds_elems, bool c128);
 hipError_t launch_slice_sum(const double* per_slice, int n_points, int64_t n_range, double* out,
-                            hipStream_t stream);
+                            hipStream_t stream, const double* weights = nullptr);
 
 }  // namespace qt

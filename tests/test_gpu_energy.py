@@ -145,3 +145,60 @@ def test_energy_oversized_lightcones_take_the_step_schedule(precision, capfd, mo
     for i in range(3):
         want = np.array([oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real for u, v in edges])
         assert np.abs(pe[i] - want).max() < TOL[precision]
+
+
+def test_dedup_energy_n1000_p3_matches_all_edges():
+    # one lightcone per isomorphism class, weighted by the class size in the
+    # FP64 edge sum, against every edge contracted on its own
+    n, p = 1000, 3
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 8, seed=21)
+    full = api.EnergyModel(n, edges, p, precision="c64")
+    dd = api.EnergyModel(n, edges, p, precision="c64", dedup=True)
+    assert len(dd.plans) < 50 and dd.weights.sum() == len(edges)
+    E0, pe0 = full.energy(gs, bs, per_edge=True)
+    E1, pe1 = dd.energy(gs, bs, per_edge=True)
+    assert np.abs(pe1 - pe0).max() < TOL["c64"]
+    assert np.abs(E1 - E0).max() < TOL["c64"] * np.abs(E0).max()
+    # the dedup'd sum against the oracle on one point, class by class
+    i = 3
+    for c in dd.classes[:6]:
+        u, v = edges[c[0]]
+        assert abs(pe1[i, c[0]] - oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real) < TOL["c64"]
+
+
+def test_dedup_gradient_n200_p2_matches_all_edges():
+    n, p = 200, 2
+    edges = regular_graph(n, 3, 0)
+    gs, bs = qaoa_params(p, 16, seed=22)
+    full = api.EnergyModel(n, edges, p, precision="c64")
+    dd = api.EnergyModel(n, edges, p, precision="c64", dedup=True)
+    E0, dg0, db0 = full.energy(gs, bs, grad=True)
+    E1, dg1, db1 = dd.energy(gs, bs, grad=True)
+    g0 = np.concatenate([dg0, db0], axis=1)
+    g1 = np.concatenate([dg1, db1], axis=1)
+    assert np.abs(E1 - E0).max() < 1e-12 * np.abs(E0).max()
+    assert (np.linalg.norm(g1 - g0, axis=1) / np.linalg.norm(g0, axis=1)).max() < 1e-12
+    # device-resident call with weights on the GPU
+    import torch
+
+    gd = torch.tensor(gs, device="cuda")
+    bd = torch.tensor(bs, device="cuda")
+    Ed, ped = dd.energy_device(gd, bd, per_edge=True)
+    assert np.abs(Ed.cpu().numpy() - E1).max() < TOL["c64"] * np.abs(E1).max()
+    assert ped.shape == (16, len(edges))
+
+
+def test_weighted_energy_rejects_negative_weights():
+    import ctypes
+
+    n, p = 12, 1
+    edges = regular_graph(n, 3, 0)
+    model = api.EnergyModel(n, edges, p)
+    gs, bs = qaoa_params(p, 1, seed=1)
+    w = np.ones(len(edges))
+    w[3] = -1.0
+    E = np.zeros(1)
+    st = L.load().qt_energy_grad_weighted(model._arr, w.ctypes.data, len(edges), 1, gs.ctypes.data, bs.ctypes.data,
+                                          E.ctypes.data, None, None, None, 0)
+    assert st == L.QT_EINVAL

@@ -67,8 +67,14 @@ typedef enum {
  *                   item.  Same values as eliminating the variables one by
  *                   one, with a smaller intermediate.
  *   QT_C64_SCALED_MFMA_BF16X3
- *                   reserved (split-BF16 products); qt_load_plan returns
- *                   QT_EUNSUPPORTED. */
+ *                   as QT_C64_SCALED_MFMA_FP32, and fused buckets with
+ *                   K >= 32 take their products on the BF16 matrix cores:
+ *                   each FP32 operand value is split into three BF16 parts
+ *                   (about 24 significant bits), a real product is the sum
+ *                   of the six part products above 2^-16 of it, and a complex
+ *                   product takes three real ones (3M: Ar Br, Ai Bi and
+ *                   (Ar + Ai)(Br + Bi)), all accumulated in FP32.  Shorter
+ *                   fused sums use the FP32 products. */
 typedef enum {
   QT_C128 = 0,
   QT_C64_SCALED = 1,

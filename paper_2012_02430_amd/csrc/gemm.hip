@@ -21,6 +21,18 @@
 // Each K stage is accumulated from zero and added to the running total with
 // Kahan compensation, so the rounding error grows with the stage depth (16
 // or 64) plus a constant rather than with K (up to 2^20 here).
+//
+// Split-BF16 mode (QT_C64_SCALED_MFMA_BF16X3, MODE 1, 32-deep stages): each
+// scaled operand value x is split into three BF16 parts x = h + m + l + r
+// with h = bf16(x), m = bf16(x - h), l = bf16(x - h - m) (|r| <= 2^-24 |x|
+// roughly), and a real product x y is formed from the six part products
+// whose order is at least 2^-16 (hh, hm, mh, hl, lh, mm) on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, which keeps about the
+// accuracy of an FP32 product.  The complex product takes three real
+// products (3M): T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi), then
+// Re = T1 - T2 and Im = T3 - T1 - T2 per stage.  The MFMA lane layout
+// (lane l holds A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16],
+// j = 0..7) matches the FP32 one above with eight K values per lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +45,16 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// x = h + m + l (+ a remainder below 2^-24 |x|), each part BF16 (rounded to
+// nearest), stored as three 16-bit words.
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
 
 // Raw buffer over the 4 GiB window at p (offsets are checked against it).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p) {
@@ -95,7 +117,7 @@ __device__ __forceinline__ uint32_t slot_part(const uint32_t* w, int q) {
 // one: the item's scales and bases are found once, and a step to the next
 // tile advances the n (or, when n wraps, the m) parts of the offsets by one
 // masked increment ((x | ~M) + 1) & M.
-template <int TB, int LM, int LN, int TK>
+template <int TB, int LM, int LN, int TK, int MODE>
 __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __restrict__ exps,
                                                     uint32_t* __restrict__ maxbits, uint32_t tiles_per_block,
                                                     uint64_t n_tiles) {
@@ -105,21 +127,28 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   constexpr int kSubM = TM / 16, kSubN = TN / 16;
   constexpr int kSubs = NB * kSubM * kSubN;
   static_assert(kSubs <= kGThreads / 64, "one 16 x 16 sub-tile per wavefront");
-  // operand row pitch: the products read row li (0..15) at depth lk (0..3)
-  // per lane; 16 + 1 and 64 + 4 put those 64 reads in distinct banks
-  constexpr int kP = TK == 64 ? TK + 4 : TK + 1;
+  static_assert(MODE == 0 || TK == 32, "split-BF16 stages are 32 deep");
+  // operand row pitch (in elements of the plane): FP32 planes: the products
+  // read row li (0..15) at depth lk (0..3) per lane, and 16 + 1 and 64 + 4
+  // put those 64 reads in distinct banks; BF16 planes: each lane reads 16
+  // bytes (eight K values), rows 80 bytes apart
+  constexpr int kP = MODE == 1 ? TK + 8 : (TK == 64 ? TK + 4 : TK + 1);
   constexpr int kALoads = kARows * TK / kGThreads, kBLoads = kBRows * TK / kGThreads;
   constexpr int kCWrites = kTileElems / kGThreads;
   static_assert(kARows * TK % kGThreads == 0 && kBRows * TK % kGThreads == 0 && kTileElems % kGThreads == 0, "");
-  constexpr int kOpFloats = 2 * (kARows + kBRows) * kP;
+  // FP32: real and imaginary planes of A and B; BF16: nine planes each
+  // (parts h, m, l of Re, Im and Re + Im), two bytes per element
+  constexpr int kOpFloats = MODE == 1 ? 9 * (kARows + kBRows) * kP / 2 : 2 * (kARows + kBRows) * kP;
   constexpr int kCFloats = 2 * kARows * (TN + 1);
   // operand planes and the output staging share the LDS: the staging is
   // written only after the last stage's products
-  __shared__ float smem[kOpFloats > kCFloats ? kOpFloats : kCFloats];
+  __shared__ __align__(16) float smem[kOpFloats > kCFloats ? kOpFloats : kCFloats];
   float* const sAr = smem;
   float* const sAi = sAr + kARows * kP;
   float* const sBr = sAi + kARows * kP;
   float* const sBi = sBr + kBRows * kP;
+  __bf16* const hA = reinterpret_cast<__bf16*>(smem);   // plane 3 c + part of A: hA + (3 c + part) kARows kP
+  __bf16* const hB = hA + 9 * kARows * kP;
   float* const sCr = smem;
   float* const sCi = smem + kARows * (TN + 1);
   const int tid = threadIdx.x;
@@ -223,20 +252,42 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       cm2 = ((cm | ~c_mh) + 1u) & c_mh;
     }
     for (uint32_t s = 0; s < n_stages; ++s) {
+      if constexpr (MODE == 0) {
 #pragma unroll
-      for (int q = 0; q < kALoads; ++q)
-        if ((uint32_t)(q * kGThreads) < a_elems && a_lane) {
-          const uint32_t o = a_lo + slot_part(g.al, q) * 4u;
-          lds(sAr, o) = va[q].x * sa;
-          lds(sAi, o) = va[q].y * sa;
-        }
+        for (int q = 0; q < kALoads; ++q)
+          if ((uint32_t)(q * kGThreads) < a_elems && a_lane) {
+            const uint32_t o = a_lo + slot_part(g.al, q) * 4u;
+            lds(sAr, o) = va[q].x * sa;
+            lds(sAi, o) = va[q].y * sa;
+          }
 #pragma unroll
-      for (int q = 0; q < kBLoads; ++q)
-        if ((uint32_t)(q * kGThreads) < b_elems && b_lane) {
-          const uint32_t o = b_lo + slot_part(g.bl, q) * 4u;
-          lds(sBr, o) = vb[q].x * sbs;
-          lds(sBi, o) = vb[q].y * sbs;
-        }
+        for (int q = 0; q < kBLoads; ++q)
+          if ((uint32_t)(q * kGThreads) < b_elems && b_lane) {
+            const uint32_t o = b_lo + slot_part(g.bl, q) * 4u;
+            lds(sBr, o) = vb[q].x * sbs;
+            lds(sBi, o) = vb[q].y * sbs;
+          }
+      } else {
+        // element offsets in the planes (a_lo, b_lo count 4 bytes per element)
+#pragma unroll
+        for (int q = 0; q < kALoads; ++q)
+          if ((uint32_t)(q * kGThreads) < a_elems && a_lane) {
+            const uint32_t o = (a_lo >> 2) + slot_part(g.al, q);
+            const float re = va[q].x * sa, im = va[q].y * sa;
+            split3(re, hA[o], hA[o + kARows * kP], hA[o + 2 * kARows * kP]);
+            split3(im, hA[o + 3 * kARows * kP], hA[o + 4 * kARows * kP], hA[o + 5 * kARows * kP]);
+            split3(re + im, hA[o + 6 * kARows * kP], hA[o + 7 * kARows * kP], hA[o + 8 * kARows * kP]);
+          }
+#pragma unroll
+        for (int q = 0; q < kBLoads; ++q)
+          if ((uint32_t)(q * kGThreads) < b_elems && b_lane) {
+            const uint32_t o = (b_lo >> 2) + slot_part(g.bl, q);
+            const float re = vb[q].x * sbs, im = vb[q].y * sbs;
+            split3(re, hB[o], hB[o + kBRows * kP], hB[o + 2 * kBRows * kP]);
+            split3(im, hB[o + 3 * kBRows * kP], hB[o + 4 * kBRows * kP], hB[o + 5 * kBRows * kP]);
+            split3(re + im, hB[o + 6 * kBRows * kP], hB[o + 7 * kBRows * kP], hB[o + 8 * kBRows * kP]);
+          }
+      }
       __syncthreads();
       // the next stage, of this tile or of the next one, in flight during the products
       if (s + 1u < n_stages) {
@@ -248,17 +299,79 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
         fetch(am2, bn2);
       }
       if (wave < kSubs) {
-        const float* ar_p = sAr + (wb * TM + wm * 16 + li) * kP + lk;
-        const float* ai_p = sAi + (wb * TM + wm * 16 + li) * kP + lk;
-        const float* br_p = sBr + (wb * TN + wn * 16 + li) * kP + lk;
-        const float* bi_p = sBi + (wb * TN + wn * 16 + li) * kP + lk;
         v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < tk; kk += 4) {
-          const float ar = ar_p[kk], ai = ai_p[kk], br = br_p[kk], bi = bi_p[kk];
-          accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accR, 0, 0, 0);
-          accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accR, 0, 0, 0);
-          accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, accI, 0, 0, 0);
-          accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, accI, 0, 0, 0);
+        if constexpr (MODE == 0) {
+          const float* ar_p = sAr + (wb * TM + wm * 16 + li) * kP + lk;
+          const float* ai_p = sAi + (wb * TM + wm * 16 + li) * kP + lk;
+          const float* br_p = sBr + (wb * TN + wn * 16 + li) * kP + lk;
+          const float* bi_p = sBi + (wb * TN + wn * 16 + li) * kP + lk;
+          if constexpr (TK == 64) {
+            // long sums (MFMA-bound): three products per 4-deep slice (3M),
+            // T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi).  The sum over
+            // the stage only needs A and B to pair the same K in each lane,
+            // so lane (li, lk) takes K = 16 lk + j in instruction j: sixteen
+            // contiguous values per row, read 16 bytes at a time (the row
+            // pitch of 68 floats keeps 8 consecutive lanes in distinct banks)
+            const float* ar16 = ar_p - lk + 16 * lk;
+            const float* ai16 = ai_p - lk + 16 * lk;
+            const float* br16 = br_p - lk + 16 * lk;
+            const float* bi16 = bi_p - lk + 16 * lk;
+            v4f t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const v4f ar = *reinterpret_cast<const v4f*>(ar16 + 4 * c);
+              const v4f ai = *reinterpret_cast<const v4f*>(ai16 + 4 * c);
+              const v4f br = *reinterpret_cast<const v4f*>(br16 + 4 * c);
+              const v4f bi = *reinterpret_cast<const v4f*>(bi16 + 4 * c);
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], br[j], t1, 0, 0, 0);
+                t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[j], bi[j], t2, 0, 0, 0);
+                t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j] + ai[j], br[j] + bi[j], t3, 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              accR[r] = t1[r] - t2[r];
+              accI[r] = t3[r] - t1[r] - t2[r];
+            }
+          } else {
+            for (int kk = 0; kk < tk; kk += 4) {
+              const float ar = ar_p[kk], ai = ai_p[kk], br = br_p[kk], bi = bi_p[kk];
+              accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accR, 0, 0, 0);
+              accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accR, 0, 0, 0);
+              accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, accI, 0, 0, 0);
+              accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, accI, 0, 0, 0);
+            }
+          }
+        } else {
+          // lane (li, lk) reads K values 8 lk .. 8 lk + 7 of its row
+          const __bf16* a_row = hA + (wb * TM + wm * 16 + li) * kP + 8 * lk;
+          const __bf16* b_row = hB + (wb * TN + wn * 16 + li) * kP + 8 * lk;
+          v4f t[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {  // Re, Im, Re + Im
+            const v8bf ah = *reinterpret_cast<const v8bf*>(a_row + (3 * c) * kARows * kP);
+            const v8bf am = *reinterpret_cast<const v8bf*>(a_row + (3 * c + 1) * kARows * kP);
+            const v8bf al = *reinterpret_cast<const v8bf*>(a_row + (3 * c + 2) * kARows * kP);
+            const v8bf bh = *reinterpret_cast<const v8bf*>(b_row + (3 * c) * kBRows * kP);
+            const v8bf bm = *reinterpret_cast<const v8bf*>(b_row + (3 * c + 1) * kBRows * kP);
+            const v8bf bl = *reinterpret_cast<const v8bf*>(b_row + (3 * c + 2) * kBRows * kP);
+            v4f x = {0.f, 0.f, 0.f, 0.f};
+            // smallest terms first
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, x, 0, 0, 0);
+            t[c] = x;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            accR[r] = t[0][r] - t[1][r];
+            accI[r] = t[2][r] - t[0][r] - t[1][r];
+          }
         }
         if (s == 0) {
           totR = accR;
@@ -311,7 +424,7 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   }
 }
 
-template <int TB, int LM, int LN, int TK>
+template <int TB, int LM, int LN, int TK, int MODE>
 hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream) {
   const uint64_t n_tiles = ((uint64_t)g.n_items << (g.nb - TB)) << ((g.nm - LM) + (g.nn - LN));
   if (n_tiles == 0) return hipSuccess;
@@ -328,22 +441,22 @@ hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream
   const uint32_t tpb = 1u << lg;
   const uint64_t grid = (n_tiles + tpb - 1) / tpb;
   if (grid > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm<TB, LM, LN, TK>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps, maxbits,
-                     tpb, n_tiles);
+  hipLaunchKernelGGL((k_gemm<TB, LM, LN, TK, MODE>), dim3((unsigned)grid), dim3(kGThreads), 0, stream, g, exps,
+                     maxbits, tpb, n_tiles);
   return hipGetLastError();
 }
 
-template <int TK>
+template <int TK, int MODE>
 hipError_t go_shape(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream) {
   switch (g.tb * 100 + g.tm * 10 + g.tn) {
-    case 55: return go<0, 5, 5, TK>(g, exps, maxbits, stream);
-    case 154: return go<1, 5, 4, TK>(g, exps, maxbits, stream);
-    case 145: return go<1, 4, 5, TK>(g, exps, maxbits, stream);
-    case 244: return go<2, 4, 4, TK>(g, exps, maxbits, stream);
-    case 54: return go<0, 5, 4, TK>(g, exps, maxbits, stream);
-    case 45: return go<0, 4, 5, TK>(g, exps, maxbits, stream);
-    case 144: return go<1, 4, 4, TK>(g, exps, maxbits, stream);
-    case 44: return go<0, 4, 4, TK>(g, exps, maxbits, stream);
+    case 55: return go<0, 5, 5, TK, MODE>(g, exps, maxbits, stream);
+    case 154: return go<1, 5, 4, TK, MODE>(g, exps, maxbits, stream);
+    case 145: return go<1, 4, 5, TK, MODE>(g, exps, maxbits, stream);
+    case 244: return go<2, 4, 4, TK, MODE>(g, exps, maxbits, stream);
+    case 54: return go<0, 5, 4, TK, MODE>(g, exps, maxbits, stream);
+    case 45: return go<0, 4, 5, TK, MODE>(g, exps, maxbits, stream);
+    case 144: return go<1, 4, 4, TK, MODE>(g, exps, maxbits, stream);
+    case 44: return go<0, 4, 4, TK, MODE>(g, exps, maxbits, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -353,9 +466,11 @@ hipError_t go_shape(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t 
 hipError_t launch_gemm(const DevGemm& g, bool scaled, int* exps, uint32_t* maxbits, hipStream_t stream) {
   if (!scaled || g.nm < 4 || g.nn < 4 || g.nk < 3 || g.tb > g.nb || g.tm > g.nm || g.tn > g.nn)
     return hipErrorInvalidValue;
-  // stage depth: 64 needs K >= 64; 16 (or 8 for K = 8) otherwise
-  if (g.tk == 64 && g.nk >= 6) return go_shape<64>(g, exps, maxbits, stream);
-  if ((g.tk == 16 && g.nk >= 4) || (g.tk == 8 && g.nk == 3)) return go_shape<16>(g, exps, maxbits, stream);
+  // stage depth: 64 needs K >= 64; 16 (or 8 for K = 8) otherwise; the
+  // split-BF16 products take 32-deep stages (K >= 32)
+  if (g.mode == 1) return g.tk == 32 && g.nk >= 5 ? go_shape<32, 1>(g, exps, maxbits, stream) : hipErrorInvalidValue;
+  if (g.tk == 64 && g.nk >= 6) return go_shape<64, 0>(g, exps, maxbits, stream);
+  if ((g.tk == 16 && g.nk >= 4) || (g.tk == 8 && g.nk == 3)) return go_shape<16, 0>(g, exps, maxbits, stream);
   return hipErrorInvalidValue;
 }
 

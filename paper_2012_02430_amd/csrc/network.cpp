@@ -159,8 +159,6 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     *out = nullptr;
     if (d->precision < QT_C128 || d->precision > QT_C64_SCALED_MFMA_BF16X3)
       return fail(QT_EINVAL, "qt_load_plan: unknown precision");
-    if (d->precision == QT_C64_SCALED_MFMA_BF16X3)
-      return fail(QT_EUNSUPPORTED, "qt_load_plan: the split-BF16 MFMA precision is not built; use QT_C64_SCALED_MFMA_FP32");
     if (d->n_order < 0 || (d->n_order > 0 && !d->order)) return fail(QT_EINVAL, "qt_load_plan: bad order");
     if (d->n_groups < 0 || d->n_groups > 64 || (d->n_groups > 0 && (!d->group_step || !d->group_len)))
       return fail(QT_EINVAL, "qt_load_plan: bad groups");
@@ -350,7 +348,7 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     // and the vectors on summed variables are first multiplied into A or B
     // (product steps), so the result is that of eliminating the same
     // variables one by one, with a smaller intermediate.
-    const bool mfma = d->precision == QT_C64_SCALED_MFMA_FP32;
+    const bool mfma = d->precision == QT_C64_SCALED_MFMA_FP32 || d->precision == QT_C64_SCALED_MFMA_BF16X3;
     const int gemm_min_rank = env_int("QT_GEMM_MIN_RANK", 12);
     auto subset = [](const std::vector<int>& a, const std::vector<int>& b) {
       for (int x : a)

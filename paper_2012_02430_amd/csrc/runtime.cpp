@@ -786,7 +786,7 @@ void number_block(std::initializer_list<std::pair<uint32_t, std::pair<int, uint3
 // the output run.  K stage: 64 deep for long sums (more operand bytes in
 // flight per workgroup), else 16 (8 for K = 8).
 void choose_gemm_tile(const qt_plan& plan, const SymStep& st, int32_t& tb_out, int32_t& tm_out, int32_t& tn_out,
-                      int32_t& tk_out) {
+                      int32_t& tk_out, int32_t& mode_out) {
   const auto& va = plan.tensors[st.ins[0].tensor].vars;
   const auto& vb = plan.tensors[st.ins[1].tensor].vars;
   const auto& vc = plan.tensors[st.out].vars;
@@ -831,6 +831,10 @@ void choose_gemm_tile(const qt_plan& plan, const SymStep& st, int32_t& tb_out, i
   tm_out = shapes[best][1];
   tn_out = shapes[best][2];
   tk_out = nk >= 6 ? 64 : (nk >= 4 ? 16 : 8);
+  // split-BF16 products (32-deep stages) for K >= 32; shorter sums are
+  // bound by their output, and keep the FP32 products
+  mode_out = plan.precision == QT_C64_SCALED_MFMA_BF16X3 && nk >= 5 ? 1 : 0;
+  if (mode_out == 1) tk_out = 32;
 }
 
 qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const SymStep& st, int elt, int np,
@@ -902,8 +906,8 @@ qt_status build_gemm(const qt_plan& plan, const qt_plan::Workspace& ws, const Sy
       !covers({g.c_bm, g.c_mm, g.c_nm}, g.nb + g.nm + g.nn, (int)vc.size()) || g.nm < 4 || g.nn < 4 || g.nk < 3 ||
       g.nb + g.nm + g.nk > kGemmMaxRank || g.nb + g.nn + g.nk > kGemmMaxRank || g.nb + g.nm + g.nn > kGemmMaxRank)
     return fail(QT_EPLAN, "internal: GEMM operand maps do not tile their tensors");
-  choose_gemm_tile(plan, st, g.tb, g.tm, g.tn, g.tk);
-  const uint32_t pitch = g.tk == 64 ? 68u : 17u;  // LDS row pitch of the kernel
+  choose_gemm_tile(plan, st, g.tb, g.tm, g.tn, g.tk, g.mode);
+  const uint32_t pitch = g.mode == 1 ? 40u : (g.tk == 64 ? 68u : 17u);  // LDS row pitch of the kernel
   const int lg_tk = ilog2(g.tk);
   const uint32_t TM = 1u << g.tm, TN = 1u << g.tn;
   g.a_kh = g.a_km & ~deposit((uint32_t)g.tk - 1u, g.a_km);
@@ -1446,10 +1450,11 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
                }() + "]" +
                (st.gemm ? ",\"gemm\":{\"k_bits\":" + std::to_string(st.kvars.size()) + ",\"flops\":" +
                               std::to_string(st.flops) + ",\"tile\":" + [&] {
-                                int32_t tb, tm, tn, tk;
-                                choose_gemm_tile(*plan, st, tb, tm, tn, tk);
+                                int32_t tb, tm, tn, tk, mode;
+                                choose_gemm_tile(*plan, st, tb, tm, tn, tk, mode);
                                 return "[" + std::to_string(tb) + "," + std::to_string(tm) + "," +
-                                       std::to_string(tn) + "," + std::to_string(tk) + "]";
+                                       std::to_string(tn) + "," + std::to_string(tk) + "],\"mode\":\"" +
+                                       (mode ? "bf16x3_3m" : "fp32_4m") + "\"";
                               }() + ",\"layouts\":" + [&] {
                                 // per operand, from bit 0 up: the counter each storage bit belongs to
                                 const auto& va = plan->tensors[st.ins[0].tensor].vars;

@@ -285,7 +285,8 @@ def test_invariants_210_qubits_full_size(precision):
     assert rel(a, np.exp(-1j * n * 0.41) * 2.0 ** -105) < TOL[precision]
 
 
-def test_c4_fused_gemm_per_slice_parity():
+@pytest.mark.parametrize("precision", ["c64_mfma_fp32", "c64_mfma_bf16x3"])
+def test_c4_fused_gemm_per_slice_parity(precision):
     # the 210-qubit, p = 1 amplitude plan (min-degree order, 8 slice
     # variables, 256 slices) with fused GEMM buckets on the matrix cores:
     # per-slice values of two slice ranges against the plain complex128 path
@@ -297,16 +298,18 @@ def test_c4_fused_gemm_per_slice_parity():
     edges = regular_graph(n, 3, 0)
     net = api.Network(N.amplitude_network(n, edges, p))
     sch = net.plan_slicing(8, algo="min_degree")
-    fused = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32")
-    ks = sorted(s["gemm"]["k_bits"] for s in fused.describe()["stream_steps"] if "gemm" in s)
-    assert ks == [4, 9], ks  # the K = 16 and K = 512 buckets
+    fused = api.Plan(net, sch.order, sch.groups, precision=precision)
+    gem = sorted((s["gemm"]["k_bits"], s["gemm"]["mode"]) for s in fused.describe()["stream_steps"] if "gemm" in s)
+    assert [k for k, _ in gem] == [4, 9], gem  # the K = 16 and K = 512 buckets
+    if precision == "c64_mfma_bf16x3":
+        assert gem[1][1] == "bf16x3_3m" and gem[0][1] == "fp32_4m"
     plain = api.Plan(net, sch.order, sch.groups, precision="c128", slice_batch=1, plain=True)
     g, b = qaoa_params(p, 1, seed=11)
     for lo, hi in ((0, 2), (181, 183)):
         _, got = fused.contract_batch(g, b, lo, hi, per_slice=True)
         _, want = plain.contract_batch(g, b, lo, hi, per_slice=True)
         err = np.abs(got[0] - want[0]).max() / np.abs(want[0]).max()
-        print(f"n=210 slices [{lo},{hi}): max rel err {err:.2e}", flush=True)
+        print(f"n=210 {precision} slices [{lo},{hi}): max rel err {err:.2e}", flush=True)
         assert err < TOL["c64"], (lo, err)
 
 

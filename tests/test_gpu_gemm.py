@@ -163,3 +163,32 @@ def test_dense_gemm_short_k_stage_depths(monkeypatch, nk, tk):
     got = plan.contract_amplitude([], [])
     want = oracle.contract(tensors, order)
     assert abs(got - want) / abs(want) < TOL, (got, want)
+
+
+@pytest.mark.parametrize("seed,nb,nm,nn,nk", [(70, 0, 5, 5, 5), (71, 2, 4, 4, 6), (72, 1, 5, 4, 9), (73, 1, 6, 5, 7),
+                                              (74, 3, 4, 5, 8)])
+def test_dense_gemm_bucket_split_bf16(monkeypatch, seed, nb, nm, nn, nk):
+    # K >= 32: products from three BF16 parts per operand on the BF16 matrix
+    # cores (3M), FP32 accumulation; the complex64 tolerance holds
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
+    spec, tensors, order, _ = dense_case(seed, nb, nm, nn, nk)
+    plan = api.Plan(api.Network(spec), order, precision="c64_mfma_bf16x3")
+    g = gemm_steps(plan)
+    assert len(g) == 1 and g[0]["gemm"]["mode"] == "bf16x3_3m" and g[0]["gemm"]["tile"][3] == 32, g
+    got = plan.contract_amplitude([], [])
+    want = oracle.contract(tensors, order)
+    assert abs(got - want) / abs(want) < TOL, (got, want)
+    # and the FP32 products of the same plan agree with it
+    ref = api.Plan(api.Network(spec), order, precision="c64_mfma_fp32").contract_amplitude([], [])
+    assert abs(got - ref) / abs(ref) < TOL
+
+
+def test_split_bf16_short_k_keeps_fp32_products(monkeypatch):
+    monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
+    spec, tensors, order, _ = dense_case(75, 1, 5, 5, 4)
+    plan = api.Plan(api.Network(spec), order, precision="c64_mfma_bf16x3")
+    g = gemm_steps(plan)
+    assert len(g) == 1 and g[0]["gemm"]["mode"] == "fp32_4m"
+    got = plan.contract_amplitude([], [])
+    want = oracle.contract(tensors, order)
+    assert abs(got - want) / abs(want) < TOL

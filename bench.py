@@ -45,9 +45,15 @@ def log(msg):
 
 
 def source_sha1(files):
+    """sha1 of the sources a kernel is built from; "file:Struct" stands for that struct's definition only."""
     h = hashlib.sha1()
     for f in files:
-        h.update(open(os.path.join(CSRC, f), "rb").read())
+        name, _, struct = f.partition(":")
+        data = open(os.path.join(CSRC, name), "rb").read()
+        if struct:
+            i = data.index(f"struct {struct} {{".encode())
+            data = data[i:data.index(b"\n};", i) + 3]
+        h.update(data)
     return h.hexdigest()
 
 
@@ -124,8 +130,9 @@ def op_roofline(plan, ops, n_steps):
         st = by_step[dom["op"]]
         kb = st["gemm"]["k_bits"]
         tile = st["gemm"]["tile"]
-        name = f"k_gemm<{tile[0]}, {tile[1]}, {tile[2]}, {tile[3]}>"
-        traffic = measured_traffic(f"gemm_k{1 << kb}_qaoa_n210_p1.md", ["gemm.hip", "qt_internal.h"],
+        mode = 1 if st["gemm"]["mode"].startswith("bf16") else 0
+        name = f"k_gemm<{tile[0]}, {tile[1]}, {tile[2]}, {tile[3]}, {mode}>"
+        traffic = measured_traffic(f"gemm_k{1 << kb}_qaoa_n210_p1.md", ["gemm.hip", "qt_internal.h:DevGemm"],
                                    kernel=name)
         achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": MFMA_FP32_PEAK_TF,

@@ -150,6 +150,10 @@ typedef struct {
    * (open_vars[0] most significant).  NULL / 0: a scalar amplitude. */
   int32_t n_open;
   const int32_t* open_vars;
+  /* MFMA precisions: a bucket is fused into one complex GEMM only when its
+   * output has at least this rank (4..28); smaller buckets stay bucket
+   * steps.  0: the default (12, or QT_GEMM_MIN_RANK). */
+  int32_t gemm_min_rank;
 } qt_plan_desc;
 
 /* Plan flags.
@@ -161,7 +165,8 @@ typedef struct {
  *     instead of once before the slices.
  *   QT_PLAN_GRAPH: when parameters and results are device memory,
  *     qt_contract_batch captures the launch sequence as a HIP graph on first
- *     use (per addresses and batch shape) and replays it afterwards. */
+ *     use (per addresses and batch shape) and replays it afterwards; set on
+ *     lightcones[0], qt_energy_grad does the same for its sequence. */
 enum { QT_PLAN_PLAIN = 1, QT_PLAN_FOLD_PREFIX = 2, QT_PLAN_GRAPH = 4 };
 
 typedef struct {
@@ -257,6 +262,15 @@ qt_status qt_contract_batch_noalloc(qt_plan* plan, int32_t n_points,
  * [n_points][p].  energy: [n_points] (required); dE_dgamma, dE_dbeta:
  * [n_points][p] or NULL (no gradient pass); per_edge: [n_points][n_edges]
  * or NULL.  Sums over edges run in FP64 in edge order.
+ * Execution: one launch of one workgroup per (edge, point), in order of
+ * decreasing cost.  Lightcones whose tensors fit the launch's LDS keep them
+ * there; larger ones run the same schedule from a global scratch area of
+ * their own (forward lightcones above 2^22 tensor elements instead take the
+ * plan's per-step schedule, outside the launch).  The device buffers of a
+ * list of lightcones (parameters, per-edge results, scratch) are built on
+ * first use and cached with it until one of its plans is freed; calls on
+ * the same list that overlap on different streams race on them and must be
+ * serialised by the caller (calls on one stream are ordered).
  * Precision: without gradient outputs the lightcones run in the plans'
  * precision.  With them, the forward and reverse pass run in complex128
  * whatever the plans' precision, and the energies returned are that pass's:
@@ -331,7 +345,8 @@ typedef struct {
 qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int32_t* n_ops, int32_t reset);
 
 /* Execution tunables of a plan; 0 selects the library default (or the
- * QT_LDS_WAVES, QT_LDS_MAX_RANK, QT_LDS_WAVES_MULTI, QT_LDS_WAVES_GRAD
+ * QT_LDS_WAVES, QT_LDS_MAX_RANK, QT_LDS_WAVES_MULTI, QT_LDS_WAVES_GRAD,
+ * QT_STEP_LG_TILES (log2 of step_tiles), QT_GEMM_TILES, QT_MULTI_LDS_CAP
  * environment variables when set).  They choose launch shapes and which
  * steps run from LDS rather than streaming, the role Eq. (1) of the paper
  * gives to its thread count per pairwise product; results stay within the
@@ -341,12 +356,22 @@ qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int3
  *                 larger steps stream from HBM
  *   multi_waves   wavefronts per workgroup of the batched lightcone launch
  *                 of qt_energy_grad (read from lightcones[0])
- *   grad_waves    the same for its gradient launch */
+ *   grad_waves    the same for its gradient launch
+ *   step_tiles    output tiles of 1024 elements per workgroup of the
+ *                 streaming bucket-step kernel (1, 2, 4, 8, 16)
+ *   gemm_tiles    output tiles per workgroup of the fused GEMM kernel
+ *                 (power of two, 1..64)
+ *   multi_lds_cap LDS bytes per workgroup of the batched lightcone launch
+ *                 (4096..163840): lightcones needing more run from global
+ *                 scratch in the same launch (read from lightcones[0]) */
 typedef struct {
   int32_t lds_waves;
   int32_t lds_max_rank;
   int32_t multi_waves;
   int32_t grad_waves;
+  int32_t step_tiles;
+  int32_t gemm_tiles;
+  int32_t multi_lds_cap;
 } qt_tuning;
 
 /* Sets a plan's tunables (QT_EINVAL outside the ranges above).  A change of

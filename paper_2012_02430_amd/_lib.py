@@ -61,7 +61,8 @@ class qt_plan_desc(ctypes.Structure):
     _fields_ = [("order", POINTER(c_int32)), ("n_order", c_int32), ("n_groups", c_int32),
                 ("group_step", POINTER(c_int32)), ("group_len", POINTER(c_int32)),
                 ("slice_vars", POINTER(c_int32)), ("precision", c_int32), ("slice_batch", c_int64),
-                ("flags", c_int32), ("n_open", c_int32), ("open_vars", POINTER(c_int32))]
+                ("flags", c_int32), ("n_open", c_int32), ("open_vars", POINTER(c_int32)),
+                ("gemm_min_rank", c_int32)]
 
 
 QT_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -114,7 +115,8 @@ QT_KCLASS_COUNT = 8
 
 # name -> (restype, argtypes); every symbol declared in include/*.h
 class qt_tuning(ctypes.Structure):
-    _fields_ = [("lds_waves", c_int32), ("lds_max_rank", c_int32), ("multi_waves", c_int32), ("grad_waves", c_int32)]
+    _fields_ = [("lds_waves", c_int32), ("lds_max_rank", c_int32), ("multi_waves", c_int32), ("grad_waves", c_int32),
+                ("step_tiles", c_int32), ("gemm_tiles", c_int32), ("multi_lds_cap", c_int32)]
 
 
 SIGNATURES = {

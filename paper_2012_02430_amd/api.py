@@ -135,7 +135,7 @@ class Plan:
     """A compiled plan (``qt_load_plan``) over a loaded network."""
 
     def __init__(self, network: Network, order, groups=(), precision="c64", slice_batch=0, plain=False,
-                 fold_prefix=False, graph=False, open_vars=()):
+                 fold_prefix=False, graph=False, open_vars=(), gemm_min_rank=0):
         lib = L.load()
         self.network = network
         groups = list(groups)
@@ -155,13 +155,14 @@ class Plan:
                            PRECISIONS[precision], int(slice_batch),
                            (L.QT_PLAN_PLAIN if plain else 0) | (L.QT_PLAN_FOLD_PREFIX if fold_prefix else 0)
                            | (L.QT_PLAN_GRAPH if graph else 0), len(self.open_vars),
-                           ctypes.cast(ov, ctypes.POINTER(ctypes.c_int32)))
+                           ctypes.cast(ov, ctypes.POINTER(ctypes.c_int32)), int(gemm_min_rank))
         h = ctypes.c_void_p()
         L.check(lib.qt_load_plan(network.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
         self.p = network.spec.p
         self.slice_batch, self.plain, self.fold_prefix = int(slice_batch), bool(plain), bool(fold_prefix)
         self.graph = bool(graph)
+        self.gemm_min_rank = int(gemm_min_rank)
 
     def signature(self) -> str:
         """Shape signature (network structure, order, slicing, precision, flags): the autotuner's cache key."""
@@ -177,18 +178,20 @@ class Plan:
                            "order": self.order, "groups": [[int(g[0]), [int(v) for v in g[1]]] for g in self.groups],
                            "open_vars": self.open_vars,
                            "precision": self.precision, "slice_batch": self.slice_batch, "plain": self.plain,
-                           "fold_prefix": self.fold_prefix}, sort_keys=True)
+                           "fold_prefix": self.fold_prefix, "gemm_min_rank": self.gemm_min_rank}, sort_keys=True)
         return hashlib.sha1(blob.encode()).hexdigest()
 
-    def set_tuning(self, lds_waves=0, lds_max_rank=0, multi_waves=0, grad_waves=0):
-        t = L.qt_tuning(int(lds_waves), int(lds_max_rank), int(multi_waves), int(grad_waves))
+    def set_tuning(self, lds_waves=0, lds_max_rank=0, multi_waves=0, grad_waves=0, step_tiles=0, gemm_tiles=0,
+                   multi_lds_cap=0):
+        """Sets every tunable (0: the library default); ``qt_plan_set_tuning``."""
+        t = L.qt_tuning(int(lds_waves), int(lds_max_rank), int(multi_waves), int(grad_waves), int(step_tiles),
+                        int(gemm_tiles), int(multi_lds_cap))
         L.check(L.load().qt_plan_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = L.qt_tuning()
         L.check(L.load().qt_plan_get_tuning(self.handle, ctypes.byref(t)))
-        return {"lds_waves": t.lds_waves, "lds_max_rank": t.lds_max_rank, "multi_waves": t.multi_waves,
-                "grad_waves": t.grad_waves}
+        return {name: getattr(t, name) for name, _ in L.qt_tuning._fields_}
 
     def __del__(self):
         if getattr(self, "handle", None) and L is not None and L._LIB is not None:
@@ -419,7 +422,7 @@ class EnergyModel:
     class representative.
     """
 
-    def __init__(self, n, edges, p, precision="c64", algo="min_fill", dedup=False):
+    def __init__(self, n, edges, p, precision="c64", algo="min_fill", dedup=False, graph=False):
         from paper_2012_02430_amd import network as N
 
         self.n, self.p = n, p
@@ -437,7 +440,7 @@ class EnergyModel:
         self.weights = np.array([float(len(m)) for m in self.classes])
         reps = [self.edges[m[0]] for m in self.classes]
         self.networks = [Network(N.energy_network(n, self.edges, p, u, v)) for u, v in reps]
-        self.plans = [Plan(net, net.order_greedy(algo)[0], precision=precision) for net in self.networks]
+        self.plans = [Plan(net, net.order_greedy(algo)[0], precision=precision, graph=graph) for net in self.networks]
         self._arr = (ctypes.c_void_p * len(self.plans))(*[pl.handle.value for pl in self.plans])
 
     def _call(self, npt, g_ptr, b_ptr, E_ptr, dg_ptr, db_ptr, pe_ptr, stream, w_ptr=None):
@@ -474,11 +477,13 @@ class EnergyModel:
 
         return hashlib.sha1(":".join(pl.signature() for pl in self.plans).encode()).hexdigest()
 
-    def set_tuning(self, multi_waves=0, grad_waves=0):
-        """Launch shape of the batched lightcone launches (read from the first plan)."""
+    def set_tuning(self, multi_waves=0, grad_waves=0, multi_lds_cap=0):
+        """Launch shape of the batched lightcone launch (read from the first plan): wavefronts per
+        workgroup of the energy and gradient launches, and the LDS bytes per workgroup above which
+        a lightcone runs from global scratch."""
         for pl in self.plans:
-            t = pl.get_tuning()
-            pl.set_tuning(t["lds_waves"], t["lds_max_rank"], multi_waves, grad_waves)
+            pl.set_tuning(**dict(pl.get_tuning(), multi_waves=multi_waves, grad_waves=grad_waves,
+                                 multi_lds_cap=multi_lds_cap))
 
     def energy_device(self, gammas, betas, grad=False, per_edge=False, stream=None):
         """Device-resident call: gammas/betas are float64 torch tensors [n_points, p] on the GPU.

@@ -434,7 +434,7 @@ hipError_t go(const DevGemm& g, int* exps, uint32_t* maxbits, hipStream_t stream
   // not hold for all of them).  A short-K tile is little work, so a few
   // tiles per workgroup pay its setup once; a long-K tile takes one.  The
   // range is a power of two that divides the tiles of one (item, batch tile).
-  const int want = std::max(1, env_int("QT_GEMM_TILES", g.nk <= 5 ? 16 : 1));
+  const int want = std::max(1, g.tiles > 0 ? g.tiles : env_int("QT_GEMM_TILES", g.nk <= 5 ? 16 : 1));
   const int lg_block = (g.nm - LM) + (g.nn - LN);
   int lg = 0;
   while (lg < lg_block && (2 << lg) <= want) ++lg;

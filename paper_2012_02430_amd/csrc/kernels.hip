@@ -483,7 +483,7 @@ void launch_step_t(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_ele
     t.lg_tiles = s.r - kLgTile;
     // a few tiles per workgroup: the per-item setup and the output max are
     // paid once per group of tiles
-    t.lg_tpb = std::min(std::min(t.lg_tiles, kMaxLgTpb), std::max(0, env_int("QT_STEP_LG_TILES", 3)));
+    t.lg_tpb = std::min(std::min(t.lg_tiles, kMaxLgTpb), std::max(0, s.lg_tpb));
     hipLaunchKernelGGL((k_step_big<E, SCALED, NIN>), dim3((unsigned)(n_elems >> (kLgTile + t.lg_tpb))), dim3(kWG), 0,
                        stream, t, exps, maxbits);
   } else {

@@ -474,10 +474,93 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
 namespace qt {
 namespace {
 
+// Synchronisation between levels.  The barrier's workgroup-scope release
+// and acquire order global as well as LDS accesses, and the wavefronts of a
+// workgroup run on one compute unit and share its vector L1, so an item in
+// global scratch needs no device-scope fence (whose L2 write-back would be
+// paid at every level).
+template <bool GLOBAL>
+__device__ __forceinline__ void x_level_sync() {
+  __syncthreads();
+}
+
+// Byte layout of a program's global scratch per point: element area, then
+// the scale slots (max bits, then exponents), then the gradient records.
+struct XArea {
+  int64_t elem_bytes, slot_bytes, rec_bytes;
+};
+__host__ __device__ inline XArea x_area(int n_slots, int n_recs, int area_elems, int elt) {
+  XArea a;
+  a.elem_bytes = ((int64_t)area_elems * elt + 15) & ~(int64_t)15;
+  a.slot_bytes = 4 * (int64_t)((n_slots + 3) & ~3);
+  a.rec_bytes = 8 * (int64_t)((n_recs + 1) & ~1);
+  return a;
+}
+
+// One (program, point) item of the multi-program executor: the point's gate
+// table, the program's levels, then its value in an FP64 epilogue (the
+// product of the closing scalars with the accumulated exponent).  `area`
+// is the item's element area (LDS, or global scratch with GLOBAL).
+template <typename E, bool SCALED, bool GLOBAL>
+__device__ __forceinline__ void x_multi_item(const XMulti& M, const XProg& P, int prog_id,
+                                             const XStep* __restrict__ psteps, const uint2* __restrict__ punits,
+                                             const int32_t* __restrict__ plev, const XFinal* __restrict__ finals,
+                                             const XCtx& c, int tid, int wave, int nw, E* area, uint32_t* smax,
+                                             int* sexp) {
+  for (int i = tid; i < P.n_slots; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  if (tid < 2) {
+    area[tid].x = 1;
+    area[tid].y = 0;
+  }
+  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x)
+    area[kXGate + t] = x_gate<E>(t, M.params + (int64_t)c.pt * 2 * M.p, M.p);
+  x_level_sync<GLOBAL>();
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw) {
+      const uint2 un = punits[u];
+      const XStep& st = psteps[un.x];
+      const bool big = st.r >= kXBigRank;
+      if (st.n_in <= 2) {
+        if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 2, 1>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+      } else if (st.n_in <= 4) {
+        if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 4, 1>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+      } else {
+        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+        else x_unit<E, SCALED, 8, 1>(st, un.y, c, area, smax, sexp, nullptr, nullptr);
+      }
+    }
+    x_level_sync<GLOBAL>();
+  }
+  if (tid == 0) {
+    double re = 1.0, im = 0.0, ex = P.log2_const;
+    for (int f = 0; f < P.n_finals; ++f) {
+      const XFinal& F = finals[P.finals_off + f];
+      const E a = area[F.lds_off];
+      const double ar = (double)a.x, ai = (double)a.y;
+      if (SCALED && F.slot >= 0) ex += sexp[F.slot];
+      const double nr = re * ar - im * ai;
+      im = re * ai + im * ar;
+      re = nr;
+    }
+    double* o = M.out + 3 * ((int64_t)c.pt * M.n_progs + prog_id);
+    o[0] = re;
+    o[1] = im;
+    o[2] = ex;
+  }
+}
+
 // Multi-program executor: one workgroup per (program, point) item runs a
-// whole network (a per-edge lightcone) in LDS, then forms its scalar
-// result: the product of the network's closing scalars in FP64 with the
-// accumulated power-of-two exponent.
+// whole network (a per-edge lightcone) -- every edge and point of an
+// energy evaluation in one launch.  Items whose program fits the launch's
+// LDS keep every tensor there; the few larger ones run the same schedule
+// from their own global scratch area.
 template <typename E, bool SCALED>
 __global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, const XProg* __restrict__ progs,
                                                             const XStep* __restrict__ steps,
@@ -486,11 +569,6 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, cons
                                                             const XFinal* __restrict__ finals,
                                                             const int32_t* __restrict__ item_prog) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int slots16 = (M.n_slots + 3) & ~3;
-  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
-  int* sexp = reinterpret_cast<int*>(smem + 4 * slots16);
-  E* lds = reinterpret_cast<E*>(smem + 8 * slots16);
-
   const uint32_t item = blockIdx.x;
   const int prog_id = item_prog[item / (uint32_t)M.n_points];
   const XProg& P = progs[prog_id];
@@ -502,57 +580,20 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, cons
   c.lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nw = blockDim.x >> 6;
-
-  for (int i = tid; i < P.n_slots; i += blockDim.x) {
-    smax[i] = 0u;
-    sexp[i] = 0;
-  }
-  if (tid < 2) {
-    lds[tid].x = 1;
-    lds[tid].y = 0;
-  }
-  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x)
-    lds[kXGate + t] = x_gate<E>(t, M.params + (int64_t)c.pt * 2 * M.p, M.p);
-  __syncthreads();
-
-  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
   const XStep* psteps = steps + P.steps_off;
   const uint2* punits = units + P.units_off;
   const int32_t* plev = level_off + P.levels_off;
-  for (int L = 0; L < P.n_levels; ++L) {
-    const int u_end = plev[L + 1];
-    for (int u = plev[L] + wave; u < u_end; u += nw) {
-      const uint2 un = punits[u];
-      const XStep& st = psteps[un.x];
-      const bool big = st.r >= kXBigRank;
-      if (st.n_in <= 2) {
-        if (big) x_unit<E, SCALED, 2, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-        else x_unit<E, SCALED, 2, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      } else if (st.n_in <= 4) {
-        if (big) x_unit<E, SCALED, 4, kBig>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-        else x_unit<E, SCALED, 4, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      } else {
-        if (big) x_unit<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-        else x_unit<E, SCALED, 8, 1>(st, un.y, c, lds, smax, sexp, nullptr, nullptr);
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double re = 1.0, im = 0.0, ex = P.log2_const;
-    for (int f = 0; f < P.n_finals; ++f) {
-      const XFinal& F = finals[P.finals_off + f];
-      const E a = lds[F.lds_off];
-      const double ar = (double)a.x, ai = (double)a.y;
-      if (SCALED && F.slot >= 0) ex += sexp[F.slot];
-      const double nr = re * ar - im * ai;
-      im = re * ai + im * ar;
-      re = nr;
-    }
-    double* o = M.out + 3 * ((int64_t)c.pt * M.n_progs + prog_id);
-    o[0] = re;
-    o[1] = im;
-    o[2] = ex;
+  if (P.scratch_off >= 0) {
+    const XArea a = x_area(P.n_slots, 0, P.area_elems, (int)sizeof(E));
+    char* base = M.scratch + P.scratch_off + (int64_t)c.pt * P.scratch_stride;
+    x_multi_item<E, SCALED, true>(M, P, prog_id, psteps, punits, plev, finals, c, tid, wave, nw,
+                                  reinterpret_cast<E*>(base), reinterpret_cast<uint32_t*>(base + a.elem_bytes),
+                                  reinterpret_cast<int*>(base + a.elem_bytes + a.slot_bytes));
+  } else {
+    const int slots16 = (M.n_slots + 3) & ~3;
+    x_multi_item<E, SCALED, false>(M, P, prog_id, psteps, punits, plev, finals, c, tid, wave, nw,
+                                   reinterpret_cast<E*>(smem + 8 * slots16), reinterpret_cast<uint32_t*>(smem),
+                                   reinterpret_cast<int*>(smem + 4 * slots16));
   }
 }
 
@@ -823,7 +864,35 @@ __device__ __forceinline__ void x_grad_epilogue(const XMulti& M, const XProg& P,
 // recomputation steps and its reverse operations, all from one level
 // schedule, then forms the item's value (as the multi-program executor) and
 // its derivatives by the 2p parameters, each the FP64 sum of the parameter's
-// gradient records in record order.
+// gradient records in record order.  Items too large for the launch's LDS
+// run the same schedule from their global scratch area.
+template <typename E, bool SCALED, bool GLOBAL>
+__device__ __forceinline__ void x_grad_item(const XMulti& M, const XProg& P, int prog_id,
+                                            const XStep* __restrict__ psteps, const XRev* __restrict__ prevs,
+                                            const uint2* __restrict__ punits, const int32_t* __restrict__ plev,
+                                            const XFinal* __restrict__ pfin, const int32_t* __restrict__ rec_off,
+                                            const XCtx& c, int tid, int wave, int nw, E* area, uint32_t* smax,
+                                            int* sexp, double* gacc) {
+  const double* prm = M.params + (int64_t)c.pt * 2 * M.p;
+  for (int i = tid; i < P.n_slots; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  if (tid < 2) {
+    area[tid].x = 1;
+    area[tid].y = 0;
+  }
+  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x) area[kXGate + t] = x_gate<E>(t, prm, M.p);
+  x_level_sync<GLOBAL>();
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw)
+      x_grad_unit<E, SCALED>(punits[u], psteps, prevs, P, pfin, c, area, smax, sexp, gacc, prm);
+    x_level_sync<GLOBAL>();
+  }
+  x_grad_epilogue<E, SCALED>(M, P, prog_id, pfin, rec_off, c.pt, tid, area, sexp, gacc);
+}
+
 template <typename E, bool SCALED>
 __global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_lds_grad(const XMulti M, const XProg* __restrict__ progs,
                                                            const XStep* __restrict__ steps,
@@ -834,13 +903,6 @@ __global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6,
                                                            const int32_t* __restrict__ item_prog,
                                                            const int32_t* __restrict__ rec_off) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int slots16 = (M.n_slots + 3) & ~3;
-  const int recs2 = (M.n_recs + 1) & ~1;
-  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
-  int* sexp = reinterpret_cast<int*>(smem + 4 * slots16);
-  double* gacc = reinterpret_cast<double*>(smem + 8 * slots16);
-  E* lds = reinterpret_cast<E*>(smem + 8 * slots16 + 8 * recs2);
-
   const uint32_t item = blockIdx.x;
   const int prog_id = item_prog[item / (uint32_t)M.n_points];
   const XProg& P = progs[prog_id];
@@ -852,99 +914,26 @@ __global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6,
   c.lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nw = blockDim.x >> 6;
-  const double* prm = M.params + (int64_t)c.pt * 2 * M.p;
-
-  for (int i = tid; i < P.n_slots; i += blockDim.x) {
-    smax[i] = 0u;
-    sexp[i] = 0;
-  }
-  if (tid < 2) {
-    lds[tid].x = 1;
-    lds[tid].y = 0;
-  }
-  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x) lds[kXGate + t] = x_gate<E>(t, prm, M.p);
-  __syncthreads();
-
   const XStep* psteps = steps + P.steps_off;
   const XRev* prevs = revs + P.revs_off;
   const uint2* punits = units + P.units_off;
   const int32_t* plev = level_off + P.levels_off;
   const XFinal* pfin = finals + P.finals_off;
-  for (int L = 0; L < P.n_levels; ++L) {
-    const int u_end = plev[L + 1];
-    for (int u = plev[L] + wave; u < u_end; u += nw)
-      x_grad_unit<E, SCALED>(punits[u], psteps, prevs, P, pfin, c, lds, smax, sexp, gacc, prm);
-    __syncthreads();
+  if (P.scratch_off >= 0) {
+    const XArea a = x_area(P.n_slots, P.n_recs, P.area_elems, (int)sizeof(E));
+    char* base = M.scratch + P.scratch_off + (int64_t)c.pt * P.scratch_stride;
+    x_grad_item<E, SCALED, true>(M, P, prog_id, psteps, prevs, punits, plev, pfin, rec_off, c, tid, wave, nw,
+                                 reinterpret_cast<E*>(base), reinterpret_cast<uint32_t*>(base + a.elem_bytes),
+                                 reinterpret_cast<int*>(base + a.elem_bytes + a.slot_bytes),
+                                 reinterpret_cast<double*>(base + a.elem_bytes + 2 * a.slot_bytes));
+  } else {
+    const int slots16 = (M.n_slots + 3) & ~3;
+    const int recs2 = (M.n_recs + 1) & ~1;
+    x_grad_item<E, SCALED, false>(M, P, prog_id, psteps, prevs, punits, plev, pfin, rec_off, c, tid, wave, nw,
+                                  reinterpret_cast<E*>(smem + 8 * slots16 + 8 * recs2),
+                                  reinterpret_cast<uint32_t*>(smem), reinterpret_cast<int*>(smem + 4 * slots16),
+                                  reinterpret_cast<double*>(smem + 8 * slots16));
   }
-  x_grad_epilogue<E, SCALED>(M, P, prog_id, pfin, rec_off, c.pt, tid, lds, sexp, gacc);
-}
-
-// The gradient schedule of one program whose tensors do not fit in LDS,
-// run level by level, one launch per level, with each item's tensors, scale
-// slots and gradient records in its own slice of a global scratch area.
-// Launch boundaries order every write before the reads of later levels.
-struct XScratch {
-  void* arena;          // [points][arena_stride] elements
-  uint32_t* smax;       // [points][slot_stride]
-  int* sexp;            // [points][slot_stride]
-  double* gacc;         // [points][rec_stride]
-  int64_t arena_stride;
-  int32_t slot_stride;
-  int32_t rec_stride;
-};
-
-template <typename E, bool SCALED>
-__global__ __launch_bounds__(64) void k_grad_init(const XMulti M, const XProg* __restrict__ progs, int prog_id,
-                                                  const XScratch S) {
-  const XProg& P = progs[prog_id];
-  const uint32_t pt = blockIdx.x;
-  E* lds = reinterpret_cast<E*>(S.arena) + (int64_t)pt * S.arena_stride;
-  uint32_t* smax = S.smax + (int64_t)pt * S.slot_stride;
-  int* sexp = S.sexp + (int64_t)pt * S.slot_stride;
-  for (int i = threadIdx.x; i < P.n_slots; i += 64) {
-    smax[i] = 0u;
-    sexp[i] = 0;
-  }
-  if (threadIdx.x < 2) {
-    lds[threadIdx.x].x = 1;
-    lds[threadIdx.x].y = 0;
-  }
-  for (int t = threadIdx.x; t < x_gate_elems(M.p); t += 64)
-    lds[kXGate + t] = x_gate<E>(t, M.params + (int64_t)pt * 2 * M.p, M.p);
-}
-
-template <typename E, bool SCALED>
-__global__ __launch_bounds__(64) void k_grad_level(const XMulti M, const XProg* __restrict__ progs,
-                                                   const XStep* __restrict__ steps, const XRev* __restrict__ revs,
-                                                   const uint2* __restrict__ units,
-                                                   const int32_t* __restrict__ level_off,
-                                                   const XFinal* __restrict__ finals, int prog_id, int level,
-                                                   const XScratch S) {
-  const XProg& P = progs[prog_id];
-  XCtx c;
-  c.pt = blockIdx.y;
-  c.sb = 0;
-  c.sid = 0;
-  c.lane = threadIdx.x;
-  E* lds = reinterpret_cast<E*>(S.arena) + (int64_t)c.pt * S.arena_stride;
-  uint32_t* smax = S.smax + (int64_t)c.pt * S.slot_stride;
-  int* sexp = S.sexp + (int64_t)c.pt * S.slot_stride;
-  double* gacc = S.gacc + (int64_t)c.pt * S.rec_stride;
-  const int u = level_off[P.levels_off + level] + blockIdx.x;
-  x_grad_unit<E, SCALED>(units[P.units_off + u], steps + P.steps_off, revs + P.revs_off, P, finals + P.finals_off, c,
-                         lds, smax, sexp, gacc, M.params + (int64_t)c.pt * 2 * M.p);
-}
-
-template <typename E, bool SCALED>
-__global__ __launch_bounds__(64) void k_grad_final(const XMulti M, const XProg* __restrict__ progs,
-                                                   const XFinal* __restrict__ finals,
-                                                   const int32_t* __restrict__ rec_off, int prog_id,
-                                                   const XScratch S) {
-  const XProg& P = progs[prog_id];
-  const uint32_t pt = blockIdx.x;
-  const E* lds = reinterpret_cast<const E*>(S.arena) + (int64_t)pt * S.arena_stride;
-  x_grad_epilogue<E, SCALED>(M, P, prog_id, finals + P.finals_off, rec_off, pt, (int)threadIdx.x, lds,
-                             S.sexp + (int64_t)pt * S.slot_stride, S.gacc + (int64_t)pt * S.rec_stride);
 }
 
 // One workgroup per output (r, q): lane-strided partial sums in index order
@@ -986,19 +975,9 @@ hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
-                              uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
-                              int rec_stride, hipStream_t stream) {
-  const XScratch S{arena, smax, sexp, gacc, arena_stride, slot_stride, rec_stride};
-  const unsigned np = (unsigned)m.n_points;
-  hipLaunchKernelGGL((k_grad_init<double2, false>), dim3(np), dim3(64), 0, stream, m, m.progs, prog_id, S);
-  for (int L = 0; L < n_levels; ++L)
-    if (level_sizes[L] > 0)
-      hipLaunchKernelGGL((k_grad_level<double2, false>), dim3((unsigned)level_sizes[L], np), dim3(64), 0, stream, m,
-                         m.progs, m.steps, m.revs, m.units, m.level_off, m.finals, prog_id, L, S);
-  hipLaunchKernelGGL((k_grad_final<double2, false>), dim3(np), dim3(64), 0, stream, m, m.progs, m.finals, m.rec_off,
-                     prog_id, S);
-  return hipGetLastError();
+int64_t multi_scratch_bytes(int n_slots, int n_recs, int area_elems, bool c128) {
+  const XArea a = x_area(n_slots, n_recs, area_elems, c128 ? 16 : 8);
+  return (a.elem_bytes + 2 * a.slot_bytes + a.rec_bytes + 255) & ~(int64_t)255;
 }
 
 hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream,

@@ -163,6 +163,8 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     if (d->n_groups < 0 || d->n_groups > 64 || (d->n_groups > 0 && (!d->group_step || !d->group_len)))
       return fail(QT_EINVAL, "qt_load_plan: bad groups");
     if (d->slice_batch < 0) return fail(QT_EINVAL, "qt_load_plan: negative slice_batch");
+    if (d->gemm_min_rank != 0 && (d->gemm_min_rank < 4 || d->gemm_min_rank > kGemmMaxRank))
+      return fail(QT_EINVAL, "qt_load_plan: gemm_min_rank must be 0 or 4.." + std::to_string(kGemmMaxRank));
     if (d->n_open < 0 || d->n_open > kMaxOpen || (d->n_open > 0 && !d->open_vars))
       return fail(QT_EINVAL, "qt_load_plan: n_open out of 0.." + std::to_string(kMaxOpen) + " or null open_vars");
 
@@ -349,7 +351,7 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     // (product steps), so the result is that of eliminating the same
     // variables one by one, with a smaller intermediate.
     const bool mfma = d->precision == QT_C64_SCALED_MFMA_FP32 || d->precision == QT_C64_SCALED_MFMA_BF16X3;
-    const int gemm_min_rank = env_int("QT_GEMM_MIN_RANK", 12);
+    const int gemm_min_rank = d->gemm_min_rank > 0 ? d->gemm_min_rank : env_int("QT_GEMM_MIN_RANK", 12);
     auto subset = [](const std::vector<int>& a, const std::vector<int>& b) {
       for (int x : a)
         if (std::find(b.begin(), b.end(), x) == b.end()) return false;

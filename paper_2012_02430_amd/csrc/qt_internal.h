@@ -258,6 +258,14 @@ struct XProg {
   int32_t recs_off;    // first of 2p + 1 offsets of its gradient records, grouped by parameter
   int32_t n_recs;
   double log2_const;   // exponent of the |+> normalisations
+  // A program too large for the launch's LDS runs from global scratch in
+  // the same launch: its element area (area_elems), scale slots and
+  // gradient records for point pt start at byte scratch_off + pt *
+  // scratch_stride of XMulti::scratch.  -1: LDS.
+  int64_t scratch_off;
+  int64_t scratch_stride;
+  int32_t area_elems;
+  int32_t pad;
 };
 
 // Reverse (adjoint) operation of the gradient executor.  For one input T_j
@@ -309,9 +317,10 @@ struct XMulti {
   int32_t n_points;
   int32_t n_progs;
   int32_t p;
-  int32_t lds_elems;       // max over programs
-  int32_t n_slots;         // max over programs
-  int32_t n_recs;          // max over programs
+  int32_t lds_elems;       // max over the programs run from LDS
+  int32_t n_slots;         // max over the programs run from LDS
+  int32_t n_recs;          // max over the programs run from LDS
+  char* scratch;           // areas of the programs run from global scratch
 };
 
 // Fused GEMM bucket: C[b, m, n] = sum_k A[b, m, k] B[b, n, k] over complex
@@ -338,7 +347,8 @@ struct DevGemm {
   int32_t c_exp_base, c_exp_pt, c_exp_sb;
   int32_t tb, tm, tn;      // tile bits of the b, m, n counters (chosen on the host)
   int32_t tk;              // K stage depth (8, 16 or 64; 32 in mode 1)
-  int32_t mode;            // 0: FP32 products (4M); 1: split-BF16 products (3M), QT_C64_SCALED_MFMA_BF16X3
+  int32_t mode;            // 0: FP32 products (3M at depth 64, else 4M); 1: split-BF16 products (3M), QT_C64_SCALED_MFMA_BF16X3
+  int32_t tiles;           // output tiles per workgroup (0: the default for the depth)
   // storage bits of each counter in each tensor
   uint32_t a_bm, a_mm, a_km, b_bm, b_nm, b_km, c_bm, c_mm, c_nm;
   // the same without the bits a tile or a stage covers (masked increments)
@@ -508,11 +518,8 @@ hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c
 // The gradient executor runs in complex128 (unscaled) for every precision.
 hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream);
 size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128);
-// The gradient schedule of one program with its tensors in global scratch,
-// one launch per level (level_sizes: units per level, host memory).
-hipError_t launch_grad_global(const XMulti& m, int prog_id, const int32_t* level_sizes, int n_levels, void* arena,
-                              uint32_t* smax, int* sexp, double* gacc, int64_t arena_stride, int slot_stride,
-                              int rec_stride, hipStream_t stream);
+// Bytes of global scratch per point of a program run from it.
+int64_t multi_scratch_bytes(int n_slots, int n_recs, int area_elems, bool c128);
 // out[r][q] = sum_i in[(r * n + i) * nq + q] in FP64, in order of i.
 // With `weights` ([n], device), entry i counts weights[i] times.
 hipError_t launch_rows_sum(const double* in, int rows, int n, int nq, double* out, hipStream_t stream,

@@ -1084,10 +1084,13 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
       return launch_step(d, c128, scaled, ws.exps, ws.maxbits, ws.step_elems[i], stream, &launches, nullptr);
     });
   };
+  const int step_lg_tpb =
+      plan.tuning.step_tiles > 0 ? ilog2(plan.tuning.step_tiles) : std::max(0, env_int("QT_STEP_LG_TILES", 3));
   auto run_op = [&](const qt_plan::Workspace::Op& op, int64_t cb) -> hipError_t {
     if (op.seg < 0 && plan.steps[op.step].gemm) {
       DevGemm g = ws.gemms[op.step];
       g.chunk_base = cb;
+      g.tiles = plan.tuning.gemm_tiles;
       const SymStep& st = plan.steps[op.step];
       ++launches;
       return timed(plan, stream, QT_KCLASS_GEMM, op.step, st.bytes_c64 * g.n_items, st.flops * g.n_items,
@@ -1096,6 +1099,7 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
     if (op.seg < 0) {
       DevStep d = ws.steps[op.step];
       d.chunk_base = cb;
+      d.lg_tpb = step_lg_tpb;
       return step(d, op.step);
     }
     auto& S = ws.segs[op.seg];
@@ -1389,10 +1393,16 @@ extern "C" qt_status qt_plan_set_tuning(qt_plan* plan, const qt_tuning* t) {
     return fail(QT_EINVAL, "qt_plan_set_tuning: wavefronts per workgroup must be 0 or 1..16");
   if (t->lds_max_rank != 0 && (t->lds_max_rank < 6 || t->lds_max_rank > 16))
     return fail(QT_EINVAL, "qt_plan_set_tuning: lds_max_rank must be 0 or 6..16");
+  auto pow2_upto = [](int32_t v, int32_t hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
+  if (!pow2_upto(t->step_tiles, 16)) return fail(QT_EINVAL, "qt_plan_set_tuning: step_tiles must be 0, 1, 2, 4, 8 or 16");
+  if (!pow2_upto(t->gemm_tiles, 64)) return fail(QT_EINVAL, "qt_plan_set_tuning: gemm_tiles must be 0 or a power of two up to 64");
+  if (t->multi_lds_cap != 0 && (t->multi_lds_cap < 4096 || t->multi_lds_cap > 160 * 1024))
+    return fail(QT_EINVAL, "qt_plan_set_tuning: multi_lds_cap must be 0 or 4096..163840");
   const bool reschedule = t->lds_waves != plan->tuning.lds_waves || t->lds_max_rank != plan->tuning.lds_max_rank;
+  const bool relaunch = t->step_tiles != plan->tuning.step_tiles || t->gemm_tiles != plan->tuning.gemm_tiles;
   plan->tuning = *t;
+  if ((reschedule || relaunch) && plan->graphs) plan->graphs->clear();
   if (reschedule) {
-    if (plan->graphs) plan->graphs->clear();
     plan->ws.reset();
   }
   return QT_OK;

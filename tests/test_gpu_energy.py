@@ -121,30 +121,65 @@ def test_energy_c128_n1000_p3_sampled():
             assert abs(pe[i, e] - want) < TOL["c128"], (i, e)
 
 
+def _job(err):
+    """(programs in LDS, programs from global scratch) of the last job built."""
+    ln = [ln for ln in err.splitlines() if ln.startswith("[qt grad] job:")][-1]
+    return int(ln.split(":")[1].split()[0]), int(ln.split(",")[2].split()[0])
+
+
 @pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_energy_oversized_lightcones_take_the_step_schedule(precision, capfd, monkeypatch):
-    # an LDS budget below what the largest lightcones need sends them through
-    # the general per-step schedule (streaming launches); the others stay in
-    # the batched LDS launch.  Every edge is checked against the oracle.
+def test_energy_oversized_lightcones_run_from_global_scratch(precision, capfd, monkeypatch):
+    # an LDS budget below what the largest lightcones need sends them to
+    # global scratch in the same launch; the others stay in LDS.  The same
+    # schedule runs either way, so every value is bitwise that of the run
+    # with every lightcone in LDS, and every edge is checked against the oracle.
     n, p = 40, 3
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, 3, seed=12)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
+    monkeypatch.setenv("QT_MULTI_LDS_CAP", str(160 * 1024))  # LDS per workgroup up to the budget
     model = api.EnergyModel(n, edges, p, precision=precision)
-    n_fit = len(edges)
+    E0, pe0 = model.energy(gs, bs, per_edge=True)
+    n_fit0, n_glob0 = _job(capfd.readouterr().err)
+    assert n_fit0 + n_glob0 == len(edges) and n_fit0 > 0
+    n_fit = n_fit0
     budget = 160 * 1024
-    while budget > 2048:  # shrink the budget until some lightcones no longer fit
+    while budget > 2048:  # shrink the budget until more lightcones no longer fit
         budget -= 2048
         monkeypatch.setenv("QT_LDS_BYTES", str(budget))
         E, pe = model.energy(gs, bs, per_edge=True)
-        line = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("[qt grad] job:")][-1]
-        n_fit = int(line.split(":")[1].split()[0])
-        if n_fit < len(edges):
+        n_fit, n_glob = _job(capfd.readouterr().err)
+        if n_fit < n_fit0:
             break
-    assert 0 < n_fit < len(edges), (budget, n_fit)
+    assert 0 < n_fit < n_fit0 and n_fit + n_glob == len(edges), (budget, n_fit, n_glob)
+    assert np.array_equal(E, E0) and np.array_equal(pe, pe0)
     for i in range(3):
         want = np.array([oracle.edge_energy(n, edges, gs[i], bs[i], u, v).real for u, v in edges])
         assert np.abs(pe[i] - want).max() < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_energy_lds_cap_tunable_moves_lightcones_to_global_scratch(precision, capfd, monkeypatch):
+    # the multi_lds_cap tunable: lightcones needing more LDS than the cap run
+    # from global scratch in the same launch, bitwise as from LDS
+    n, p = 40, 3
+    edges = regular_graph(n, 3, 2)
+    gs, bs = qaoa_params(p, 5, seed=13)
+    monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
+    model = api.EnergyModel(n, edges, p, precision=precision)
+    model.set_tuning(multi_lds_cap=160 * 1024)
+    ref = model.energy(gs, bs, per_edge=True)
+    n_glob0 = _job(capfd.readouterr().err)[1]
+    for cap in (16384, 65536):
+        model.set_tuning(multi_lds_cap=cap)
+        got = model.energy(gs, bs, per_edge=True)
+        n_fit, n_glob = _job(capfd.readouterr().err)
+        assert n_fit + n_glob == len(edges) and n_glob >= n_glob0
+        if cap == 16384:
+            assert n_glob > n_glob0
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y), cap
+    model.set_tuning()
 
 
 def test_dedup_energy_n1000_p3_matches_all_edges():

@@ -151,13 +151,15 @@ def _job_line(err):
 def test_checkpoint_recompute_under_forced_budget(precision, capfd, monkeypatch):
     # budgets below what keeps every intermediate force dropped checkpoints
     # that are recomputed in the reverse schedule, and below what any
-    # recomputation reaches, the level-per-launch path from global scratch;
-    # both run the same arithmetic, so the results are bitwise equal
+    # recomputation reaches, programs that run from global scratch in the
+    # same launch; all run the same arithmetic, so the results are bitwise
+    # equal
     n, p = 10, 2
     edges = regular_graph(n, 3, 0)
     gs, bs = qaoa_params(p, 4, seed=7)
     model = api.EnergyModel(n, edges, p, precision=precision)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
+    monkeypatch.setenv("QT_MULTI_LDS_CAP", str(160 * 1024))  # LDS per workgroup up to the budget
     full = model.energy(gs, bs, grad=True)
     need, n_global = _job_line(capfd.readouterr().err)
     assert n_global == 0
@@ -186,6 +188,7 @@ def test_global_scratch_path_matches_lds(precision, capfd, monkeypatch):
     edges = regular_graph(n, 3, 5)
     gs, bs = qaoa_params(p, 3, seed=8)
     model = api.EnergyModel(n, edges, p, precision=precision)
+    monkeypatch.setenv("QT_MULTI_LDS_CAP", str(160 * 1024))
     lds = model.energy(gs, bs, per_edge=True, grad=True)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
     monkeypatch.setenv("QT_GRAD_LDS_BYTES", "1024")

@@ -90,3 +90,47 @@ def test_graph_plan_with_host_arrays_runs_eagerly():
     a, pa = eager.contract_batch(gs, bs, per_slice=True)
     c, pc = graph.contract_batch(gs, bs, per_slice=True)
     assert np.array_equal(a, c) and np.array_equal(pa, pc)
+
+
+@pytest.mark.parametrize("grad,dedup", [(False, False), (True, False), (True, True)])
+def test_energy_graph_replays_equal_eager(grad, dedup, capfd, monkeypatch):
+    # QT_PLAN_GRAPH on the lightcones: qt_energy_grad captures its device
+    # sequence (parameter copy, the batched launch, FP64 sums, result copies)
+    # once per argument set and replays it; parameters change in place
+    # between replays, with eager work and synchronisations in between.  Some
+    # lightcones run from global scratch (LDS cap), so both item kinds are in
+    # the graph.
+    n, p, npt = 20, 3, 4
+    edges = regular_graph(n, 3, 9)
+    eager = api.EnergyModel(n, edges, p, precision="c64", dedup=dedup)
+    graph = api.EnergyModel(n, edges, p, precision="c64", dedup=dedup, graph=True)
+    for m in (eager, graph):
+        m.set_tuning(multi_lds_cap=8192)
+    monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
+    g = torch.zeros(npt, p, dtype=torch.float64, device="cuda")
+    b = torch.zeros(npt, p, dtype=torch.float64, device="cuda")
+    n_pl = len(graph.plans)
+    E = torch.zeros(npt, dtype=torch.float64, device="cuda")
+    pe = torch.zeros(npt, n_pl, dtype=torch.float64, device="cuda")
+    dg = torch.zeros(npt, p, dtype=torch.float64, device="cuda")
+    db = torch.zeros(npt, p, dtype=torch.float64, device="cuda")
+    w = torch.tensor(graph.weights, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    for r in range(4):
+        gs, bs = qaoa_params(p, npt, seed=40 + r)
+        g.copy_(torch.from_numpy(gs))
+        b.copy_(torch.from_numpy(bs))
+        graph._call(npt, g.data_ptr(), b.data_ptr(), E.data_ptr(), dg.data_ptr() if grad else None,
+                    db.data_ptr() if grad else None, pe.data_ptr(), s, w.data_ptr())
+        junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        want = eager.energy(gs, bs, per_edge=True, grad=grad)
+        assert np.array_equal(E.cpu().numpy(), want[0]), r
+        got_pe = pe.cpu().numpy()
+        assert np.array_equal(got_pe[:, eager.class_of] if dedup else got_pe, want[1]), r
+        if grad:
+            assert np.array_equal(dg.cpu().numpy(), want[2]) and np.array_equal(db.cpu().numpy(), want[3]), r
+        del junk
+    err = capfd.readouterr().err
+    globs = [int(ln.split(",")[2].split()[0]) for ln in err.splitlines() if ln.startswith("[qt grad] job:")]
+    assert globs and max(globs) > 0

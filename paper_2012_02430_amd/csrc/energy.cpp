@@ -31,6 +31,7 @@ struct Program {
   std::vector<int32_t> levels;
   std::vector<XFinal> finals;
   std::vector<int32_t> rec_off;  // gradient programs: 2p + 1 record offsets
+  std::vector<std::vector<int>> lsteps;  // forward programs: steps of each level
   int n_levels = 0, n_slots = 0, n_recs = 0, lds_elems = 0;
   int dropped = 0, recomputed = 0;
   double log2_const = 0, cost = 0, bytes_c64 = 0, flops = 0;
@@ -102,6 +103,29 @@ void push_step_units(const qt_plan& plan, int s, int xs_index, int elt, std::vec
   for (int64_t c = 0; c < chunks; ++c) units.push_back(make_uint2((uint32_t)xs_index, (uint32_t)c));
 }
 
+// Units of a forward program run for P points per workgroup, level by
+// level: a step with fewer than 64 outputs takes 64 / 2^r points per unit
+// (unit index: the block of points); a larger one takes P x chunks units of
+// its per-point size (unit index: point x chunks + chunk).  With P = 1 these
+// are the per-point units.
+void pts_units(const Program& pg, int P, int elt, std::vector<uint2>& units, std::vector<int32_t>& levels) {
+  for (const auto& lv : pg.lsteps) {
+    levels.push_back((int32_t)(units.size()));
+    for (int xs : lv) {
+      const int r = pg.steps[xs].r;
+      if (r < 6) {
+        const int per = 64 >> r;
+        for (int b = 0; b < (P + per - 1) / per; ++b) units.push_back(make_uint2((uint32_t)xs, (uint32_t)b));
+      } else {
+        const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, pg.steps[xs].n_in, elt));
+        for (int q = 0; q < P; ++q)
+          for (int64_t c = 0; c < chunks; ++c) units.push_back(make_uint2((uint32_t)xs, (uint32_t)(q * chunks + c)));
+      }
+    }
+  }
+  levels.push_back((int32_t)units.size());
+}
+
 int count_intermediates(const qt_plan& plan) {
   int n = 0;
   for (const SymTensor& T : plan.tensors) n += T.leaf < 0;
@@ -155,10 +179,14 @@ qt_status build_program(const qt_plan& plan, int elt, int64_t cap_elems, Program
     pg.bytes_c64 += st.bytes_c64;
     pg.flops += st.flops;
   }
+  pg.lsteps.assign(pg.n_levels, {});
   for (int L = 0; L < pg.n_levels; ++L) {
     pg.levels.push_back((int32_t)pg.units.size());
     for (int i = 0; i < nsteps; ++i)
-      if (depth[i] == L) push_step_units(plan, i, i, elt, pg.units);
+      if (depth[i] == L) {
+        push_step_units(plan, i, i, elt, pg.units);
+        pg.lsteps[L].push_back(i);
+      }
   }
   pg.levels.push_back((int32_t)pg.units.size());
   for (int t : plan.finals) {
@@ -549,7 +577,9 @@ struct EnergyJob {
   double* weights = nullptr; // [n_progs]: per-edge weights of the sums (weighted calls)
   char* scratch = nullptr;   // areas of the programs run from global scratch
   XMulti multi{};
-  int n_items = 0;           // programs of the batched launch (times np items)
+  int n_items = 0;           // programs of the batched launch
+  int n_blocks = 0;          // forward launch: workgroups (program, group of points)
+  size_t smem = 0;           // forward launch: LDS bytes per workgroup
   int n_fit = 0, n_global = 0;
   std::vector<int> big;      // forward programs beyond kMaxGlobalElems
   double bytes_c64 = 0, flops = 0;
@@ -618,10 +648,18 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     return grad ? lds_grad_smem_bytes(pg.n_slots, pg.n_recs, pg.lds_elems, elt == 16)
                 : lds_exec_smem_bytes(pg.n_slots, pg.lds_elems, elt == 16);
   };
+  // Forward programs in LDS: per point, the scale slots (max and exponent)
+  // and the tensor area, whose stride is odd so that the points' copies of
+  // an element fall in different LDS banks.
+  auto slot_stride = [](const Program& pg) { return (pg.n_slots + 3) & ~3; };
+  auto pt_stride = [](const Program& pg) { return pg.lds_elems | 1; };
+  auto pt_bytes = [&](const Program& pg) { return 8ll * slot_stride(pg) + (int64_t)pt_stride(pg) * elt; };
+  int p_max = 1;  // points per workgroup: a power of two, at most 64 and the points' count rounded up
+  while (p_max < 64 && p_max < np) p_max *= 2;
   for (int e = 0; e < n; ++e) {
     if (grad) QT_TRY(build_grad_program(*plans[e], elt, cap_elems, e, progs[e]));
     else QT_TRY(build_program(*plans[e], elt, cap_elems, progs[e]));
-    if (progs[e].fits && (int64_t)smem_of(progs[e]) > lds_cap) global[e] = 1;
+    if (progs[e].fits && (grad ? (int64_t)smem_of(progs[e]) : pt_bytes(progs[e])) > lds_cap) global[e] = 1;
     if (!progs[e].fits) {  // every intermediate kept, in global scratch
       progs[e] = Program{};
       if (grad) QT_TRY(build_grad_program(*plans[e], elt, int64_t(1) << 40, e, progs[e]));
@@ -639,7 +677,8 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   std::vector<XFinal> finals;
   int max_lds = 0;
   max_slots = max_recs = 0;
-  int64_t scratch_bytes = 0;
+  int64_t scratch_bytes = 0, smem_multi = 16;
+  std::vector<int> n_pts(n, 1);
   for (int e = 0; e < n; ++e) {
     const Program& pg = progs[e];
     XProg& x = xp[e];
@@ -657,10 +696,27 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     x.log2_const = pg.log2_const;
     x.area_elems = pg.lds_elems;
     x.scratch_off = -1;
+    x.n_pts = 1;
     steps.insert(steps.end(), pg.steps.begin(), pg.steps.end());
     revs.insert(revs.end(), pg.revs.begin(), pg.revs.end());
-    units.insert(units.end(), pg.units.begin(), pg.units.end());
-    levels.insert(levels.end(), pg.levels.begin(), pg.levels.end());
+    if (!grad && pg.fits && !global[e]) {
+      // as many points as the LDS cap holds
+      const int64_t b = pt_bytes(pg);
+      int P = p_max;
+      while (P > 1 && P * b > lds_cap) P /= 2;
+      n_pts[e] = x.n_pts = P;
+      x.pt_stride = pt_stride(pg);
+      x.slot_stride = slot_stride(pg);
+      smem_multi = std::max<int64_t>(smem_multi, P * b);
+      std::vector<uint2> pu;
+      std::vector<int32_t> pl;
+      pts_units(pg, P, elt, pu, pl);
+      units.insert(units.end(), pu.begin(), pu.end());
+      levels.insert(levels.end(), pl.begin(), pl.end());
+    } else {
+      units.insert(units.end(), pg.units.begin(), pg.units.end());
+      levels.insert(levels.end(), pg.levels.begin(), pg.levels.end());
+    }
     finals.insert(finals.end(), pg.finals.begin(), pg.finals.end());
     rec_off.insert(rec_off.end(), pg.rec_off.begin(), pg.rec_off.end());
     if (global[e]) {
@@ -687,6 +743,12 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     return progs[a].cost > progs[b].cost;
   });
   job.n_items = (int)order.size();
+  // forward launch: one workgroup per (program, group of its points)
+  std::vector<int2> items;
+  for (int e : order)
+    for (int pt = 0; pt < np; pt += n_pts[e]) items.push_back(make_int2(e, pt));
+  job.n_blocks = (int)items.size();
+  job.smem = (size_t)smem_multi;
   auto pad = [](size_t b) { return (b + 255) & ~(size_t)255; };
   struct Part {
     const void* src;
@@ -699,7 +761,8 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
                         {finals.data(), finals.size() * sizeof(XFinal)},
                         {order.data(), order.size() * sizeof(int32_t)},
                         {revs.data(), revs.size() * sizeof(XRev)},
-                        {rec_off.data(), rec_off.size() * sizeof(int32_t)}};
+                        {rec_off.data(), rec_off.size() * sizeof(int32_t)},
+                        {items.data(), items.size() * sizeof(int2)}};
   constexpr int kParts = sizeof(parts) / sizeof(parts[0]);
   size_t at[kParts], total = 0;
   for (int i = 0; i < kParts; ++i) {
@@ -731,6 +794,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   m.item_prog = (const int32_t*)(base + at[5]);
   m.revs = (const XRev*)(base + at[6]);
   m.rec_off = (const int32_t*)(base + at[7]);
+  m.items = (const int2*)(base + at[8]);
   m.params = job.params;
   m.out = job.out;
   m.gout = job.gout;
@@ -754,9 +818,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     std::fprintf(stderr,
                  "[qt grad] job: %d of %d programs in LDS, %zu bytes of LDS per workgroup, %d from global scratch, "
                  "%lld scratch bytes, %d by steps\n",
-                 job.n_fit, n,
-                 grad ? lds_grad_smem_bytes(max_slots, max_recs, max_lds, elt == 16)
-                      : lds_exec_smem_bytes(max_slots, max_lds, elt == 16),
+                 job.n_fit, n, grad ? lds_grad_smem_bytes(max_slots, max_recs, max_lds, elt == 16) : job.smem,
                  job.n_global, (long long)scratch_bytes, (int)job.big.size());
   return QT_OK;
 }
@@ -806,12 +868,13 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     const qt_tuning& tu = lightcones[0]->tuning;
     const int64_t lds_bytes = std::min<int64_t>(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
     const int64_t budget = grad ? std::min<int64_t>(lds_bytes, env_int("QT_GRAD_LDS_BYTES", (int)lds_bytes)) : lds_bytes;
-    // Default LDS per workgroup: small enough that many workgroups share a
-    // compute unit (the lightcones are short and latency-bound), the larger
-    // lightcones running from global scratch, where their few hundred KiB
-    // stay in the L2 (measured on the 1000-node p = 3 energy and the
-    // 200-node p = 2 gradient; the autotuner searches this tunable).
-    const int dflt_cap = grad ? 8192 : (lightcones[0]->precision == QT_C128 ? 24576 : 12288);
+    // Default LDS per workgroup (the autotuner searches this tunable): the
+    // forward launch holds a few points of a lightcone per workgroup with
+    // several workgroups per compute unit; the gradient launch, one point
+    // per workgroup, runs its larger lightcones from global scratch, where
+    // their few hundred KiB stay in the L2 (measured on the 1000-node p = 3
+    // energy and the 200-node p = 2 gradient).
+    const int dflt_cap = grad ? 8192 : (lightcones[0]->precision == QT_C128 ? 65536 : 32768);
     const int64_t lds_cap = std::min<int64_t>(budget, tuned(tu.multi_lds_cap, "QT_MULTI_LDS_CAP", dflt_cap));
     hipStream_t stream = (hipStream_t)hip_stream;
     std::shared_ptr<EnergyJob> job;
@@ -837,7 +900,7 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
       }
     }
     const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 2)
-                                                                    : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 2)));
+                                                                    : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 4)));
     std::lock_guard<std::mutex> run_lk(job->run_mu);
     // The device sequence: parameters in, the batched launch, the FP64 sums
     // over edges and the results out.
@@ -845,7 +908,7 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
       EnergyJob& J = *job;
       QT_TRY(upload_params_to(J.params, n_points, p, gammas, betas, s));
       if (grad) QT_HIP_CHECK(launch_lds_grad(J.multi, J.n_items, waves, s));
-      else QT_HIP_CHECK(launch_lds_multi(J.multi, J.n_items, waves, J.wide, !J.wide, s));
+      else QT_HIP_CHECK(launch_lds_multi(J.multi, J.n_blocks, J.smem, waves, J.wide, !J.wide, s));
       for (int e : J.big) {
         const double* sums = nullptr;
         QT_TRY(run_plan_points(*lightcones[e], n_points, gammas, betas, s, &sums));

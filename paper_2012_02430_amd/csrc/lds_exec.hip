@@ -22,11 +22,14 @@
 namespace qt {
 namespace {
 
+// Complex product with its fused multiply-adds written out, so that every
+// executor variant (per point or point-batched, LDS or global scratch)
+// rounds it the same way whatever the compiler would contract.
 __device__ __forceinline__ float2 xmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 xmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 xadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 xadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -556,44 +559,256 @@ __device__ __forceinline__ void x_multi_item(const XMulti& M, const XProg& P, in
   }
 }
 
-// Multi-program executor: one workgroup per (program, point) item runs a
-// whole network (a per-edge lightcone) -- every edge and point of an
-// energy evaluation in one launch.  Items whose program fits the launch's
-// LDS keep every tensor there; the few larger ones run the same schedule
-// from their own global scratch area.
+// Max of non-negative values (float bits) over each aligned group of 2^lg
+// lanes (lg <= 5): DPP steps inside rows of 16 lanes (swap of neighbours, of
+// pairs, mirror of each half row, mirror of the row), then one lane
+// exchange across the two rows of a 32-lane group.  Every lane of a group
+// ends with the group's max.
+__device__ __forceinline__ uint32_t xseg_max(uint32_t v, int lg) {
+  if (lg >= 1) v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  if (lg >= 2) v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  if (lg >= 3) v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  if (lg >= 4) v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  if (lg >= 5) v = max(v, (uint32_t)__shfl_xor((int)v, 16));
+  return v;
+}
+
+// A unit of a point-batched lightcone program.  The workgroup holds the
+// tensors of `npts` points of one program, point q's area at element q *
+// stride and its scale slots at q * S.  A step with fewer than 64 outputs
+// is packed: its unit covers 64 / 2^r points, lane = (point, output); a
+// larger step's unit covers 64 x EPU outputs of one point (uy = point x
+// chunks + chunk), as in the per-point executor.  Operands and the output
+// are in LDS; the output's scale slot belongs to the step alone, so a
+// packed unit stores its point's max and exponent directly.
+template <typename E, bool SCALED, int NIN, int EPU>
+__device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_t lane, uint32_t npts, uint32_t stride,
+                                           uint32_t S, E* __restrict__ lds, uint32_t* __restrict__ smax,
+                                           int* __restrict__ sexp) {
+  using R = typename XReal<E>::R;
+  const int r = st.r;
+  const uint32_t n = 1u << r;
+  const bool packed = r < 6;
+  uint32_t q, xl, chunk = 0;
+  if (packed) {
+    q = (uy << (6 - r)) + (lane >> r);
+    xl = lane & (n - 1u);
+  } else {
+    constexpr int lg_epu = EPU == 4 ? 2 : (EPU == 2 ? 1 : 0);
+    const int lgc = r - 6 - lg_epu;
+    chunk = uy & ((1u << lgc) - 1u);
+    q = uy >> lgc;
+    xl = lane;
+  }
+  const bool valid = q < npts;
+  const uint32_t qq = valid ? q : 0u;
+  const uint32_t qoff = qq * stride, soff = qq * S;
+  const uint32_t cx = chunk * EPU * 64u;
+  uint32_t base[NIN], lp[NIN];
+  int slot[NIN];
+  R sc[NIN];
+  int eacc = 0;
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    base[j] = st.in[j].lds_off + qoff;
+    slot[j] = st.in[j].slot;
+  }
+  uint32_t mbits[NIN];
+  int mexp[NIN];
+  if (SCALED) {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const uint32_t s = soff + (uint32_t)(slot[j] >= 0 ? slot[j] : 0);
+      mbits[j] = smax[s];
+      mexp[j] = sexp[s];
+    }
+  }
+  uint32_t lw[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) lw[j] = st.in[j].lane_runs;
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(xl, lw[j]);
+  if (chunk != 0) {
+    uint32_t rw[NIN][6];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const uint32_t* const w = reinterpret_cast<const uint32_t*>(st.in[j].run_lo);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rw[j][k] = w[k];
+    }
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(cx, rw[j]) << st.in[j].has_v;
+  }
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    sc[j] = (R)1;
+    if (SCALED && slot[j] >= 0) {
+      const int sh = xshift(mbits[j]);
+      sc[j] = (R)xpow2neg(sh);
+      eacc += mexp[j] + sh;
+    }
+  }
+  E a0[EPU][NIN], a1[EPU][NIN];
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const uint32_t hv = (uint32_t)st.in[j].has_v;
+      const uint32_t i = base[j] + lp[j] + st.in[j].ep[e];
+      a0[e][j] = lds[i];
+      a1[e][j] = lds[i + hv];
+    }
+  }
+  const XOut& o = st.out;
+  float m = 0.f;
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) {
+    E t0 = a0[e][0], t1 = a1[e][0];
+    if (SCALED) {
+      t0 = xscale(t0, sc[0]);
+      t1 = xscale(t1, sc[0]);
+    }
+#pragma unroll
+    for (int j = 1; j < NIN; ++j) {
+      E x0 = a0[e][j], x1 = a1[e][j];
+      if (SCALED) {
+        x0 = xscale(x0, sc[j]);
+        x1 = xscale(x1, sc[j]);
+      }
+      t0 = xmul(t0, x0);
+      t1 = xmul(t1, x1);
+    }
+    const E res = st.sum ? xadd(t0, t1) : t0;
+    const uint32_t x = cx + e * 64u + xl;
+    if (valid && x < n) {
+      lds[qoff + o.lds_off + x] = res;
+      if (SCALED) m = fmaxf(m, fmaxf(fabsf((float)res.x), fabsf((float)res.y)));
+    }
+  }
+  if (SCALED) {
+    if (packed) {
+      const uint32_t mw = xseg_max(__float_as_uint(m), r);
+      if (valid && xl == 0u) {
+        smax[soff + o.slot] = mw;
+        sexp[soff + o.slot] = eacc;
+      }
+    } else {
+      const uint32_t mw = xwave_max(__float_as_uint(m));
+      if (lane == 0u && valid) {
+        atomicMax(smax + soff + o.slot, mw);
+        if (chunk == 0) sexp[soff + o.slot] = eacc;
+      }
+    }
+  }
+}
+
+// One point-batched item of the multi-program executor: up to P.n_pts
+// points (from pt0) of one program in the workgroup's LDS.
+template <typename E, bool SCALED>
+__device__ __forceinline__ void x_multi_pts(const XMulti& M, const XProg& P, int prog_id, uint32_t pt0,
+                                            const XStep* __restrict__ psteps, const uint2* __restrict__ punits,
+                                            const int32_t* __restrict__ plev, const XFinal* __restrict__ finals,
+                                            int tid, int wave, int nw, unsigned char* smem) {
+  const uint32_t np = (uint32_t)P.n_pts;
+  const uint32_t npts = min(np, (uint32_t)M.n_points - pt0);
+  const uint32_t S = (uint32_t)P.slot_stride, stride = (uint32_t)P.pt_stride;
+  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
+  int* sexp = reinterpret_cast<int*>(smem + 4 * np * S);
+  E* lds = reinterpret_cast<E*>(smem + 8 * np * S);
+  for (uint32_t i = tid; i < np * S; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  const uint32_t ge = (uint32_t)x_gate_elems(M.p);
+  for (uint32_t i = tid; i < np * (ge + kXGate); i += blockDim.x) {
+    const uint32_t q = i / (ge + kXGate), t = i - q * (ge + kXGate);
+    E v;
+    if (t < (uint32_t)kXGate) {
+      v.x = 1;
+      v.y = 0;
+    } else {
+      const uint32_t pq = pt0 + min(q, npts - 1u);
+      v = x_gate<E>((int)(t - kXGate), M.params + (int64_t)pq * 2 * M.p, M.p);
+    }
+    lds[q * stride + t] = v;
+  }
+  __syncthreads();
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  const uint32_t lane = tid & 63;
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw) {
+      const uint2 un = punits[u];
+      const XStep& st = psteps[un.x];
+      const bool big = st.r >= kXBigRank;
+      if (st.n_in <= 2) {
+        if (big) x_unit_pts<E, SCALED, 2, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        else x_unit_pts<E, SCALED, 2, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+      } else if (st.n_in <= 4) {
+        if (big) x_unit_pts<E, SCALED, 4, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        else x_unit_pts<E, SCALED, 4, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+      } else {
+        if (big) x_unit_pts<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        else x_unit_pts<E, SCALED, 8, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t q = tid; q < npts; q += blockDim.x) {
+    double re = 1.0, im = 0.0, ex = P.log2_const;
+    for (int f = 0; f < P.n_finals; ++f) {
+      const XFinal& F = finals[P.finals_off + f];
+      const E a = lds[q * stride + F.lds_off];
+      const double ar = (double)a.x, ai = (double)a.y;
+      if (SCALED && F.slot >= 0) ex += sexp[q * S + F.slot];
+      const double nr = re * ar - im * ai;
+      im = re * ai + im * ar;
+      re = nr;
+    }
+    double* o = M.out + 3 * ((int64_t)(pt0 + q) * M.n_progs + prog_id);
+    o[0] = re;
+    o[1] = im;
+    o[2] = ex;
+  }
+}
+
+// Multi-program executor: one workgroup per item runs a whole network (a
+// per-edge lightcone) -- every edge and point of an energy evaluation in one
+// launch.  An item is a group of points of one program whose tensors, for
+// all of them, fit the launch's LDS: the points share the descriptor loads
+// and the barriers of the level chain, and the small steps fill the lanes
+// with several points.  A program too large for that runs one point per
+// item from its own global scratch area.
 template <typename E, bool SCALED>
 __global__ __launch_bounds__(kXMaxThreads) void k_lds_multi(const XMulti M, const XProg* __restrict__ progs,
                                                             const XStep* __restrict__ steps,
                                                             const uint2* __restrict__ units,
                                                             const int32_t* __restrict__ level_off,
                                                             const XFinal* __restrict__ finals,
-                                                            const int32_t* __restrict__ item_prog) {
+                                                            const int2* __restrict__ items) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t item = blockIdx.x;
-  const int prog_id = item_prog[item / (uint32_t)M.n_points];
+  const int2 it = items[blockIdx.x];
+  const int prog_id = it.x;
   const XProg& P = progs[prog_id];
-  XCtx c;
-  c.pt = item % (uint32_t)M.n_points;
-  c.sb = 0;
-  c.sid = 0;
   const int tid = threadIdx.x;
-  c.lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nw = blockDim.x >> 6;
   const XStep* psteps = steps + P.steps_off;
   const uint2* punits = units + P.units_off;
   const int32_t* plev = level_off + P.levels_off;
   if (P.scratch_off >= 0) {
+    XCtx c;
+    c.pt = (uint32_t)it.y;
+    c.sb = 0;
+    c.sid = 0;
+    c.lane = tid & 63;
     const XArea a = x_area(P.n_slots, 0, P.area_elems, (int)sizeof(E));
     char* base = M.scratch + P.scratch_off + (int64_t)c.pt * P.scratch_stride;
     x_multi_item<E, SCALED, true>(M, P, prog_id, psteps, punits, plev, finals, c, tid, wave, nw,
                                   reinterpret_cast<E*>(base), reinterpret_cast<uint32_t*>(base + a.elem_bytes),
                                   reinterpret_cast<int*>(base + a.elem_bytes + a.slot_bytes));
   } else {
-    const int slots16 = (M.n_slots + 3) & ~3;
-    x_multi_item<E, SCALED, false>(M, P, prog_id, psteps, punits, plev, finals, c, tid, wave, nw,
-                                   reinterpret_cast<E*>(smem + 8 * slots16), reinterpret_cast<uint32_t*>(smem),
-                                   reinterpret_cast<int*>(smem + 4 * slots16));
+    x_multi_pts<E, SCALED>(M, P, prog_id, (uint32_t)it.y, psteps, punits, plev, finals, tid, wave, nw, smem);
   }
 }
 
@@ -608,10 +823,9 @@ __global__ void k_amp_to_real(const double* __restrict__ amp, int64_t n, double*
 
 }  // namespace
 
-hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled, hipStream_t stream) {
-  const int64_t n_items = (int64_t)n_item_progs * m.n_points;
+hipError_t launch_lds_multi(const XMulti& m, int n_items, size_t smem, int waves, bool c128, bool scaled,
+                            hipStream_t stream) {
   if (n_items == 0) return hipSuccess;
-  const size_t smem = lds_exec_smem_bytes(m.n_slots, m.lds_elems, c128);
   const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
   const void* fn = c128 ? reinterpret_cast<const void*>(&k_lds_multi<double2, false>)
                         : (scaled ? reinterpret_cast<const void*>(&k_lds_multi<float2, true>)
@@ -620,13 +834,13 @@ hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c
   if (e != hipSuccess) return e;
   if (c128)
     hipLaunchKernelGGL((k_lds_multi<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
-                       m.level_off, m.finals, m.item_prog);
+                       m.level_off, m.finals, m.items);
   else if (scaled)
     hipLaunchKernelGGL((k_lds_multi<float2, true>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
-                       m.level_off, m.finals, m.item_prog);
+                       m.level_off, m.finals, m.items);
   else
     hipLaunchKernelGGL((k_lds_multi<float2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.units,
-                       m.level_off, m.finals, m.item_prog);
+                       m.level_off, m.finals, m.items);
   return hipGetLastError();
 }
 

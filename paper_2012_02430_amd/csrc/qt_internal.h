@@ -265,7 +265,11 @@ struct XProg {
   int64_t scratch_off;
   int64_t scratch_stride;
   int32_t area_elems;
-  int32_t pad;
+  // Forward programs in LDS run n_pts points per workgroup: point q's
+  // tensors at element q * pt_stride, its scale slots at q * slot_stride.
+  int32_t n_pts;
+  int32_t pt_stride;
+  int32_t slot_stride;
 };
 
 // Reverse (adjoint) operation of the gradient executor.  For one input T_j
@@ -321,6 +325,7 @@ struct XMulti {
   int32_t n_slots;         // max over the programs run from LDS
   int32_t n_recs;          // max over the programs run from LDS
   char* scratch;           // areas of the programs run from global scratch
+  const int2* items;       // multi-program executor: (program, first point) per workgroup
 };
 
 // Fused GEMM bucket: C[b, m, n] = sum_k A[b, m, k] B[b, n, k] over complex
@@ -513,7 +518,7 @@ hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, i
                         double* per_slice, int64_t slice_end, hipStream_t stream);
 hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c128, bool scaled, int* exps,
                            uint32_t* maxbits, hipStream_t stream);
-hipError_t launch_lds_multi(const XMulti& m, int n_item_progs, int waves, bool c128, bool scaled,
+hipError_t launch_lds_multi(const XMulti& m, int n_items, size_t smem, int waves, bool c128, bool scaled,
                             hipStream_t stream);
 // The gradient executor runs in complex128 (unscaled) for every precision.
 hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream);

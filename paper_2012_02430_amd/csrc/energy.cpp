@@ -126,6 +126,35 @@ void pts_units(const Program& pg, int P, int elt, std::vector<uint2>& units, std
   levels.push_back((int32_t)units.size());
 }
 
+// The gradient schedule's units for P points per workgroup: each forward
+// or recomputation step's units as in pts_units, emitted where its first
+// per-point unit stood; reverse operations and the closing-scalar unit as
+// they are (a reverse unit runs every point of the workgroup in turn).
+void grad_pts_units(const Program& pg, int P, int elt, std::vector<uint2>& units, std::vector<int32_t>& levels) {
+  for (int L = 0; L < pg.n_levels; ++L) {
+    levels.push_back((int32_t)units.size());
+    for (int u = pg.levels[L]; u < pg.levels[L + 1]; ++u) {
+      const uint2 un = pg.units[u];
+      const uint32_t kind = un.x & ~kXUnitIndex, idx = un.x & kXUnitIndex;
+      if (kind == 0) {
+        if (un.y != 0) continue;  // emitted with the step's first unit
+        const int r = pg.steps[idx].r;
+        if (r < 6) {
+          const int per = 64 >> r;
+          for (int b = 0; b < (P + per - 1) / per; ++b) units.push_back(make_uint2(un.x, (uint32_t)b));
+        } else {
+          const int64_t chunks = std::max<int64_t>(1, (1ll << r) / x_unit_elems(r, pg.steps[idx].n_in, elt));
+          for (int q = 0; q < P; ++q)
+            for (int64_t c = 0; c < chunks; ++c) units.push_back(make_uint2(un.x, (uint32_t)(q * chunks + c)));
+        }
+      } else {  // reverse operations run every point in their unit; the closing-scalar unit takes a lane per point
+        units.push_back(un);
+      }
+    }
+  }
+  levels.push_back((int32_t)units.size());
+}
+
 int count_intermediates(const qt_plan& plan) {
   int n = 0;
   for (const SymTensor& T : plan.tensors) n += T.leaf < 0;
@@ -641,7 +670,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     if (grad) max_recs = std::max(max_recs, count_records(*plans[e]));
   }
   const int64_t fixed = 8 * (int64_t)((max_slots + 3) & ~3) + 8 * (int64_t)((max_recs + 1) & ~1);
-  const int64_t cap_elems = (lds_bytes - fixed) / elt - x_tensor_base(p);
+  const int64_t cap_elems = (lds_bytes - fixed) / elt - 1 - x_tensor_base(p);  // - 1: the odd point stride
   std::vector<Program> progs(n);
   std::vector<char> global(n, 0);
   auto smem_of = [&](const Program& pg) {
@@ -652,14 +681,17 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   // and the tensor area, whose stride is odd so that the points' copies of
   // an element fall in different LDS banks.
   auto slot_stride = [](const Program& pg) { return (pg.n_slots + 3) & ~3; };
+  auto rec_stride = [](const Program& pg) { return (pg.n_recs + 1) & ~1; };
   auto pt_stride = [](const Program& pg) { return pg.lds_elems | 1; };
-  auto pt_bytes = [&](const Program& pg) { return 8ll * slot_stride(pg) + (int64_t)pt_stride(pg) * elt; };
+  auto pt_bytes = [&](const Program& pg) {
+    return 8ll * slot_stride(pg) + 8ll * rec_stride(pg) + (int64_t)pt_stride(pg) * elt;
+  };
   int p_max = 1;  // points per workgroup: a power of two, at most 64 and the points' count rounded up
   while (p_max < 64 && p_max < np) p_max *= 2;
   for (int e = 0; e < n; ++e) {
     if (grad) QT_TRY(build_grad_program(*plans[e], elt, cap_elems, e, progs[e]));
     else QT_TRY(build_program(*plans[e], elt, cap_elems, progs[e]));
-    if (progs[e].fits && (grad ? (int64_t)smem_of(progs[e]) : pt_bytes(progs[e])) > lds_cap) global[e] = 1;
+    if (progs[e].fits && pt_bytes(progs[e]) > lds_cap) global[e] = 1;
     if (!progs[e].fits) {  // every intermediate kept, in global scratch
       progs[e] = Program{};
       if (grad) QT_TRY(build_grad_program(*plans[e], elt, int64_t(1) << 40, e, progs[e]));
@@ -677,7 +709,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   std::vector<XFinal> finals;
   int max_lds = 0;
   max_slots = max_recs = 0;
-  int64_t scratch_bytes = 0, smem_multi = 16;
+  int64_t scratch_bytes = 0, smem_multi = 16, max_pt_bytes = 0;
   std::vector<int> n_pts(n, 1);
   for (int e = 0; e < n; ++e) {
     const Program& pg = progs[e];
@@ -699,7 +731,7 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
     x.n_pts = 1;
     steps.insert(steps.end(), pg.steps.begin(), pg.steps.end());
     revs.insert(revs.end(), pg.revs.begin(), pg.revs.end());
-    if (!grad && pg.fits && !global[e]) {
+    if (pg.fits && !global[e]) {
       // as many points as the LDS cap holds
       const int64_t b = pt_bytes(pg);
       int P = p_max;
@@ -707,10 +739,13 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
       n_pts[e] = x.n_pts = P;
       x.pt_stride = pt_stride(pg);
       x.slot_stride = slot_stride(pg);
+      x.rec_stride = rec_stride(pg);
       smem_multi = std::max<int64_t>(smem_multi, P * b);
+      max_pt_bytes = std::max(max_pt_bytes, b);
       std::vector<uint2> pu;
       std::vector<int32_t> pl;
-      pts_units(pg, P, elt, pu, pl);
+      if (grad) grad_pts_units(pg, P, elt, pu, pl);
+      else pts_units(pg, P, elt, pu, pl);
       units.insert(units.end(), pu.begin(), pu.end());
       levels.insert(levels.end(), pl.begin(), pl.end());
     } else {
@@ -817,9 +852,9 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   if (env_int("QT_DEBUG_GRAD_SCHEDULE", 0))
     std::fprintf(stderr,
                  "[qt grad] job: %d of %d programs in LDS, %zu bytes of LDS per workgroup, %d from global scratch, "
-                 "%lld scratch bytes, %d by steps\n",
-                 job.n_fit, n, grad ? lds_grad_smem_bytes(max_slots, max_recs, max_lds, elt == 16) : job.smem,
-                 job.n_global, (long long)scratch_bytes, (int)job.big.size());
+                 "%lld scratch bytes, %d by steps, %lld bytes per point\n",
+                 job.n_fit, n, job.smem, job.n_global, (long long)scratch_bytes, (int)job.big.size(),
+                 (long long)max_pt_bytes);
   return QT_OK;
 }
 
@@ -868,13 +903,12 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     const qt_tuning& tu = lightcones[0]->tuning;
     const int64_t lds_bytes = std::min<int64_t>(160 * 1024, env_int("QT_LDS_BYTES", 160 * 1024));
     const int64_t budget = grad ? std::min<int64_t>(lds_bytes, env_int("QT_GRAD_LDS_BYTES", (int)lds_bytes)) : lds_bytes;
-    // Default LDS per workgroup (the autotuner searches this tunable): the
-    // forward launch holds a few points of a lightcone per workgroup with
-    // several workgroups per compute unit; the gradient launch, one point
-    // per workgroup, runs its larger lightcones from global scratch, where
-    // their few hundred KiB stay in the L2 (measured on the 1000-node p = 3
-    // energy and the 200-node p = 2 gradient).
-    const int dflt_cap = grad ? 8192 : (lightcones[0]->precision == QT_C128 ? 65536 : 32768);
+    // Default LDS per workgroup (the autotuner searches this tunable): a few
+    // points of a lightcone per workgroup with several workgroups per
+    // compute unit (measured on the 1000-node p = 3 energy and the 200-node
+    // p = 2 gradient, whose complex128 tensors and records take about twice
+    // the bytes per point).
+    const int dflt_cap = (grad || lightcones[0]->precision == QT_C128) ? 65536 : 32768;
     const int64_t lds_cap = std::min<int64_t>(budget, tuned(tu.multi_lds_cap, "QT_MULTI_LDS_CAP", dflt_cap));
     hipStream_t stream = (hipStream_t)hip_stream;
     std::shared_ptr<EnergyJob> job;
@@ -899,7 +933,7 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
         job = nj;
       }
     }
-    const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 2)
+    const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 8)
                                                                     : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 4)));
     std::lock_guard<std::mutex> run_lk(job->run_mu);
     // The device sequence: parameters in, the batched launch, the FP64 sums
@@ -907,7 +941,7 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     auto enqueue = [&](hipStream_t s) -> qt_status {
       EnergyJob& J = *job;
       QT_TRY(upload_params_to(J.params, n_points, p, gammas, betas, s));
-      if (grad) QT_HIP_CHECK(launch_lds_grad(J.multi, J.n_items, waves, s));
+      if (grad) QT_HIP_CHECK(launch_lds_grad(J.multi, J.n_blocks, J.smem, waves, s));
       else QT_HIP_CHECK(launch_lds_multi(J.multi, J.n_blocks, J.smem, waves, J.wide, !J.wide, s));
       for (int e : J.big) {
         const double* sums = nullptr;

@@ -908,9 +908,15 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
       eacc += sexp[op.slot] + sh;
     }
   }
-  E acc;
-  acc.x = 0;
-  acc.y = 0;
+  // Four iterations in flight (their operand reads issue together), each
+  // into its own partial sum; the partial sums are added in a fixed order.
+  constexpr int kU = 4;
+  E part[kU];
+#pragma unroll
+  for (int k = 0; k < kU; ++k) {
+    part[k].x = 0;
+    part[k].y = 0;
+  }
   const bool live = g < C;  // lane groups beyond a short complement add nothing
   const uint32_t n_it = C > G ? C / G : 1u;
   for (uint32_t ib = 0; ib < n_it; ib += 64) {
@@ -919,7 +925,31 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
 #pragma unroll
     for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(ci, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
     const uint32_t nb = n_it - ib < 64u ? n_it - ib : 64u;
-    for (uint32_t t = 0; t < nb; ++t) {
+    uint32_t t = 0;
+    for (; t + kU <= nb; t += kU) {
+      E v[kU];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) {
+        v[k] = lds[base[0] + (uint32_t)__builtin_amdgcn_readlane((int)cm[0], (int)(t + k))];
+        if (SCALED) v[k] = xscale(v[k], sc[0]);
+      }
+#pragma unroll
+      for (int o = 1; o < NOPS; ++o) {
+        E x[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) x[k] = lds[base[o] + (uint32_t)__builtin_amdgcn_readlane((int)cm[o], (int)(t + k))];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+          if (SCALED) x[k] = xscale(x[k], sc[o]);
+          v[k] = xmul(v[k], x[k]);
+        }
+      }
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < kU; ++k) part[k] = xadd(part[k], v[k]);
+      }
+    }
+    for (; t < nb; ++t) {
       E v = lds[base[0] + (uint32_t)__builtin_amdgcn_readlane((int)cm[0], (int)t)];
       if (SCALED) v = xscale(v, sc[0]);
 #pragma unroll
@@ -928,9 +958,10 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
         if (SCALED) x = xscale(x, sc[o]);
         v = xmul(v, x);
       }
-      if (live) acc = xadd(acc, v);
+      if (live) part[0] = xadd(part[0], v);
     }
   }
+  E acc = xadd(xadd(part[0], part[1]), xadd(part[2], part[3]));
   if (!wide) {
     for (uint32_t off = 1u << ry; off < 64u; off <<= 1) {
       acc.x += __shfl_xor(acc.x, (int)off);
@@ -954,6 +985,97 @@ __device__ __forceinline__ void x_runit(const XRev& rv, uint32_t chunk, uint32_t
     if (lane == 0) {
       atomicMax(smax + rv.out_slot, mw);
       if (chunk == 0) sexp[rv.out_slot] = eacc;
+    }
+  }
+}
+
+// x_runit for every point of a point-batched item (unscaled elements):
+// the unit's maps are decoded once, then each point's reduction runs in
+// turn on its own tensors (element offset q * stride) and records (q * R).
+template <typename E, int NOPS>
+__device__ __forceinline__ void x_runit_pts(const XRev& rv, uint32_t chunk, uint32_t lane, uint32_t npts,
+                                            uint32_t stride, uint32_t R, E* __restrict__ lds,
+                                            double* __restrict__ gacc) {
+  const int ry = rv.ry;
+  const bool wide = ry >= 6;
+  const uint32_t y = wide ? chunk * 64u + lane : (lane & ((1u << ry) - 1u));
+  const uint32_t g = wide ? 0u : (lane >> ry);
+  const uint32_t G = wide ? 1u : (64u >> ry);
+  const uint32_t C = 1u << rv.nc;
+  uint32_t base[NOPS];
+#pragma unroll
+  for (int o = 0; o < NOPS; ++o) {
+    const XROp& op = rv.op[o];
+    base[o] = op.lds_off + xpext_all(y, op.y_lo, op.y_len, op.y_dst) + xpext_all(g, op.c_lo, op.c_len, op.c_dst);
+  }
+  const bool live = g < C;
+  const uint32_t n_it = C > G ? C / G : 1u;
+  const bool one_block = n_it <= 64u;
+  uint32_t cm[NOPS];
+  if (one_block) {
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(lane * G, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
+  }
+  constexpr int kU = 4;
+  for (uint32_t q = 0; q < npts; ++q) {
+    const uint32_t qo = q * stride;
+    E part[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      part[k].x = 0;
+      part[k].y = 0;
+    }
+    for (uint32_t ib = 0; ib < n_it; ib += 64) {
+      if (!one_block) {
+        const uint32_t ci = (ib + lane) * G;
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(ci, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
+      }
+      const uint32_t nb = n_it - ib < 64u ? n_it - ib : 64u;
+      uint32_t t = 0;
+      for (; t + kU <= nb; t += kU) {
+        E v[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k)
+          v[k] = lds[qo + base[0] + (uint32_t)__builtin_amdgcn_readlane((int)cm[0], (int)(t + k))];
+#pragma unroll
+        for (int o = 1; o < NOPS; ++o) {
+          E x[kU];
+#pragma unroll
+          for (int k = 0; k < kU; ++k)
+            x[k] = lds[qo + base[o] + (uint32_t)__builtin_amdgcn_readlane((int)cm[o], (int)(t + k))];
+#pragma unroll
+          for (int k = 0; k < kU; ++k) v[k] = xmul(v[k], x[k]);
+        }
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < kU; ++k) part[k] = xadd(part[k], v[k]);
+        }
+      }
+      for (; t < nb; ++t) {
+        E v = lds[qo + base[0] + (uint32_t)__builtin_amdgcn_readlane((int)cm[0], (int)t)];
+#pragma unroll
+        for (int o = 1; o < NOPS; ++o) v = xmul(v, lds[qo + base[o] + (uint32_t)__builtin_amdgcn_readlane((int)cm[o], (int)t)]);
+        if (live) part[0] = xadd(part[0], v);
+      }
+    }
+    E acc = xadd(xadd(part[0], part[1]), xadd(part[2], part[3]));
+    if (!wide) {
+      for (uint32_t off = 1u << ry; off < 64u; off <<= 1) {
+        acc.x += __shfl_xor(acc.x, (int)off);
+        acc.y += __shfl_xor(acc.y, (int)off);
+      }
+    }
+    if (rv.gate >= 0) {
+      double v = 0.0;
+      if (g == 0) {
+        const double2 d = x_dgate(rv.gate, y, lds + qo + rv.out_off);
+        v = (double)acc.x * d.x - (double)acc.y * d.y;
+      }
+      for (uint32_t off = 1; off < (1u << ry); off <<= 1) v += __shfl_xor(v, (int)off);
+      if (lane == 0) gacc[q * R + rv.rec] = v;
+    } else if (g == 0) {
+      lds[qo + rv.out_off + y] = acc;
     }
   }
 }
@@ -1107,25 +1229,114 @@ __device__ __forceinline__ void x_grad_item(const XMulti& M, const XProg& P, int
   x_grad_epilogue<E, SCALED>(M, P, prog_id, pfin, rec_off, c.pt, tid, area, sexp, gacc);
 }
 
+// One point-batched item of the gradient executor: up to P.n_pts points
+// (from pt0) of one program in the workgroup's LDS, point q's tensors at
+// element q * pt_stride, its scale slots at q * slot_stride and its
+// gradient records at q * rec_stride.  Forward and recomputation steps run
+// as point-batched units; a reverse operation's unit names its point; the
+// adjoints of the closing scalars take one lane per point.
 template <typename E, bool SCALED>
-__global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_lds_grad(const XMulti M, const XProg* __restrict__ progs,
-                                                           const XStep* __restrict__ steps,
-                                                           const XRev* __restrict__ revs,
-                                                           const uint2* __restrict__ units,
-                                                           const int32_t* __restrict__ level_off,
-                                                           const XFinal* __restrict__ finals,
-                                                           const int32_t* __restrict__ item_prog,
-                                                           const int32_t* __restrict__ rec_off) {
+__device__ __forceinline__ void x_grad_pts(const XMulti& M, const XProg& P, int prog_id, uint32_t pt0,
+                                           const XStep* __restrict__ psteps, const XRev* __restrict__ prevs,
+                                           const uint2* __restrict__ punits, const int32_t* __restrict__ plev,
+                                           const XFinal* __restrict__ pfin, const int32_t* __restrict__ rec_off,
+                                           int tid, int wave, int nw, unsigned char* smem) {
+  const uint32_t np = (uint32_t)P.n_pts;
+  const uint32_t npts = min(np, (uint32_t)M.n_points - pt0);
+  const uint32_t S = (uint32_t)P.slot_stride, R = (uint32_t)P.rec_stride, stride = (uint32_t)P.pt_stride;
+  uint32_t* smax = reinterpret_cast<uint32_t*>(smem);
+  int* sexp = reinterpret_cast<int*>(smem + 4 * np * S);
+  double* gacc = reinterpret_cast<double*>(smem + 8 * np * S);
+  E* lds = reinterpret_cast<E*>(smem + 8 * np * S + 8 * np * R);
+  for (uint32_t i = tid; i < np * S; i += blockDim.x) {
+    smax[i] = 0u;
+    sexp[i] = 0;
+  }
+  const uint32_t ge = (uint32_t)x_gate_elems(M.p);
+  for (uint32_t i = tid; i < np * (ge + kXGate); i += blockDim.x) {
+    const uint32_t q = i / (ge + kXGate), t = i - q * (ge + kXGate);
+    E v;
+    if (t < (uint32_t)kXGate) {
+      v.x = 1;
+      v.y = 0;
+    } else {
+      const uint32_t pq = pt0 + min(q, npts - 1u);
+      v = x_gate<E>((int)(t - kXGate), M.params + (int64_t)pq * 2 * M.p, M.p);
+    }
+    lds[q * stride + t] = v;
+  }
+  __syncthreads();
+  constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
+  const uint32_t lane = tid & 63;
+  for (int L = 0; L < P.n_levels; ++L) {
+    const int u_end = plev[L + 1];
+    for (int u = plev[L] + wave; u < u_end; u += nw) {
+      const uint2 un = punits[u];
+      const uint32_t kind = un.x & ~kXUnitIndex, idx = un.x & kXUnitIndex;
+      if (kind == 0) {
+        const XStep& st = psteps[idx];
+        const bool big = st.r >= kXBigRank;
+        if (st.n_in <= 2) {
+          if (big) x_unit_pts<E, SCALED, 2, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+          else x_unit_pts<E, SCALED, 2, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        } else if (st.n_in <= 4) {
+          if (big) x_unit_pts<E, SCALED, 4, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+          else x_unit_pts<E, SCALED, 4, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        } else {
+          if (big) x_unit_pts<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+          else x_unit_pts<E, SCALED, 8, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
+        }
+      } else if (kind == kXUnitRev) {
+        static_assert(!SCALED, "the gradient pass runs on unscaled elements");
+        const XRev& rv = prevs[idx];
+        if (rv.n_ops <= 2) x_runit_pts<E, 2>(rv, un.y, lane, npts, stride, R, lds, gacc);
+        else if (rv.n_ops <= 4) x_runit_pts<E, 4>(rv, un.y, lane, npts, stride, R, lds, gacc);
+        else x_runit_pts<E, 8>(rv, un.y, lane, npts, stride, R, lds, gacc);
+      } else if (lane < npts) {
+        E* lq = lds + lane * stride;
+        x_final_adjoints<E, SCALED>(P, pfin, lq, smax + lane * S, sexp + lane * S, lq);
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t per = 2u * (uint32_t)M.p + 1u;
+  const int32_t* ro = rec_off + P.recs_off;
+  for (uint32_t i = tid; i < npts * per; i += blockDim.x) {
+    const uint32_t q = i / per, k = i - q * per;
+    const uint32_t pt = pt0 + q;
+    if (k == 0) {
+      double re = 1.0, im = 0.0, ex = P.log2_const;
+      for (int f = 0; f < P.n_finals; ++f) {
+        const XFinal& F = pfin[f];
+        const E a = lds[q * stride + F.lds_off];
+        const double ar = (double)a.x, ai = (double)a.y;
+        if (SCALED && F.slot >= 0) ex += sexp[q * S + F.slot];
+        const double nr = re * ar - im * ai;
+        im = re * ai + im * ar;
+        re = nr;
+      }
+      double* o = M.out + 3 * ((int64_t)pt * M.n_progs + prog_id);
+      o[0] = re;
+      o[1] = im;
+      o[2] = ex;
+    } else {
+      double s = 0.0;
+      for (int r = ro[k - 1]; r < ro[k]; ++r) s += gacc[q * R + r];
+      M.gout[((int64_t)pt * M.n_progs + prog_id) * 2 * M.p + (k - 1)] = s;
+    }
+  }
+}
+
+template <typename E, bool SCALED>
+__global__ __launch_bounds__(kXMaxThreads) void k_lds_grad(
+    const XMulti M, const XProg* __restrict__ progs, const XStep* __restrict__ steps, const XRev* __restrict__ revs,
+    const uint2* __restrict__ units, const int32_t* __restrict__ level_off, const XFinal* __restrict__ finals,
+    const int2* __restrict__ items, const int32_t* __restrict__ rec_off) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t item = blockIdx.x;
-  const int prog_id = item_prog[item / (uint32_t)M.n_points];
+  const int2 it = items[blockIdx.x];
+  const int prog_id = it.x;
   const XProg& P = progs[prog_id];
-  XCtx c;
-  c.pt = item % (uint32_t)M.n_points;
-  c.sb = 0;
-  c.sid = 0;
   const int tid = threadIdx.x;
-  c.lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nw = blockDim.x >> 6;
   const XStep* psteps = steps + P.steps_off;
@@ -1134,6 +1345,11 @@ __global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6,
   const int32_t* plev = level_off + P.levels_off;
   const XFinal* pfin = finals + P.finals_off;
   if (P.scratch_off >= 0) {
+    XCtx c;
+    c.pt = (uint32_t)it.y;
+    c.sb = 0;
+    c.sid = 0;
+    c.lane = tid & 63;
     const XArea a = x_area(P.n_slots, P.n_recs, P.area_elems, (int)sizeof(E));
     char* base = M.scratch + P.scratch_off + (int64_t)c.pt * P.scratch_stride;
     x_grad_item<E, SCALED, true>(M, P, prog_id, psteps, prevs, punits, plev, pfin, rec_off, c, tid, wave, nw,
@@ -1141,12 +1357,8 @@ __global__ __launch_bounds__(kXMaxThreads) __attribute__((amdgpu_waves_per_eu(6,
                                  reinterpret_cast<int*>(base + a.elem_bytes + a.slot_bytes),
                                  reinterpret_cast<double*>(base + a.elem_bytes + 2 * a.slot_bytes));
   } else {
-    const int slots16 = (M.n_slots + 3) & ~3;
-    const int recs2 = (M.n_recs + 1) & ~1;
-    x_grad_item<E, SCALED, false>(M, P, prog_id, psteps, prevs, punits, plev, pfin, rec_off, c, tid, wave, nw,
-                                  reinterpret_cast<E*>(smem + 8 * slots16 + 8 * recs2),
-                                  reinterpret_cast<uint32_t*>(smem), reinterpret_cast<int*>(smem + 4 * slots16),
-                                  reinterpret_cast<double*>(smem + 8 * slots16));
+    x_grad_pts<E, SCALED>(M, P, prog_id, (uint32_t)it.y, psteps, prevs, punits, plev, pfin, rec_off, tid, wave, nw,
+                          smem);
   }
 }
 
@@ -1176,16 +1388,14 @@ size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128) {
   return 8 * slots16 + 8 * recs2 + (size_t)lds_elems * (c128 ? 16 : 8);
 }
 
-hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream) {
-  const int64_t n_items = (int64_t)n_item_progs * m.n_points;
+hipError_t launch_lds_grad(const XMulti& m, int n_items, size_t smem, int waves, hipStream_t stream) {
   if (n_items == 0) return hipSuccess;
-  const size_t smem = lds_grad_smem_bytes(m.n_slots, m.n_recs, m.lds_elems, true);
   const dim3 grid((unsigned)n_items), block((unsigned)(64 * waves));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_grad<double2, false>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_lds_grad<double2, false>), grid, block, smem, stream, m, m.progs, m.steps, m.revs, m.units,
-                     m.level_off, m.finals, m.item_prog, m.rec_off);
+                     m.level_off, m.finals, m.items, m.rec_off);
   return hipGetLastError();
 }
 

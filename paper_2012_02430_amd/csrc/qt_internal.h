@@ -270,6 +270,8 @@ struct XProg {
   int32_t n_pts;
   int32_t pt_stride;
   int32_t slot_stride;
+  int32_t rec_stride;  // gradient programs: gradient records per point
+  int32_t pad;
 };
 
 // Reverse (adjoint) operation of the gradient executor.  For one input T_j
@@ -521,7 +523,7 @@ hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c1
 hipError_t launch_lds_multi(const XMulti& m, int n_items, size_t smem, int waves, bool c128, bool scaled,
                             hipStream_t stream);
 // The gradient executor runs in complex128 (unscaled) for every precision.
-hipError_t launch_lds_grad(const XMulti& m, int n_item_progs, int waves, hipStream_t stream);
+hipError_t launch_lds_grad(const XMulti& m, int n_items, size_t smem, int waves, hipStream_t stream);
 size_t lds_grad_smem_bytes(int n_slots, int n_recs, int lds_elems, bool c128);
 // Bytes of global scratch per point of a program run from it.
 int64_t multi_scratch_bytes(int n_slots, int n_recs, int area_elems, bool c128);

@@ -141,10 +141,11 @@ def test_grad_reproducible(precision):
 
 
 def _job_line(err):
+    """(LDS bytes per point of the largest program in LDS, programs from global scratch) of the last job."""
     lines = [ln for ln in err.splitlines() if ln.startswith("[qt grad] job:")]
     assert lines, err
     ln = lines[-1]
-    return int(ln.split(",")[1].split()[0]), int(ln.split(",")[2].split()[0])
+    return int(ln.split(",")[-1].split()[0]), int(ln.split(",")[2].split()[0])
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])

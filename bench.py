@@ -352,9 +352,10 @@ def energy_section(args):
     model = api.EnergyModel(n, edges, p, precision="c64")
     if args.multi_waves:
         model.set_tuning(args.multi_waves, 0)
-        waves = args.multi_waves
+        waves, cap = args.multi_waves, 0
     else:
-        waves = autotune.tune_energy(model, npt, repeats=3)["waves"]
+        tu = autotune.tune_energy(model, npt, repeats=3)
+        waves, cap = tu["waves"], tu["lds_cap"]
     lib = L.load()
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
     bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
@@ -401,7 +402,7 @@ def energy_section(args):
     # the same evaluation with lightcones deduplicated up to isomorphism: one contraction per class,
     # weighted by the class size (reported apart: it skips the duplicate contractions)
     dd = api.EnergyModel(n, edges, p, precision="c64", dedup=True)
-    dd.set_tuning(waves, 0)
+    dd.set_tuning(waves, 0, cap)
     for _ in range(args.warmup):
         dd.energy_device(gd, bd)
     torch.cuda.synchronize()
@@ -426,7 +427,7 @@ def energy_section(args):
                      "frac_of_packed_peak": tf / VALU_FP32_PACKED_TF, "algorithmic_flops_per_evaluation": flops,
                      "traffic": None},
         "max_abs_err_vs_oracle": err, "err_sample": "300 edges at point 7",
-        "waves": waves,
+        "waves": waves, "lds_cap": cap,
         "plain_c128": {"value": plain_rate, "unit": "edge-energies/s",
                        "sample": f"{len(plain)} lightcones, one launch per bucket step"},
         "speedup_vs_plain_c128": rate / plain_rate,
@@ -447,9 +448,10 @@ def gradient_section(args):
     model = api.EnergyModel(n, edges, p, precision="c64")
     if args.grad_waves:
         model.set_tuning(args.multi_waves, args.grad_waves)
-        waves = args.grad_waves
+        waves, cap = args.grad_waves, 0
     else:
-        waves = autotune.tune_energy(model, npt, grad=True, repeats=3)["waves"]
+        tu = autotune.tune_energy(model, npt, grad=True, repeats=3)
+        waves, cap = tu["waves"], tu["lds_cap"]
         autotune.tune_energy(model, npt, grad=False, repeats=3)
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
     bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
@@ -490,7 +492,7 @@ def gradient_section(args):
                      "peak": VALU_FP64_TF, "unit": "TFLOP/s", "frac": tf / VALU_FP64_TF,
                      "flops": "forward-step flops only (a lower bound of the adjoint's)", "traffic": None},
         "max_normwise_rel_err_vs_oracle": max(errs), "err_sample": "points 0, 21, 42, 63",
-        "waves": waves,
+        "waves": waves, "lds_cap": cap,
     }
 
 

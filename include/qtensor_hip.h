@@ -346,8 +346,8 @@ qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int3
 
 /* Execution tunables of a plan; 0 selects the library default (or the
  * QT_LDS_WAVES, QT_LDS_MAX_RANK, QT_LDS_WAVES_MULTI, QT_LDS_WAVES_GRAD,
- * QT_STEP_LG_TILES (log2 of step_tiles), QT_GEMM_TILES, QT_MULTI_LDS_CAP
- * environment variables when set).  They choose launch shapes and which
+ * QT_STEP_LG_TILES (log2 of step_tiles), QT_GEMM_TILES, QT_MULTI_LDS_CAP,
+ * QT_GRAD_LDS_CAP environment variables when set).  They choose launch shapes and which
  * steps run from LDS rather than streaming, the role Eq. (1) of the paper
  * gives to its thread count per pairwise product; results stay within the
  * stated tolerances and are bitwise reproducible for fixed tunables.
@@ -362,8 +362,11 @@ qt_status qt_profile_read_ops(qt_plan* plan, qt_op_stats* out, int32_t cap, int3
  *   gemm_tiles    output tiles per workgroup of the fused GEMM kernel
  *                 (power of two, 1..64)
  *   multi_lds_cap LDS bytes per workgroup of the batched lightcone launch
- *                 (4096..163840): lightcones needing more run from global
- *                 scratch in the same launch (read from lightcones[0]) */
+ *                 (4096..163840): as many points of a lightcone as fit
+ *                 share a workgroup; lightcones needing more than one
+ *                 point's worth run from global scratch in the same launch
+ *                 (read from lightcones[0])
+ *   grad_lds_cap  the same for the gradient launch */
 typedef struct {
   int32_t lds_waves;
   int32_t lds_max_rank;
@@ -372,6 +375,7 @@ typedef struct {
   int32_t step_tiles;
   int32_t gemm_tiles;
   int32_t multi_lds_cap;
+  int32_t grad_lds_cap;
 } qt_tuning;
 
 /* Sets a plan's tunables (QT_EINVAL outside the ranges above).  A change of

@@ -116,7 +116,8 @@ QT_KCLASS_COUNT = 8
 # name -> (restype, argtypes); every symbol declared in include/*.h
 class qt_tuning(ctypes.Structure):
     _fields_ = [("lds_waves", c_int32), ("lds_max_rank", c_int32), ("multi_waves", c_int32), ("grad_waves", c_int32),
-                ("step_tiles", c_int32), ("gemm_tiles", c_int32), ("multi_lds_cap", c_int32)]
+                ("step_tiles", c_int32), ("gemm_tiles", c_int32), ("multi_lds_cap", c_int32),
+                ("grad_lds_cap", c_int32)]
 
 
 SIGNATURES = {

@@ -182,10 +182,10 @@ class Plan:
         return hashlib.sha1(blob.encode()).hexdigest()
 
     def set_tuning(self, lds_waves=0, lds_max_rank=0, multi_waves=0, grad_waves=0, step_tiles=0, gemm_tiles=0,
-                   multi_lds_cap=0):
+                   multi_lds_cap=0, grad_lds_cap=0):
         """Sets every tunable (0: the library default); ``qt_plan_set_tuning``."""
         t = L.qt_tuning(int(lds_waves), int(lds_max_rank), int(multi_waves), int(grad_waves), int(step_tiles),
-                        int(gemm_tiles), int(multi_lds_cap))
+                        int(gemm_tiles), int(multi_lds_cap), int(grad_lds_cap))
         L.check(L.load().qt_plan_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -477,13 +477,12 @@ class EnergyModel:
 
         return hashlib.sha1(":".join(pl.signature() for pl in self.plans).encode()).hexdigest()
 
-    def set_tuning(self, multi_waves=0, grad_waves=0, multi_lds_cap=0):
-        """Launch shape of the batched lightcone launch (read from the first plan): wavefronts per
-        workgroup of the energy and gradient launches, and the LDS bytes per workgroup above which
-        a lightcone runs from global scratch."""
+    def set_tuning(self, multi_waves=0, grad_waves=0, multi_lds_cap=0, grad_lds_cap=0):
+        """Launch shapes of the batched lightcone launches (read from the first plan): wavefronts
+        per workgroup and LDS bytes per workgroup of the energy and of the gradient launch."""
         for pl in self.plans:
             pl.set_tuning(**dict(pl.get_tuning(), multi_waves=multi_waves, grad_waves=grad_waves,
-                                 multi_lds_cap=multi_lds_cap))
+                                 multi_lds_cap=multi_lds_cap, grad_lds_cap=grad_lds_cap))
 
     def energy_device(self, gammas, betas, grad=False, per_edge=False, stream=None):
         """Device-resident call: gammas/betas are float64 torch tensors [n_points, p] on the GPU.

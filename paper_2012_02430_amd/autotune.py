@@ -178,8 +178,7 @@ def tune_gemm_min_rank(network, order, groups=(), precision="c64_mfma_fp32", n_p
 def tune_energy(model, n_points: int, grad: bool = False, repeats: int = 5, cache: bool = True,
                 waves=MULTI_WAVES, caps=MULTI_LDS_CAPS) -> dict:
     """Picks the wavefronts per workgroup and the LDS bytes per workgroup of ``qt_energy_grad``'s
-    batched launch (energy or gradient) on their joint grid.  The energy and the gradient launch
-    share the LDS cap tunable: the one tuned last is kept."""
+    batched launch (energy or gradient, each with its own pair of tunables) on their joint grid."""
     import numpy as np
     import torch
 
@@ -189,7 +188,10 @@ def tune_energy(model, n_points: int, grad: bool = False, repeats: int = 5, cach
 
     def apply(w, cap):
         t = model.plans[0].get_tuning()
-        model.set_tuning(w if not grad else t["multi_waves"], w if grad else t["grad_waves"], cap)
+        if grad:
+            model.set_tuning(t["multi_waves"], w, t["multi_lds_cap"], cap)
+        else:
+            model.set_tuning(w, t["grad_waves"], cap, t["grad_lds_cap"])
 
     if cache:
         hit = _load(path).get(key)

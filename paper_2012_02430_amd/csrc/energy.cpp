@@ -909,7 +909,8 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     // p = 2 gradient, whose complex128 tensors and records take about twice
     // the bytes per point).
     const int dflt_cap = (grad || lightcones[0]->precision == QT_C128) ? 65536 : 32768;
-    const int64_t lds_cap = std::min<int64_t>(budget, tuned(tu.multi_lds_cap, "QT_MULTI_LDS_CAP", dflt_cap));
+    const int64_t lds_cap = std::min<int64_t>(budget, grad ? tuned(tu.grad_lds_cap, "QT_GRAD_LDS_CAP", dflt_cap)
+                                                           : tuned(tu.multi_lds_cap, "QT_MULTI_LDS_CAP", dflt_cap));
     hipStream_t stream = (hipStream_t)hip_stream;
     std::shared_ptr<EnergyJob> job;
     {

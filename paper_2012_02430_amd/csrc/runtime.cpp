@@ -1396,8 +1396,9 @@ extern "C" qt_status qt_plan_set_tuning(qt_plan* plan, const qt_tuning* t) {
   auto pow2_upto = [](int32_t v, int32_t hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
   if (!pow2_upto(t->step_tiles, 16)) return fail(QT_EINVAL, "qt_plan_set_tuning: step_tiles must be 0, 1, 2, 4, 8 or 16");
   if (!pow2_upto(t->gemm_tiles, 64)) return fail(QT_EINVAL, "qt_plan_set_tuning: gemm_tiles must be 0 or a power of two up to 64");
-  if (t->multi_lds_cap != 0 && (t->multi_lds_cap < 4096 || t->multi_lds_cap > 160 * 1024))
-    return fail(QT_EINVAL, "qt_plan_set_tuning: multi_lds_cap must be 0 or 4096..163840");
+  for (int32_t cap : {t->multi_lds_cap, t->grad_lds_cap})
+    if (cap != 0 && (cap < 4096 || cap > 160 * 1024))
+      return fail(QT_EINVAL, "qt_plan_set_tuning: multi_lds_cap and grad_lds_cap must be 0 or 4096..163840");
   const bool reschedule = t->lds_waves != plan->tuning.lds_waves || t->lds_max_rank != plan->tuning.lds_max_rank;
   const bool relaunch = t->step_tiles != plan->tuning.step_tiles || t->gemm_tiles != plan->tuning.gemm_tiles;
   plan->tuning = *t;

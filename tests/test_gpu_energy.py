@@ -237,3 +237,42 @@ def test_weighted_energy_rejects_negative_weights():
     st = L.load().qt_energy_grad_weighted(model._arr, w.ctypes.data, len(edges), 1, gs.ctypes.data, bs.ctypes.data,
                                           E.ctypes.data, None, None, None, 0)
     assert st == L.QT_EINVAL
+
+
+def test_energy_job_cache_eviction_and_threads():
+    # The library caches one job (uploaded programs and device buffers) per
+    # list of lightcones, at most 16, dropping the oldest; a plan's free drops
+    # its jobs.  Jobs are shared-owned, so a call that holds one survives an
+    # eviction by another thread, and calls on one model are serialised.
+    import threading
+
+    n, p = 10, 1
+    gs, bs = qaoa_params(p, 3, seed=31)
+    models = [api.EnergyModel(n, regular_graph(n, 3, s), p, precision="c128") for s in range(18)]
+    first = [m.energy(gs, bs) for m in models]  # 18 jobs: the first two are evicted
+    for m, e in zip(models, first):  # rebuilt on demand, same values
+        assert np.array_equal(m.energy(gs, bs), e)
+    e0 = models[0].edges
+    want = [sum(edge_energy_sv(n, e0, gs[i], bs[i], u, v) for u, v in e0) for i in range(3)]
+    assert np.abs(first[0] - np.array(want)).max() < 1e-12 * np.abs(want).max()
+    del models[5]  # frees its plans and their jobs
+    errors = []
+
+    def worker(k):
+        try:
+            for _ in range(5):
+                j = (3 * k) % 8  # threads k and k + 8/gcd share a model
+                m = models[j]
+                got = m.energy(gs, bs)
+                ref = first[j if j < 5 else j + 1]
+                if not np.array_equal(got, ref):
+                    errors.append(k)
+        except Exception as ex:  # noqa: BLE001 - reported below
+            errors.append(repr(ex))
+
+    threads = [threading.Thread(target=worker, args=(k % 4,)) for k in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors

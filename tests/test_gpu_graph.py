@@ -105,7 +105,7 @@ def test_energy_graph_replays_equal_eager(grad, dedup, capfd, monkeypatch):
     eager = api.EnergyModel(n, edges, p, precision="c64", dedup=dedup)
     graph = api.EnergyModel(n, edges, p, precision="c64", dedup=dedup, graph=True)
     for m in (eager, graph):
-        m.set_tuning(multi_lds_cap=8192)
+        m.set_tuning(multi_lds_cap=8192, grad_lds_cap=8192)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
     g = torch.zeros(npt, p, dtype=torch.float64, device="cuda")
     b = torch.zeros(npt, p, dtype=torch.float64, device="cuda")

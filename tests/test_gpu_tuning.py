@@ -48,7 +48,7 @@ def test_tune_energy_leaves_results_bitwise(tmp_path, monkeypatch, grad):
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
     for w, cap in ((1, 4096), (16, 0), (4, 160 * 1024)):
-        model.set_tuning(w, w, cap)
+        model.set_tuning(w, w, cap, cap)
         for x, y in zip(before, model.energy(gs, bs, per_edge=True, grad=grad)):
             assert np.array_equal(x, y)
 

@@ -207,13 +207,14 @@ def test_plan_tuning_roundtrip_and_validation(lib):
     edges = regular_graph(16, 3, 0)
     net = api.Network(N.amplitude_network(16, edges, 2))
     plan = api.Plan(net, net.order_greedy("min_fill")[0], precision="c64")
-    names = ("lds_waves", "lds_max_rank", "multi_waves", "grad_waves", "step_tiles", "gemm_tiles", "multi_lds_cap")
+    names = ("lds_waves", "lds_max_rank", "multi_waves", "grad_waves", "step_tiles", "gemm_tiles", "multi_lds_cap",
+             "grad_lds_cap")
     assert plan.get_tuning() == dict.fromkeys(names, 0)
-    plan.set_tuning(8, 12, 2, 4, 4, 32, 65536)
-    assert plan.get_tuning() == dict(zip(names, (8, 12, 2, 4, 4, 32, 65536)))
+    plan.set_tuning(8, 12, 2, 4, 4, 32, 65536, 8192)
+    assert plan.get_tuning() == dict(zip(names, (8, 12, 2, 4, 4, 32, 65536, 8192)))
     for bad in ((17, 0, 0, 0), (0, 5, 0, 0), (0, 17, 0, 0), (0, 0, -1, 0), (0, 0, 0, 99), (0, 0, 0, 0, 3),
                 (0, 0, 0, 0, 32), (0, 0, 0, 0, 0, 128), (0, 0, 0, 0, 0, 6), (0, 0, 0, 0, 0, 0, 4095),
-                (0, 0, 0, 0, 0, 0, 160 * 1024 + 1)):
+                (0, 0, 0, 0, 0, 0, 160 * 1024 + 1), (0, 0, 0, 0, 0, 0, 0, 100)):
         with pytest.raises(L.QTError) as ex:
             plan.set_tuning(*bad)
         assert ex.value.status == L.QT_EINVAL

@@ -162,15 +162,27 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   // linear over disjoint bits: an input's tile part is that of the first
   // tile plus one weight per set low bit (a few scalar adds per tile, and no
   // run tables live across the tile loop).
+  // Small inputs (gates, at most kSmallIn elements per item) are staged in
+  // LDS once and read from there: their loads would otherwise cost vector
+  // memory instructions on the same path as the large operands' for a few
+  // cached bytes.
+  __shared__ E sm[NIN][kSmallIn];
   const E* src[NIN];
-  uint32_t lanep[NIN], tw[NIN][kMaxLgTpb];
+  uint32_t lanep[NIN], tw[NIN][kMaxLgTpb], tbase[NIN];
   R scale[NIN];
   int eacc = 0;
+  bool any_small = false;
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {
     const DevIn& in = s.in[j];
-    src[j] = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-             ((int64_t)pext_bits(sid, in.smask) << in.slow) + ((int64_t)pext_tile(tile0, in) << in.has_v);
+    const E* blk = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                   ((int64_t)pext_bits(sid, in.smask) << in.slow);
+    tbase[j] = pext_tile(tile0, in) << in.has_v;
+    src[j] = blk + tbase[j];
+    if (in.small_n) {
+      any_small = true;
+      if ((int)tid < in.small_n) sm[j][tid] = blk[tid];
+    }
 #pragma unroll
     for (int b = 0; b < kMaxLgTpb; ++b) tw[j][b] = b < s.lg_tpb ? pext_tile(1u << b, in) << in.has_v : 0u;
     lanep[j] = pext_runs(tid, in);
@@ -182,18 +194,21 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
       eacc += exps[slot] + sh;
     }
   }
+  if (any_small) __syncthreads();
   E* const out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
   float mx = 0.f;
   const uint32_t n_here = 1u << s.lg_tpb;
   for (uint32_t t = 0; t < n_here; ++t) {
     const uint32_t tile = tile0 + t;
     __amdgpu_buffer_rsrc_t rs[NIN];
+    uint32_t tpart[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       uint32_t part = 0;
 #pragma unroll
       for (int b = 0; b < kMaxLgTpb; ++b) part += (t >> b) & 1u ? tw[j][b] : 0u;
       rs[j] = rsrc_of(src[j] + part);
+      tpart[j] = tbase[j] + part;
     }
     E a0[kEPT][NIN], a1[kEPT][NIN];
 #pragma unroll
@@ -201,11 +216,14 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
 #pragma unroll
       for (int j = 0; j < NIN; ++j) {
         const int hv = s.in[j].has_v;
-        const uint32_t off = ((s.in[j].ep[e] + lanep[j]) << hv) * (uint32_t)sizeof(E);
-        if (hv) {
-          Cx<E>::bload_pair(rs[j], off, a0[e][j], a1[e][j]);
+        const uint32_t li = (s.in[j].ep[e] + lanep[j]) << hv;
+        if (s.in[j].small_n) {
+          a0[e][j] = sm[j][tpart[j] + li];
+          a1[e][j] = sm[j][tpart[j] + li + (uint32_t)hv];
+        } else if (hv) {
+          Cx<E>::bload_pair(rs[j], li * (uint32_t)sizeof(E), a0[e][j], a1[e][j]);
         } else {
-          a0[e][j] = Cx<E>::bload(rs[j], off);
+          a0[e][j] = Cx<E>::bload(rs[j], li * (uint32_t)sizeof(E));
           a1[e][j] = a0[e][j];
         }
       }

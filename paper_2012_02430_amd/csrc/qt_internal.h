@@ -88,7 +88,12 @@ struct DevIn {
   uint8_t t_len[kMaxRuns];
   uint8_t t_dst[kMaxRuns];
   uint32_t ep[4];
+  // Elements of the tensor's block per batch item when it is small enough
+  // (at most kSmallIn) for the streaming kernel to stage it in LDS; else 0.
+  int32_t small_n;
+  int32_t pad;
 };
+constexpr int kSmallIn = 64;
 
 struct DevStep {
   void* out;

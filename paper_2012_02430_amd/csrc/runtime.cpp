@@ -368,6 +368,8 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
   d.smask = smask;
   d.slow = slow;
   d.has_v = has_v;
+  const int block_rank = st.rank - __builtin_popcount(smask);
+  d.small_n = block_rank <= 6 ? (1 << block_rank) : 0;
   if (!make_runs(mask, kMaxRuns, d.run_lo, d.run_len, d.run_dst, d.nruns)) return false;
   // tile part: the bits of x from 10 up, as runs over the tile index
   constexpr int kLgTile = 10;

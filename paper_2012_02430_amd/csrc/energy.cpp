@@ -460,7 +460,7 @@ qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, in
       const uint64_t zc = full & ~zj;
       rv.ry = __builtin_popcountll(zj);
       rv.nc = __builtin_popcountll(zc);
-      rv.n_ops = x_nin_class((int)st.ins.size());
+      rv.n_ops = (int)st.ins.size();  // the adjoint R-bar and the step's other inputs
       rv.gate = gk;
       rv.param = param;
       rv.rec = -1;
@@ -495,7 +495,7 @@ qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, in
         if (!fill_rop(zj, zc, zmask(st.ins[i]), op))
           return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
       }
-      for (; o < rv.n_ops; ++o) rv.op[o].slot = -1;  // identity operands (element 0, no runs)
+      for (; o < kMaxIn; ++o) rv.op[o].slot = -1;  // unused operands: identity (element 0, no runs)
       if (gk >= 0) recs.push_back({param, (int)pg.revs.size()});
       revs_of[s].push_back((int)pg.revs.size());
       pg.revs.push_back(rv);

@@ -1155,9 +1155,15 @@ __device__ __forceinline__ void x_grad_unit(const uint2 un, const XStep* __restr
     }
   } else if (kind == kXUnitRev) {
     const XRev& rv = prevs[idx];
-    if (rv.n_ops <= 2) x_runit<E, SCALED, 2>(rv, un.y, c.lane, lds, smax, sexp, gacc);
-    else if (rv.n_ops <= 4) x_runit<E, SCALED, 4>(rv, un.y, c.lane, lds, smax, sexp, gacc);
-    else x_runit<E, SCALED, 8>(rv, un.y, c.lane, lds, smax, sexp, gacc);
+    switch (rv.n_ops) {
+      case 1:
+      case 2: x_runit<E, SCALED, 2>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+      case 3: x_runit<E, SCALED, 3>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+      case 4: x_runit<E, SCALED, 4>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+      case 5: x_runit<E, SCALED, 5>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+      case 6: x_runit<E, SCALED, 6>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+      default: x_runit<E, SCALED, 8>(rv, un.y, c.lane, lds, smax, sexp, gacc); break;
+    }
   } else if (c.lane == 0) {
     x_final_adjoints<E, SCALED>(P, pfin, lds, smax, sexp, lds);
   }
@@ -1289,9 +1295,15 @@ __device__ __forceinline__ void x_grad_pts(const XMulti& M, const XProg& P, int 
       } else if (kind == kXUnitRev) {
         static_assert(!SCALED, "the gradient pass runs on unscaled elements");
         const XRev& rv = prevs[idx];
-        if (rv.n_ops <= 2) x_runit_pts<E, 2>(rv, un.y, lane, npts, stride, R, lds, gacc);
-        else if (rv.n_ops <= 4) x_runit_pts<E, 4>(rv, un.y, lane, npts, stride, R, lds, gacc);
-        else x_runit_pts<E, 8>(rv, un.y, lane, npts, stride, R, lds, gacc);
+        switch (rv.n_ops) {  // exact operand counts: no identity operands read or multiplied
+          case 1:
+          case 2: x_runit_pts<E, 2>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+          case 3: x_runit_pts<E, 3>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+          case 4: x_runit_pts<E, 4>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+          case 5: x_runit_pts<E, 5>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+          case 6: x_runit_pts<E, 6>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+          default: x_runit_pts<E, 8>(rv, un.y, lane, npts, stride, R, lds, gacc); break;
+        }
       } else if (lane < npts) {
         E* lq = lds + lane * stride;
         x_final_adjoints<E, SCALED>(P, pfin, lq, smax + lane * S, sexp + lane * S, lq);

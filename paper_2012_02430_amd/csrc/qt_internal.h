@@ -302,7 +302,7 @@ struct XRev {
   int32_t out_slot;   // its scale slot (-1: unscaled)
   int32_t ry;         // bits of y (rank of T_j)
   int32_t nc;         // bits of c
-  int32_t n_ops;      // operand class: 2, 4 or 8
+  int32_t n_ops;      // operands (2..8): R-bar, then the step's other inputs
   int32_t gate;       // -1: tensor adjoint; 0..3: derivative of ZZ, ZZ^dagger, RX, RX^dagger
   int32_t param;      // gate parameter: layer k's gamma at k, its beta at p + k
   int32_t rec;        // gradient record of a gate input

@@ -60,7 +60,7 @@ qt_status fill_xstep(const qt_plan& plan, int s, int elt, Loc out, LocFn loc, XS
   xs.out.slot = out.slot;
   xs.r = st.rank;
   xs.sum = st.sum;
-  xs.n_in = x_nin_class((int)st.ins.size());
+  xs.n_in = (int)st.ins.size();  // exact; operands up to the class (2, 4, 8) are identities
   const int epu = x_epu(st.rank, (int)st.ins.size(), elt);
   for (size_t j = 0; j < st.ins.size(); ++j) {
     const SymIn& si = st.ins[j];
@@ -88,7 +88,7 @@ qt_status fill_xstep(const qt_plan& plan, int s, int elt, Loc out, LocFn loc, XS
       x.ep[e] = r << x.has_v;
     }
   }
-  for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {
+  for (int j = (int)st.ins.size(); j < x_nin_class(xs.n_in); ++j) {
     XOp& id = xs.in[j];  // identity operand
     std::memset(&id, 0, sizeof(id));
     id.has_v = 1;

@@ -702,6 +702,40 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
   }
 }
 
+// x_unit_pts on the step's exact input count (no identity operands read or
+// multiplied); outputs per lane as the host's units assume: kBig for big
+// steps of up to four inputs, half that above four, one for small steps.
+template <typename E, bool SCALED, int kBig>
+__device__ __forceinline__ void x_unit_pts_any(const XStep& st, uint32_t uy, uint32_t lane, uint32_t npts,
+                                               uint32_t stride, uint32_t S, E* __restrict__ lds,
+                                               uint32_t* __restrict__ smax, int* __restrict__ sexp) {
+  constexpr int kHalf = kBig > 1 ? kBig / 2 : 1;
+  const bool big = st.r >= kXBigRank;
+  switch (st.n_in) {
+    case 1:
+    case 2:
+      if (big) x_unit_pts<E, SCALED, 2, kBig>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      else x_unit_pts<E, SCALED, 2, 1>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      break;
+    case 3:
+      if (big) x_unit_pts<E, SCALED, 3, kBig>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      else x_unit_pts<E, SCALED, 3, 1>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      break;
+    case 4:
+      if (big) x_unit_pts<E, SCALED, 4, kBig>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      else x_unit_pts<E, SCALED, 4, 1>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      break;
+    case 5:
+      if (big) x_unit_pts<E, SCALED, 5, kHalf>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      else x_unit_pts<E, SCALED, 5, 1>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      break;
+    default:
+      if (big) x_unit_pts<E, SCALED, 8, kHalf>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      else x_unit_pts<E, SCALED, 8, 1>(st, uy, lane, npts, stride, S, lds, smax, sexp);
+      break;
+  }
+}
+
 // One point-batched item of the multi-program executor: up to P.n_pts
 // points (from pt0) of one program in the workgroup's LDS.
 template <typename E, bool SCALED>
@@ -740,17 +774,7 @@ __device__ __forceinline__ void x_multi_pts(const XMulti& M, const XProg& P, int
     for (int u = plev[L] + wave; u < u_end; u += nw) {
       const uint2 un = punits[u];
       const XStep& st = psteps[un.x];
-      const bool big = st.r >= kXBigRank;
-      if (st.n_in <= 2) {
-        if (big) x_unit_pts<E, SCALED, 2, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        else x_unit_pts<E, SCALED, 2, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-      } else if (st.n_in <= 4) {
-        if (big) x_unit_pts<E, SCALED, 4, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        else x_unit_pts<E, SCALED, 4, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-      } else {
-        if (big) x_unit_pts<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        else x_unit_pts<E, SCALED, 8, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-      }
+      x_unit_pts_any<E, SCALED, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
     }
     __syncthreads();
   }
@@ -1281,17 +1305,7 @@ __device__ __forceinline__ void x_grad_pts(const XMulti& M, const XProg& P, int 
       const uint32_t kind = un.x & ~kXUnitIndex, idx = un.x & kXUnitIndex;
       if (kind == 0) {
         const XStep& st = psteps[idx];
-        const bool big = st.r >= kXBigRank;
-        if (st.n_in <= 2) {
-          if (big) x_unit_pts<E, SCALED, 2, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-          else x_unit_pts<E, SCALED, 2, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        } else if (st.n_in <= 4) {
-          if (big) x_unit_pts<E, SCALED, 4, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-          else x_unit_pts<E, SCALED, 4, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        } else {
-          if (big) x_unit_pts<E, SCALED, 8, (kBig > 1 ? kBig / 2 : 1)>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-          else x_unit_pts<E, SCALED, 8, 1>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
-        }
+        x_unit_pts_any<E, SCALED, kBig>(st, un.y, lane, npts, stride, S, lds, smax, sexp);
       } else if (kind == kXUnitRev) {
         static_assert(!SCALED, "the gradient pass runs on unscaled elements");
         const XRev& rv = prevs[idx];

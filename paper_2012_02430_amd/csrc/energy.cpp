@@ -339,6 +339,25 @@ bool fill_rop(uint64_t zj, uint64_t zc, uint64_t zo, XROp& op) {
   return add_run_pairs(py, op.y_lo, op.y_len, op.y_dst) && add_run_pairs(pc, op.c_lo, op.c_len, op.c_dst);
 }
 
+uint32_t runs_pext(uint64_t x, const uint8_t* lo, const uint8_t* len, const uint8_t* dst) {
+  uint32_t r = 0;
+  for (int i = 0; i < kXRuns; ++i)
+    if (len[i]) r |= (uint32_t)(((x >> lo[i]) & ((1ull << len[i]) - 1ull)) << dst[i]);
+  return r;
+}
+
+// Per-lane-bit weights of a reverse operand's maps (XROp::lw, iw) for an
+// adjoint of ry bits.
+void rop_weights(int ry, XROp& op) {
+  const bool wide = ry >= 6;
+  const uint64_t G = wide ? 1u : (64u >> ry);
+  for (int b = 0; b < 6; ++b) {
+    op.lw[b] = (wide || b < ry) ? runs_pext(1ull << b, op.y_lo, op.y_len, op.y_dst)
+                                : runs_pext(1ull << (b - ry), op.c_lo, op.c_len, op.c_dst);
+    op.iw[b] = runs_pext(G << b, op.c_lo, op.c_len, op.c_dst);
+  }
+}
+
 int gate_deriv_kind(int kind) {
   switch (kind) {
     case QT_T_ZZ: return 0;
@@ -496,6 +515,7 @@ qt_status build_grad_program(const qt_plan& plan, int elt, int64_t cap_elems, in
           return fail(QT_EUNSUPPORTED, "qt_energy_grad: index map too fragmented");
       }
       for (; o < kMaxIn; ++o) rv.op[o].slot = -1;  // unused operands: identity (element 0, no runs)
+      for (int q = 0; q < kMaxIn; ++q) rop_weights(rv.ry, rv.op[q]);
       if (gk >= 0) recs.push_back({param, (int)pg.revs.size()});
       revs_of[s].push_back((int)pg.revs.size());
       pg.revs.push_back(rv);

@@ -1026,20 +1026,35 @@ __device__ __forceinline__ void x_runit_pts(const XRev& rv, uint32_t chunk, uint
   const uint32_t g = wide ? 0u : (lane >> ry);
   const uint32_t G = wide ? 1u : (64u >> ry);
   const uint32_t C = 1u << rv.nc;
-  uint32_t base[NOPS];
+  // operand offsets from the per-lane-bit weights (the run tables only for
+  // a wide adjoint's chunk part and the iteration blocks past the first)
+  uint32_t base[NOPS], cml[NOPS];
 #pragma unroll
   for (int o = 0; o < NOPS; ++o) {
     const XROp& op = rv.op[o];
-    base[o] = op.lds_off + xpext_all(y, op.y_lo, op.y_len, op.y_dst) + xpext_all(g, op.c_lo, op.c_len, op.c_dst);
+    uint32_t lw[6], iw[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      lw[b] = op.lw[b];
+      iw[b] = op.iw[b];
+    }
+    uint32_t bo = op.lds_off, co = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const bool on = (lane >> b) & 1u;
+      bo += on ? lw[b] : 0u;
+      co += on ? iw[b] : 0u;
+    }
+    if (wide && chunk != 0) bo += xpext_all(chunk * 64u, op.y_lo, op.y_len, op.y_dst);
+    base[o] = bo;
+    cml[o] = co;
   }
   const bool live = g < C;
   const uint32_t n_it = C > G ? C / G : 1u;
   const bool one_block = n_it <= 64u;
   uint32_t cm[NOPS];
-  if (one_block) {
 #pragma unroll
-    for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(lane * G, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
-  }
+  for (int o = 0; o < NOPS; ++o) cm[o] = cml[o];
   constexpr int kU = 4;
   for (uint32_t q = 0; q < npts; ++q) {
     const uint32_t qo = q * stride;
@@ -1051,9 +1066,9 @@ __device__ __forceinline__ void x_runit_pts(const XRev& rv, uint32_t chunk, uint
     }
     for (uint32_t ib = 0; ib < n_it; ib += 64) {
       if (!one_block) {
-        const uint32_t ci = (ib + lane) * G;
 #pragma unroll
-        for (int o = 0; o < NOPS; ++o) cm[o] = xpext_all(ci, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst);
+        for (int o = 0; o < NOPS; ++o)
+          cm[o] = cml[o] + (ib ? xpext_all(ib * G, rv.op[o].c_lo, rv.op[o].c_len, rv.op[o].c_dst) : 0u);
       }
       const uint32_t nb = n_it - ib < 64u ? n_it - ib : 64u;
       uint32_t t = 0;

@@ -294,6 +294,12 @@ struct XROp {
   int32_t slot;  // scale slot, -1: unscaled
   uint8_t y_lo[kXRuns], y_len[kXRuns], y_dst[kXRuns];
   uint8_t c_lo[kXRuns], c_len[kXRuns], c_dst[kXRuns];
+  // The same maps per lane bit b of a unit (linear over disjoint bits):
+  // lw[b] = the operand offset of lane bit b (a y bit, or for a small
+  // adjoint above its ry bits a bit of the complement group g);
+  // iw[b] = that of bit b of the iteration index of the first 64
+  // iterations (complement c = g + G i).
+  uint32_t lw[6], iw[6];
 };
 // the executors read these byte tables as 32-bit words
 static_assert(kXRuns % 4 == 0 && offsetof(XROp, y_lo) % 4 == 0 && sizeof(XROp) % 4 == 0, "word-aligned run tables");

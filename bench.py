@@ -328,7 +328,50 @@ def c2_section(args):
         "graph_replay": {"value": graph_value, "unit": "amplitudes/s"},
         "launches_per_amplitude": plan.info().n_launches,
         "tuning": {"lds_waves": tuning["lds_waves"], "lds_max_rank": tuning["lds_max_rank"]},
+        "batch_of_amplitudes": open_outputs(args, n, p, k, edges),
     }
+
+
+def open_outputs(args, n, p, k, edges):
+    """Several amplitudes from one contraction (Section VII): a qubits left open, 2^a amplitudes per
+    contraction of the same 8-variable slicing plan (searched with the open variables excluded)."""
+    import numpy as np
+    import torch
+
+    from paper_2012_02430_amd import api
+    from paper_2012_02430_amd import network as N
+    from workloads import qaoa_params
+
+    out = {}
+    for a in (4, 8):
+        open_q = [int(q) for q in np.random.default_rng(a).choice(n, a, replace=False)]
+        net = api.Network(N.amplitude_network(n, edges, p, open_qubits=open_q))
+        ov = N.open_vars(n, p, open_q)
+        sch = net.plan_slicing(k, algo="min_fill", exclude=ov)
+        plan = api.Plan(net, sch.order, sch.groups, precision="c64", fold_prefix=True, open_vars=ov)
+        g, b = qaoa_params(p, 1, seed=1)
+        gd = torch.tensor(g, dtype=torch.float64, device="cuda")
+        bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+        od = torch.zeros((1 << a) * 3, dtype=torch.float64, device="cuda")
+        steps = max(20, 5 * args.steps)
+        el = time_amplitudes(plan, gd, bd, od, steps, args.warmup)
+        got = od.view(-1, 3).cpu().numpy()
+        amps = np.array([api.amp_to_complex(*row) for row in got])
+        # one entry against the complex128 single amplitude of that bitstring (a plan of its own)
+        j = 5
+        z = np.zeros(n, dtype=np.uint8)
+        for qi, q in enumerate(open_q):
+            z[q] = (j >> (a - 1 - qi)) & 1
+        full = api.Network(N.amplitude_network(n, edges, p, z))
+        want = api.Plan(full, full.order_greedy("min_fill")[0], precision="c128").contract_amplitude(g[0], b[0])
+        err = abs(amps[j] - want) / abs(want)
+        rate = (1 << a) * steps / el
+        log(f"n=60 batch of 2^{a} amplitudes: {rate:.0f} amplitudes/s ({1e3 * el / steps:.3f} ms per contraction), "
+            f"entry {j} rel err {err:.1e}")
+        out[f"a={a}"] = {"value": rate, "unit": "amplitudes/s", "ms_per_contraction": 1e3 * el / steps,
+                         "amplitudes_per_contraction": 1 << a, "width": plan.info().width,
+                         "rel_err_entry5_vs_c128_single_amplitude": err}
+    return out
 
 
 # ------------------------------------------------------------------ energy and gradient

@@ -162,11 +162,11 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
   // linear over disjoint bits: an input's tile part is that of the first
   // tile plus one weight per set low bit (a few scalar adds per tile, and no
   // run tables live across the tile loop).
-  // Small inputs (gates, at most kSmallIn elements per item) are staged in
-  // LDS once and read from there: their loads would otherwise cost vector
-  // memory instructions on the same path as the large operands' for a few
-  // cached bytes.
-  __shared__ E sm[NIN][kSmallIn];
+  // Small inputs (gates and small factors, at most x_small_cap(NIN)
+  // elements per item) are staged in LDS once and read from there: their
+  // loads would otherwise cost vector memory instructions on the same path
+  // as the large operands' for a few cached bytes.
+  __shared__ E sm[NIN][x_small_cap(NIN)];
   const E* src[NIN];
   uint32_t lanep[NIN], tw[NIN][kMaxLgTpb], tbase[NIN];
   R scale[NIN];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
     src[j] = blk + tbase[j];
     if (in.small_n) {
       any_small = true;
-      if ((int)tid < in.small_n) sm[j][tid] = blk[tid];
+      for (int i = (int)tid; i < in.small_n; i += kWG) sm[j][i] = blk[i];
     }
 #pragma unroll
     for (int b = 0; b < kMaxLgTpb; ++b) tw[j][b] = b < s.lg_tpb ? pext_tile(1u << b, in) << in.has_v : 0u;

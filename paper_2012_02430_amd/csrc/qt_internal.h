@@ -89,11 +89,12 @@ struct DevIn {
   uint8_t t_dst[kMaxRuns];
   uint32_t ep[4];
   // Elements of the tensor's block per batch item when it is small enough
-  // (at most kSmallIn) for the streaming kernel to stage it in LDS; else 0.
+  // (at most x_small_cap(inputs of the step)) for the streaming kernel to
+  // stage it in LDS; else 0.
   int32_t small_n;
   int32_t pad;
 };
-constexpr int kSmallIn = 64;
+__host__ __device__ constexpr int x_small_cap(int n_in) { return n_in <= 2 ? 512 : (n_in <= 4 ? 128 : 64); }
 
 struct DevStep {
   void* out;

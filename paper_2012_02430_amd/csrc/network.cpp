@@ -537,6 +537,73 @@ extern "C" qt_status qt_load_plan(const qt_network* net, const qt_plan_desc* d, 
     for (const auto& b : buckets)
       if (!b.empty()) return fail(QT_EPLAN, "qt_load_plan: internal: bucket left unprocessed");
 
+    // A product step (no summed variable) one of whose inputs holds all of
+    // its output's variables and is an intermediate consumed only there,
+    // produced at the same level by a step that is not a fused GEMM, is
+    // merged with that producer: the producer moves to the product's place
+    // (its output has no other reader, and its inputs exist by then) and
+    // takes the product's other inputs without the summed variable (they
+    // multiply both of its v-products alike), so its output is the product.
+    // The product's output's reader reads it instead.  Same arithmetic up
+    // to rounding order, one pass over the large tensor fewer.  The plain
+    // path keeps every step.
+    if (!(d->flags & QT_PLAN_PLAIN)) {
+      for (int pi = 0; pi < (int)steps.size(); ++pi) {
+        const SymStep& P = steps[pi];
+        if (P.sum || P.gemm || P.ins.size() < 2) continue;
+        const uint32_t all = P.rank >= 32 ? ~0u : ((1u << P.rank) - 1u);
+        int cover = -1;
+        for (size_t j = 0; j < P.ins.size(); ++j) {
+          const SymIn& in = P.ins[j];
+          const SymTensor& X = T[in.tensor];
+          if (X.leaf < 0 && X.producer >= 0 && X.consumer == pi && X.rank == P.rank && in.mask == all && !in.smask) {
+            cover = (int)j;
+            break;
+          }
+        }
+        if (cover < 0) continue;
+        const int t = P.ins[cover].tensor;
+        const int si = T[t].producer;
+        if (steps[si].gemm || steps[si].level != P.level || steps[si].ins.size() + P.ins.size() - 1 > (size_t)kMaxIn)
+          continue;
+        SymStep merged = steps[si];
+        double extra_elems = 0;
+        std::vector<int> extra;
+        for (size_t j = 0; j < P.ins.size(); ++j) {
+          if ((int)j == cover) continue;
+          SymIn in = P.ins[j];
+          in.has_v = 0;
+          merged.ins.push_back(in);
+          extra.push_back(in.tensor);
+          extra_elems += std::ldexp(1.0, T[in.tensor].rank - __builtin_popcount(in.smask));
+        }
+        const int m = (int)merged.ins.size();
+        merged.bytes_c64 += 8.0 * extra_elems;
+        merged.flops = std::ldexp(1.0, merged.rank) * (merged.sum ? (12.0 * (m - 1) + 2.0) : 6.0 * (m - 1));
+        const int o = P.out, oc = T[o].consumer;
+        steps[pi] = std::move(merged);  // the merged step at the product's place ...
+        for (const SymIn& in : steps[pi].ins) T[in.tensor].consumer = pi;
+        T[t].producer = pi;
+        T[t].consumer = oc;
+        if (oc == -2) {
+          for (auto& f : plan->finals)
+            if (f == o) f = t;
+        } else if (oc >= 0) {
+          for (SymIn& in : steps[oc].ins)
+            if (in.tensor == o) in.tensor = t;
+        }
+        T[o].producer = -1;
+        T[o].consumer = -1;
+        steps.erase(steps.begin() + si);  // ... and the producer's old place gone
+        for (auto& X : T) {
+          if (X.producer > si) --X.producer;
+          if (X.consumer > si) --X.consumer;
+        }
+        if (si < plan->n_prefix_steps) --plan->n_prefix_steps;
+        pi = si - 1;  // steps from the producer's old place on have moved
+      }
+    }
+
     // Widths and algorithmic counts.
     for (const auto& st : steps) {
       if (st.sum) {

@@ -94,7 +94,12 @@ struct DevIn {
   int32_t small_n;
   int32_t pad;
 };
-__host__ __device__ constexpr int x_small_cap(int n_in) { return n_in <= 2 ? 512 : (n_in <= 4 ? 128 : 64); }
+// Staging capacity per input, as measured on the 210-qubit plan: larger
+// static LDS slowed its three- and four-input steps (whose other inputs are
+// larger) and helped its five-input step, which carries a merged factor.
+__host__ __device__ constexpr int x_small_cap(int n_in) {
+  return n_in <= 2 ? 512 : (n_in <= 4 ? 128 : (n_in == 5 ? 512 : 64));
+}
 
 struct DevStep {
   void* out;

@@ -275,3 +275,28 @@ def test_gemm_fusion_shrinks_the_n210_plan():
     g = [s for s in fused.describe()["stream_steps"] if "gemm" in s]
     assert len(g) >= 1
     assert fused.info().width < plain.info().width
+
+
+def test_product_steps_merged_into_their_producers(lib):
+    # The 210-qubit plan with fused GEMM buckets: the product steps that fold
+    # a bucket's small tensors into a GEMM operand are merged with the step
+    # producing that operand (an extra input without the summed variable);
+    # the plain plan keeps them as steps of their own.
+    from paper_2012_02430_amd import api
+
+    n, p = 210, 1
+    edges = regular_graph(n, 3, 0)
+    net = api.Network(N.amplitude_network(n, edges, p))
+    sch = net.plan_slicing(8, algo="min_degree")
+
+    def products(plan):  # streaming steps with no summed variable whose first input covers the output
+        st = plan.describe()["stream_steps"]
+        return [s for s in st if "gemm" not in s and not any(s["in_has_v"]) and s["in_ranks"][0] == s["rank"]]
+
+    fused = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32")
+    plain = api.Plan(net, sch.order, sch.groups, precision="c64_mfma_fp32", plain=True)
+    assert products(fused) == [] and len(products(plain)) >= 2
+    merged = [s for s in fused.describe()["stream_steps"] if "gemm" not in s and s["in_has_v"][-1] == 0
+              and any(s["in_has_v"])]
+    assert len(merged) >= 2
+    assert fused.info().n_steps == plain.info().n_steps - len(products(plain))

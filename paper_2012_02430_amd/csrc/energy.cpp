@@ -925,10 +925,10 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     const int64_t budget = grad ? std::min<int64_t>(lds_bytes, env_int("QT_GRAD_LDS_BYTES", (int)lds_bytes)) : lds_bytes;
     // Default LDS per workgroup (the autotuner searches this tunable): a few
     // points of a lightcone per workgroup with several workgroups per
-    // compute unit (measured on the 1000-node p = 3 energy and the 200-node
-    // p = 2 gradient, whose complex128 tensors and records take about twice
-    // the bytes per point).
-    const int dflt_cap = (grad || lightcones[0]->precision == QT_C128) ? 65536 : 32768;
+    // compute unit; the time follows the points per wavefront, so the
+    // default pairs 32 KiB with four wavefronts (measured on the 1000-node
+    // p = 3 energy and the 200-node p = 2 gradient).
+    const int dflt_cap = (!grad && lightcones[0]->precision == QT_C128) ? 65536 : 32768;
     const int64_t lds_cap = std::min<int64_t>(budget, grad ? tuned(tu.grad_lds_cap, "QT_GRAD_LDS_CAP", dflt_cap)
                                                            : tuned(tu.multi_lds_cap, "QT_MULTI_LDS_CAP", dflt_cap));
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -954,7 +954,7 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
         job = nj;
       }
     }
-    const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 8)
+    const int waves = std::max(1, std::min(kXMaxThreads / 64, grad ? tuned(tu.grad_waves, "QT_LDS_WAVES_GRAD", 4)
                                                                     : tuned(tu.multi_waves, "QT_LDS_WAVES_MULTI", 4)));
     std::lock_guard<std::mutex> run_lk(job->run_mu);
     // The device sequence: parameters in, the batched launch, the FP64 sums

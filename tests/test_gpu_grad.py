@@ -160,7 +160,7 @@ def test_checkpoint_recompute_under_forced_budget(precision, capfd, monkeypatch)
     gs, bs = qaoa_params(p, 4, seed=7)
     model = api.EnergyModel(n, edges, p, precision=precision)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
-    monkeypatch.setenv("QT_MULTI_LDS_CAP", str(160 * 1024))  # LDS per workgroup up to the budget
+    monkeypatch.setenv("QT_GRAD_LDS_CAP", str(160 * 1024))  # LDS per workgroup up to the budget
     full = model.energy(gs, bs, grad=True)
     need, n_global = _job_line(capfd.readouterr().err)
     assert n_global == 0
@@ -189,7 +189,7 @@ def test_global_scratch_path_matches_lds(precision, capfd, monkeypatch):
     edges = regular_graph(n, 3, 5)
     gs, bs = qaoa_params(p, 3, seed=8)
     model = api.EnergyModel(n, edges, p, precision=precision)
-    monkeypatch.setenv("QT_MULTI_LDS_CAP", str(160 * 1024))
+    monkeypatch.setenv("QT_GRAD_LDS_CAP", str(160 * 1024))
     lds = model.energy(gs, bs, per_edge=True, grad=True)
     monkeypatch.setenv("QT_DEBUG_GRAD_SCHEDULE", "1")
     monkeypatch.setenv("QT_GRAD_LDS_BYTES", "1024")

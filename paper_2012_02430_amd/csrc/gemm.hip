@@ -336,18 +336,12 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
               accI[r] = t3[r] - t1[r] - t2[r];
             }
           } else {
-            // short stages: 3M as well, three products per 4-deep slice
-            v4f t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
             for (int kk = 0; kk < tk; kk += 4) {
               const float ar = ar_p[kk], ai = ai_p[kk], br = br_p[kk], bi = bi_p[kk];
-              t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, t1, 0, 0, 0);
-              t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, t2, 0, 0, 0);
-              t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, br + bi, t3, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              accR[r] = t1[r] - t2[r];
-              accI[r] = t3[r] - t1[r] - t2[r];
+              accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accR, 0, 0, 0);
+              accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accR, 0, 0, 0);
+              accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, accI, 0, 0, 0);
+              accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, accI, 0, 0, 0);
             }
           }
         } else {

@@ -371,7 +371,7 @@ struct DevGemm {
   int32_t c_exp_base, c_exp_pt, c_exp_sb;
   int32_t tb, tm, tn;      // tile bits of the b, m, n counters (chosen on the host)
   int32_t tk;              // K stage depth (8, 16 or 64; 32 in mode 1)
-  int32_t mode;            // 0: FP32 products (3M); 1: split-BF16 products (3M), QT_C64_SCALED_MFMA_BF16X3
+  int32_t mode;            // 0: FP32 products (3M at depth 64, else 4M); 1: split-BF16 products (3M), QT_C64_SCALED_MFMA_BF16X3
   int32_t tiles;           // output tiles per workgroup (0: the default for the depth)
   // storage bits of each counter in each tensor
   uint32_t a_bm, a_mm, a_km, b_bm, b_nm, b_km, c_bm, c_mm, c_nm;

@@ -1468,7 +1468,7 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
                                 choose_gemm_tile(*plan, st, tb, tm, tn, tk, mode);
                                 return "[" + std::to_string(tb) + "," + std::to_string(tm) + "," +
                                        std::to_string(tn) + "," + std::to_string(tk) + "],\"mode\":\"" +
-                                       (mode ? "bf16x3_3m" : "fp32_3m") + "\"";
+                                       (mode ? "bf16x3_3m" : (tk == 64 ? "fp32_3m" : "fp32_4m")) + "\"";
                               }() + ",\"layouts\":" + [&] {
                                 // per operand, from bit 0 up: the counter each storage bit belongs to
                                 const auto& va = plan->tensors[st.ins[0].tensor].vars;

@@ -302,7 +302,7 @@ def test_c4_fused_gemm_per_slice_parity(precision):
     gem = sorted((s["gemm"]["k_bits"], s["gemm"]["mode"]) for s in fused.describe()["stream_steps"] if "gemm" in s)
     assert [k for k, _ in gem] == [4, 9], gem  # the K = 16 and K = 512 buckets
     if precision == "c64_mfma_bf16x3":
-        assert gem[1][1] == "bf16x3_3m" and gem[0][1] == "fp32_3m"
+        assert gem[1][1] == "bf16x3_3m" and gem[0][1] == "fp32_4m"
     plain = api.Plan(net, sch.order, sch.groups, precision="c128", slice_batch=1, plain=True)
     g, b = qaoa_params(p, 1, seed=11)
     for lo, hi in ((0, 2), (181, 183)):

@@ -188,7 +188,7 @@ def test_split_bf16_short_k_keeps_fp32_products(monkeypatch):
     spec, tensors, order, _ = dense_case(75, 1, 5, 5, 4)
     plan = api.Plan(api.Network(spec), order, precision="c64_mfma_bf16x3")
     g = gemm_steps(plan)
-    assert len(g) == 1 and g[0]["gemm"]["mode"] == "fp32_3m"
+    assert len(g) == 1 and g[0]["gemm"]["mode"] == "fp32_4m"
     got = plan.contract_amplitude([], [])
     want = oracle.contract(tensors, order)
     assert abs(got - want) / abs(want) < TOL

@@ -329,7 +329,33 @@ def c2_section(args):
         "launches_per_amplitude": plan.info().n_launches,
         "tuning": {"lds_waves": tuning["lds_waves"], "lds_max_rank": tuning["lds_max_rank"]},
         "batch_of_amplitudes": open_outputs(args, n, p, k, edges),
+        "parameter_batch": points_batch(args, plan, p),
     }
+
+
+def points_batch(args, plan, p):
+    """The same amplitude at 32 seeded (gamma, beta) points per call (one launch runs every point and
+    slice): throughput once the single amplitude's dependency-chain latency is shared by many items."""
+    import torch
+
+    from workloads import qaoa_params
+
+    npt = 32
+    g, b = qaoa_params(p, npt, seed=2)
+    gd = torch.tensor(g, dtype=torch.float64, device="cuda")
+    bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+    od = torch.zeros(npt, 3, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup + 1):
+        plan.contract_device(gd, bd, od)
+    torch.cuda.synchronize()
+    steps = max(10, 2 * args.steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.contract_device(gd, bd, od)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    log(f"n=60 amplitude at {npt} parameter points per call: {npt / el:.0f} amplitudes/s ({1e3 * el:.3f} ms per call)")
+    return {"metric": "amplitudes/s", "value": npt / el, "points_per_call": npt, "ms_per_call": 1e3 * el}
 
 
 def open_outputs(args, n, p, k, edges):

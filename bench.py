@@ -423,7 +423,7 @@ def energy_section(args):
         model.set_tuning(args.multi_waves, 0)
         waves, cap = args.multi_waves, 0
     else:
-        tu = autotune.tune_energy(model, npt, repeats=3)
+        tu = autotune.tune_energy(model, npt, repeats=7)
         waves, cap = tu["waves"], tu["lds_cap"]
     lib = L.load()
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
@@ -519,9 +519,9 @@ def gradient_section(args):
         model.set_tuning(args.multi_waves, args.grad_waves)
         waves, cap = args.grad_waves, 0
     else:
-        tu = autotune.tune_energy(model, npt, grad=True, repeats=3)
+        tu = autotune.tune_energy(model, npt, grad=True, repeats=7)
         waves, cap = tu["waves"], tu["lds_cap"]
-        autotune.tune_energy(model, npt, grad=False, repeats=3)
+        autotune.tune_energy(model, npt, grad=False, repeats=7)
     gd = torch.tensor(gs, dtype=torch.float64, device="cuda")
     bd = torch.tensor(bs, dtype=torch.float64, device="cuda")
     steps = max(10, 2 * args.steps)

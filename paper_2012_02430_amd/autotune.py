@@ -68,9 +68,11 @@ def _arch() -> str:
 
 
 def _time_ms(fn, repeats: int) -> float:
-    """Median over `repeats` timed calls (HIP events on torch's current stream), after one untimed call."""
+    """Median over `repeats` timed calls (HIP events on torch's current stream), after two untimed calls
+    (the first may build the call's device state)."""
     import torch
 
+    fn()
     fn()
     torch.cuda.synchronize()
     times = []

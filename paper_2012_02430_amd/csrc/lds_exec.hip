@@ -138,11 +138,67 @@ __device__ __forceinline__ uint32_t xwave_max(uint32_t v) {
 // Power of two that brings max|x| into [0.5, 1), clamped so that 2^-shift is
 // a normal float.
 __device__ __forceinline__ int xshift(uint32_t maxbits) {
+  // ilogb + 1 from the biased exponent field; a subnormal max (field 0)
+  // lands on the lower clamp, as ilogb would, and an infinite one on the
+  // upper
   if (maxbits == 0) return 0;
-  const int s = ilogbf(__uint_as_float(maxbits)) + 1;
-  return s < -126 ? -126 : (s > 127 ? 127 : s);
+  const int s = (int)((maxbits >> 23) & 0xffu) - 126;
+  return s > 127 ? 127 : s;
 }
 __device__ __forceinline__ float xpow2neg(int sh) { return __int_as_float((127 - sh) << 23); }
+
+// Holds a wavefront-uniform value in a scalar register from this point on:
+// the scalar loads it comes from complete here and are not scheduled among
+// later LDS accesses.
+__device__ __forceinline__ uint32_t xpin(uint32_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+__device__ __forceinline__ int xpin(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+__device__ __forceinline__ uint64_t xpin(uint64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+__device__ __forceinline__ int64_t xpin(int64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// The output part of a step descriptor and its rank and sum flag, as the
+// unit uses them (loaded with the operand fields, pinned with them).
+struct XOutRegs {
+  uint64_t ptr;
+  int64_t pt_stride, sb_stride;
+  uint32_t lds_off;
+  int slot_kind, slot, exp_pt, exp_sb, r, sum;
+  __device__ __forceinline__ void load(const XStep& st) {
+    ptr = reinterpret_cast<uint64_t>(st.out.ptr);
+    pt_stride = st.out.pt_stride;
+    sb_stride = st.out.sb_stride;
+    lds_off = st.out.lds_off;
+    slot_kind = st.out.slot_kind;
+    slot = st.out.slot;
+    exp_pt = st.out.exp_pt;
+    exp_sb = st.out.exp_sb;
+    r = st.r;
+    sum = st.sum;
+  }
+  __device__ __forceinline__ void pin() {
+    ptr = xpin(ptr);
+    pt_stride = xpin(pt_stride);
+    sb_stride = xpin(sb_stride);
+    lds_off = xpin(lds_off);
+    slot_kind = xpin(slot_kind);
+    slot = xpin(slot);
+    exp_pt = xpin(exp_pt);
+    exp_sb = xpin(exp_sb);
+    r = xpin(r);
+    sum = xpin(sum);
+  }
+};
 
 struct XCtx {
   uint32_t pt, sb;
@@ -150,12 +206,56 @@ struct XCtx {
   uint32_t lane;
 };
 
+// The operands of a unit's outputs: element e of operand j at LDS index
+// base + lp + ep (lp and ep shifted by has_v), and its v = 1 partner.
+template <typename E, int NIN, int EPU>
+__device__ __forceinline__ void x_load_ops(const E* __restrict__ lds, const uint32_t (&base)[NIN],
+                                           const uint32_t (&lp)[NIN], const uint32_t (&ep)[NIN][EPU],
+                                           const uint32_t (&hv)[NIN], E (&a0)[EPU][NIN], E (&a1)[EPU][NIN]) {
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const uint32_t i = base[j] + lp[j] + ep[j][e];
+      a0[e][j] = lds[i];
+      a1[e][j] = lds[i + hv[j]];
+    }
+  }
+}
+
+// The two elements of an operand at v = 0 and v = 1: adjacent (v is the
+// lowest bit of every operand that holds it) and, at an even index, one
+// aligned access.
+template <typename E>
+struct alignas(2 * sizeof(E)) XPair {
+  E a, b;
+};
+
+// x_load_ops for a step whose every operand holds v at an even base (the
+// host checks both): each pair in one read, which also spreads the lanes of
+// a wavefront over all LDS banks where two reads at a stride of two
+// elements would conflict.
+template <typename E, int NIN, int EPU>
+__device__ __forceinline__ void x_load_pairs(const E* __restrict__ lds, const uint32_t (&base)[NIN],
+                                             const uint32_t (&lp)[NIN], const uint32_t (&ep)[NIN][EPU],
+                                             E (&a0)[EPU][NIN], E (&a1)[EPU][NIN]) {
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      const XPair<E> q = *reinterpret_cast<const XPair<E>*>(lds + base[j] + lp[j] + ep[j][e]);
+      a0[e][j] = q.a;
+      a1[e][j] = q.b;
+    }
+  }
+}
+
 // PRE: read the unit's descriptor fields, scale slots and maps in phases,
 // each one batch of loads (a few round trips per unit instead of one per
 // field), else read each field where it is used (kernels short of
 // registers).  FOLDED: the descriptor is the unit's own copy, with the
 // chunk's part of each operand index already in lds_off.
-template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true, bool FOLDED = false>
+template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true, bool FOLDED = false, bool PAIRS = false>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,
                                        uint32_t* __restrict__ gmax) {
@@ -164,10 +264,17 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
   uint32_t base[NIN], lp[NIN];
   R sc[NIN];
   int eacc = 0;
+  uint32_t hvv[NIN], epv[NIN][EPU];
+  int slotv[NIN];  // scale slot per operand, -1: unscaled (its scale stays 1 and is not applied)
+  XOutRegs ov;
+  E a0[EPU][NIN], a1[EPU][NIN];
   if constexpr (PRE) {
-    // Setup in phases so that each phase's loads issue together: the
-    // operands' descriptor fields, then their scale slots (read even for an
-    // unscaled operand, at slot 0, and ignored), then the index maps.
+    // Setup in phases so that each phase's loads issue together: every
+    // descriptor word the unit uses (one batch of scalar loads, held in
+    // scalar registers: a wait on a scalar load also drains the LDS accesses
+    // in flight, so none may fall between the operand loads), then the
+    // scale slots (read even for an unscaled operand, at slot 0, and
+    // ignored), then the index maps.
     uint32_t smk[NIN];
     int slw[NIN], slot[NIN];
 #pragma unroll
@@ -176,26 +283,14 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       smk[j] = st.in[j].smask;
       slw[j] = st.in[j].slow;
       slot[j] = st.in[j].slot;
-    }
-    uint32_t mbits[NIN];
-    int mexp[NIN];
-    if (SCALED) {
+      hvv[j] = (uint32_t)st.in[j].has_v;
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) {
-        const int q = slot[j] >= 0 ? slot[j] : 0;
-        mbits[j] = smax[q];
-        mexp[j] = sexp[q];
-      }
+      for (int e = 0; e < EPU; ++e) epv[j][e] = st.in[j].ep[e];
     }
-    // the lane part from the packed lane runs; unless the chunk part is
-    // folded in, and past the first chunk (whose part is zero: the common
-    // case of small steps), the run tables as words (6 per operand: lo,
-    // len, dst for runs 0-3 and 4-7), all loaded before any is used
+    ov.load(st);
     uint32_t lw[NIN];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) lw[j] = st.in[j].lane_runs;
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
     if constexpr (!FOLDED) {
       if (chunk != 0) {
         uint32_t rw[NIN][6];
@@ -206,28 +301,69 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
           for (int q = 0; q < 6; ++q) rw[j][q] = w[q];
         }
 #pragma unroll
-        for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(cx, rw[j]) << st.in[j].has_v;
+        for (int j = 0; j < NIN; ++j) lw[j] = xpin(lw[j]);
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) base[j] += xpext_words(cx, rw[j]) << hvv[j];
       }
     }
 #pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      base[j] = xpin(base[j]);
+      smk[j] = xpin(smk[j]);
+      slw[j] = xpin(slw[j]);
+      slot[j] = xpin(slot[j]);
+      hvv[j] = xpin(hvv[j]);
+      lw[j] = xpin(lw[j]);
+#pragma unroll
+      for (int e = 0; e < EPU; ++e) epv[j][e] = xpin(epv[j][e]);
+    }
+    ov.pin();
+    uint32_t mbits[NIN];
+    int mexp[NIN];
+    if (SCALED) {
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) {
+        const int q = slot[j] >= 0 ? slot[j] : 0;
+        mbits[j] = smax[q];
+        mexp[j] = sexp[q];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) slotv[j] = slot[j];
+    // the lane part from the packed lane runs (the chunk part, unless
+    // folded into lds_off, was added to base above: past the first chunk,
+    // whose part is zero, from the run tables as words, 6 per operand: lo,
+    // len, dst for runs 0-3 and 4-7)
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(c.lane, lw[j]);
+#pragma unroll
     for (int j = 0; j < NIN; ++j)
       if (smk[j]) base[j] += xpext_bits(c.sid, smk[j]) << slw[j];
+    // the operand loads issue before the scale slots are waited for; the
+    // slots (the same in every lane) are then decoded on the scalar unit
+    if constexpr (PAIRS) x_load_pairs<E, NIN, EPU>(lds, base, lp, epv, a0, a1);
+    else x_load_ops<E, NIN, EPU>(lds, base, lp, epv, hvv, a0, a1);
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       sc[j] = (R)1;
       if (SCALED && slot[j] >= 0) {
-        const int sh = xshift(mbits[j]);
+        const int sh = xshift((uint32_t)__builtin_amdgcn_readfirstlane((int)mbits[j]));
         sc[j] = (R)xpow2neg(sh);
-        eacc += mexp[j] + sh;
+        eacc += __builtin_amdgcn_readfirstlane(mexp[j]) + sh;
       }
     }
   } else {
+    ov.load(st);
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
       const XOp& in = st.in[j];
+      hvv[j] = (uint32_t)in.has_v;
+#pragma unroll
+      for (int e = 0; e < EPU; ++e) epv[j][e] = in.ep[e];
       base[j] = in.lds_off + (xpext_bits(c.sid, in.smask) << in.slow);
       lp[j] = xpext_lane_word(c.lane, in.lane_runs);
       if (chunk != 0) lp[j] += xpext_all(cx, in.run_lo, in.run_len, in.run_dst) << in.has_v;
+      slotv[j] = in.slot;
       sc[j] = (R)1;
       if (SCALED && in.slot >= 0) {
         const int sh = xshift(smax[in.slot]);
@@ -235,51 +371,44 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
         eacc += sexp[in.slot] + sh;
       }
     }
+    x_load_ops<E, NIN, EPU>(lds, base, lp, epv, hvv, a0, a1);
   }
-  E a0[EPU][NIN], a1[EPU][NIN];
-#pragma unroll
-  for (int e = 0; e < EPU; ++e) {
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) {
-      const uint32_t hv = (uint32_t)st.in[j].has_v;
-      const uint32_t i = base[j] + lp[j] + st.in[j].ep[e];  // lp and ep are shifted by has_v
-      a0[e][j] = lds[i];
-      a1[e][j] = lds[i + hv];
-    }
-  }
-  const XOut& o = st.out;
-  const uint32_t n = 1u << st.r;
+  const uint32_t n = 1u << ov.r;
   float m = 0.f;
   E res[EPU];
+  // the product over operands in their order, each scaled operand times
+  // its power of two first (an unscaled one is used as loaded)
+  E t0[EPU], t1[EPU];
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    if (SCALED && slotv[j] >= 0) {
+#pragma unroll
+      for (int e = 0; e < EPU; ++e) {
+        a0[e][j] = xscale(a0[e][j], sc[j]);
+        a1[e][j] = xscale(a1[e][j], sc[j]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) {
+      t0[e] = j == 0 ? a0[e][0] : xmul(t0[e], a0[e][j]);
+      t1[e] = j == 0 ? a1[e][0] : xmul(t1[e], a1[e][j]);
+    }
+  }
 #pragma unroll
   for (int e = 0; e < EPU; ++e) {
-    E t0 = a0[e][0], t1 = a1[e][0];
-    if (SCALED) {
-      t0 = xscale(t0, sc[0]);
-      t1 = xscale(t1, sc[0]);
-    }
-#pragma unroll
-    for (int j = 1; j < NIN; ++j) {
-      E x0 = a0[e][j], x1 = a1[e][j];
-      if (SCALED) {
-        x0 = xscale(x0, sc[j]);
-        x1 = xscale(x1, sc[j]);
-      }
-      t0 = xmul(t0, x0);
-      t1 = xmul(t1, x1);
-    }
-    res[e] = st.sum ? xadd(t0, t1) : t0;
+    res[e] = ov.sum ? xadd(t0[e], t1[e]) : t0[e];
     const uint32_t x = cx + e * 64u + c.lane;
     if (SCALED && x < n) m = fmaxf(m, fmaxf(fabsf((float)res[e].x), fabsf((float)res[e].y)));
   }
-  if (o.ptr == nullptr) {
+  if (ov.ptr == 0) {
 #pragma unroll
     for (int e = 0; e < EPU; ++e) {
       const uint32_t x = cx + e * 64u + c.lane;
-      if (x < n) lds[o.lds_off + x] = res[e];
+      if (x < n) lds[ov.lds_off + x] = res[e];
     }
   } else {
-    gmut_t<E> g = (gmut_t<E>)(reinterpret_cast<E*>(o.ptr) + (int64_t)c.pt * o.pt_stride + (int64_t)c.sb * o.sb_stride);
+    gmut_t<E> g = (gmut_t<E>)(reinterpret_cast<E*>(ov.ptr) + (int64_t)c.pt * ov.pt_stride +
+                              (int64_t)c.sb * ov.sb_stride);
 #pragma unroll
     for (int e = 0; e < EPU; ++e) {
       const uint32_t x = cx + e * 64u + c.lane;
@@ -289,14 +418,14 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
       }
     }
   }
-  if (SCALED && o.slot_kind != 0) {
+  if (SCALED && ov.slot_kind != 0) {
     const uint32_t mw = xwave_max(__float_as_uint(m));
     if (c.lane == 0) {
-      if (o.slot_kind == 1) {
-        atomicMax(smax + o.slot, mw);
-        if (chunk == 0) sexp[o.slot] = eacc;
+      if (ov.slot_kind == 1) {
+        atomicMax(smax + ov.slot, mw);
+        if (chunk == 0) sexp[ov.slot] = eacc;
       } else {
-        const int g = o.slot + (int)c.pt * o.exp_pt + (int)c.sb * o.exp_sb;
+        const int g = ov.slot + (int)c.pt * ov.exp_pt + (int)c.sb * ov.exp_sb;
         atomicMax(gmax + g, mw);
         if (chunk == 0) gexps[g] = eacc;
       }
@@ -409,9 +538,31 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
     const int u_end = level_off[L + 1];
     for (int u = u_beg + wave; u < u_end; u += nw) {
       const XStep& st = steps[u];
-      const uint32_t chunk = (uint32_t)st.pad;
+      const uint32_t chunk = (uint32_t)st.chunk;
       const bool big = st.r >= kXBigRank;
-      if (st.n_in <= 2) {
+      constexpr int kHalf = kBig > 1 ? kBig / 2 : 1;
+      if (st.out.pairs != 0 && st.n_in <= 5) {
+        // exact operand counts, pairs read as one access
+        switch (st.n_in) {
+          case 1:
+          case 2:
+            if (big) x_unit<E, SCALED, 2, kBig, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            else x_unit<E, SCALED, 2, 1, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            break;
+          case 3:
+            if (big) x_unit<E, SCALED, 3, kBig, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            else x_unit<E, SCALED, 3, 1, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            break;
+          case 4:
+            if (big) x_unit<E, SCALED, 4, kBig, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            else x_unit<E, SCALED, 4, 1, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            break;
+          default:
+            if (big) x_unit<E, SCALED, 5, kHalf, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            else x_unit<E, SCALED, 5, 1, true, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
+            break;
+        }
+      } else if (st.n_in <= 2) {
         if (big) x_unit<E, SCALED, 2, kBig, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
         else x_unit<E, SCALED, 2, 1, true, true>(st, chunk, c, lds, smax, sexp, gexps, gmax);
       } else if (st.n_in <= 4) {
@@ -586,7 +737,33 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
                                            uint32_t S, E* __restrict__ lds, uint32_t* __restrict__ smax,
                                            int* __restrict__ sexp) {
   using R = typename XReal<E>::R;
-  const int r = st.r;
+  // every descriptor word first, in one batch of scalar loads held in
+  // scalar registers (a wait on a scalar load drains the LDS accesses in
+  // flight, so none may fall between the operand loads)
+  uint32_t base[NIN], lw[NIN], hvv[NIN], epv[NIN][EPU];
+  int slot[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    base[j] = st.in[j].lds_off;
+    slot[j] = st.in[j].slot;
+    lw[j] = st.in[j].lane_runs;
+    hvv[j] = (uint32_t)st.in[j].has_v;
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) epv[j][e] = st.in[j].ep[e];
+  }
+  const int r = xpin(st.r);
+  const int sum = xpin(st.sum);
+  const uint32_t o_off = xpin(st.out.lds_off);
+  const int o_slot = xpin(st.out.slot);
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    base[j] = xpin(base[j]);
+    slot[j] = xpin(slot[j]);
+    lw[j] = xpin(lw[j]);
+    hvv[j] = xpin(hvv[j]);
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) epv[j][e] = xpin(epv[j][e]);
+  }
   const uint32_t n = 1u << r;
   const bool packed = r < 6;
   uint32_t q, xl, chunk = 0;
@@ -604,15 +781,11 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
   const uint32_t qq = valid ? q : 0u;
   const uint32_t qoff = qq * stride, soff = qq * S;
   const uint32_t cx = chunk * EPU * 64u;
-  uint32_t base[NIN], lp[NIN];
-  int slot[NIN];
+  uint32_t lp[NIN];
   R sc[NIN];
   int eacc = 0;
 #pragma unroll
-  for (int j = 0; j < NIN; ++j) {
-    base[j] = st.in[j].lds_off + qoff;
-    slot[j] = st.in[j].slot;
-  }
+  for (int j = 0; j < NIN; ++j) base[j] += qoff;
   uint32_t mbits[NIN];
   int mexp[NIN];
   if (SCALED) {
@@ -623,12 +796,10 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
       mexp[j] = sexp[s];
     }
   }
-  uint32_t lw[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; ++j) lw[j] = st.in[j].lane_runs;
 #pragma unroll
   for (int j = 0; j < NIN; ++j) lp[j] = xpext_lane_word(xl, lw[j]);
   if (chunk != 0) {
+    // past the first chunk (wavefront-uniform): the run tables as words
     uint32_t rw[NIN][6];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) {
@@ -637,8 +808,10 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
       for (int k = 0; k < 6; ++k) rw[j][k] = w[k];
     }
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(cx, rw[j]) << st.in[j].has_v;
+    for (int j = 0; j < NIN; ++j) lp[j] += xpext_words(cx, rw[j]) << hvv[j];
   }
+  E a0[EPU][NIN], a1[EPU][NIN];
+  x_load_ops<E, NIN, EPU>(lds, base, lp, epv, hvv, a0, a1);
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {
     sc[j] = (R)1;
@@ -648,18 +821,6 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
       eacc += mexp[j] + sh;
     }
   }
-  E a0[EPU][NIN], a1[EPU][NIN];
-#pragma unroll
-  for (int e = 0; e < EPU; ++e) {
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) {
-      const uint32_t hv = (uint32_t)st.in[j].has_v;
-      const uint32_t i = base[j] + lp[j] + st.in[j].ep[e];
-      a0[e][j] = lds[i];
-      a1[e][j] = lds[i + hv];
-    }
-  }
-  const XOut& o = st.out;
   float m = 0.f;
 #pragma unroll
   for (int e = 0; e < EPU; ++e) {
@@ -678,10 +839,10 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
       t0 = xmul(t0, x0);
       t1 = xmul(t1, x1);
     }
-    const E res = st.sum ? xadd(t0, t1) : t0;
+    const E res = sum ? xadd(t0, t1) : t0;
     const uint32_t x = cx + e * 64u + xl;
     if (valid && x < n) {
-      lds[qoff + o.lds_off + x] = res;
+      lds[qoff + o_off + x] = res;
       if (SCALED) m = fmaxf(m, fmaxf(fabsf((float)res.x), fabsf((float)res.y)));
     }
   }
@@ -689,14 +850,14 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
     if (packed) {
       const uint32_t mw = xseg_max(__float_as_uint(m), r);
       if (valid && xl == 0u) {
-        smax[soff + o.slot] = mw;
-        sexp[soff + o.slot] = eacc;
+        smax[soff + o_slot] = mw;
+        sexp[soff + o_slot] = eacc;
       }
     } else {
       const uint32_t mw = xwave_max(__float_as_uint(m));
       if (lane == 0u && valid) {
-        atomicMax(smax + soff + o.slot, mw);
-        if (chunk == 0) sexp[soff + o.slot] = eacc;
+        atomicMax(smax + soff + o_slot, mw);
+        if (chunk == 0) sexp[soff + o_slot] = eacc;
       }
     }
   }

@@ -163,15 +163,21 @@ struct XOut {
   int32_t slot;
   int32_t exp_pt;
   int32_t exp_sb;
-  int32_t pad;
+  int32_t pairs;  // LDS executor: every operand holds v at an even base (see XStep)
 };
 
+// A step of the LDS executors.  n_in is the exact operand count; in[] is
+// padded with identity operands up to 2, 4 or 8.  chunk: the unit's chunk
+// where each unit has its own copy (the chunk's part of every operand index
+// then folded into lds_off).  out.pairs = 1 when every operand holds the
+// summed variable (as bit 0) at an even LDS base, so that the v = 0 and
+// v = 1 elements are one aligned pair.
 struct XStep {
   XOut out;
   int32_t r;
   int32_t sum;
   int32_t n_in;
-  int32_t pad;
+  int32_t chunk;
   XOp in[kMaxIn];
 };
 

@@ -647,16 +647,24 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
       to_out(st.out, xs.out);
       xs.r = st.rank;
       xs.sum = st.sum;
-      xs.n_in = x_nin_class((int)st.ins.size());
+      xs.n_in = (int)st.ins.size();
       const int epu = x_epu(st.rank, (int)st.ins.size(), elt);
       for (size_t j = 0; j < st.ins.size(); ++j)
         if (!to_op(st.ins[j].tensor, st.ins[j], epu, xs.in[j]))
           return fail(QT_EPLAN, "internal: LDS segment operand not in LDS or index map too fragmented");
-      for (int j = (int)st.ins.size(); j < xs.n_in; ++j) {
+      for (int j = (int)st.ins.size(); j < x_nin_class(xs.n_in); ++j) {
         XOp& id = xs.in[j];  // identity operand: LDS elements 0 and 1 (1 + 0i), index 0
         std::memset(&id, 0, sizeof(id));
         id.has_v = 1;
         id.slot = -1;
+      }
+      // pairs: every operand (identities included) holds v, at an even
+      // base: LDS offsets even, slice blocks above bit 0, lane and chunk
+      // parts shifted by has_v
+      xs.out.pairs = 1;
+      for (int j = 0; j < x_nin_class(xs.n_in); ++j) {
+        const XOp& o = xs.in[j];
+        if (o.has_v != 1 || (o.lds_off & 1u) != 0 || (o.smask != 0 && o.slow < 1)) xs.out.pairs = 0;
       }
     }
     S.units.clear();
@@ -694,12 +702,12 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
         cp.lslot = ws.lds_slot[t];
         S.copies.push_back(cp);
       }
-    // per-unit descriptors: the unit's chunk in the pad field, and the
+    // per-unit descriptors: the unit's chunk in the chunk field, and the
     // chunk's part of every operand index folded into the operand's offset
     S.ustep.clear();
     for (const uint2& u : S.units) {
       XStep x = S.xsteps[u.x];
-      x.pad = (int32_t)u.y;
+      x.chunk = (int32_t)u.y;
       const SymStep& st = plan.steps[S.steps[u.x]];
       const uint32_t cx = u.y * 64u * (uint32_t)x_epu(st.rank, (int)st.ins.size(), elt);
       for (size_t j = 0; j < st.ins.size(); ++j) {
@@ -1441,7 +1449,20 @@ extern "C" qt_status qt_plan_describe(const qt_plan* plan, char* buf, int64_t ca
            std::to_string(S.steps.size()) + ",\"first_step\":" + std::to_string(S.steps.front()) +
            ",\"levels\":" + std::to_string(S.n_levels) + ",\"lds_bytes\":" + std::to_string(smem) +
            ",\"slots\":" + std::to_string(S.n_slots) + ",\"internal\":" + std::to_string(internal) +
-           ",\"staged\":" + std::to_string(staged) + "}";
+           ",\"staged\":" + std::to_string(staged) + ",\"step_list\":[";
+      // per step, in plan order: [dependency level, rank, summed, per-input [rank within a slice, has_v, leaf]]
+      for (size_t a = 0; a < S.steps.size(); ++a) {
+        const SymStep& st = plan->steps[S.steps[a]];
+        j += std::string(a ? "," : "") + "[" + std::to_string(ws.depth[S.steps[a]]) + "," +
+             std::to_string(st.rank) + "," + std::to_string(st.sum) + ",[";
+        for (size_t q = 0; q < st.ins.size(); ++q) {
+          const SymTensor& T = plan->tensors[st.ins[q].tensor];
+          j += std::string(q ? "," : "") + "[" + std::to_string(T.rank - __builtin_popcount(st.ins[q].smask)) +
+               "," + std::to_string(st.ins[q].has_v) + "," + std::to_string(T.leaf >= 0 ? 1 : 0) + "]";
+        }
+        j += "]]";
+      }
+      j += "]}";
     }
     j += "],\"stream_steps\":[";
     bool first = true;

@@ -300,3 +300,27 @@ def test_product_steps_merged_into_their_producers(lib):
               and any(s["in_has_v"])]
     assert len(merged) >= 2
     assert fused.info().n_steps == plain.info().n_steps - len(products(plain))
+
+
+def test_describe_lists_segment_steps_by_level(lib):
+    """Each LDS segment lists its steps: dependency level, rank, summed flag
+    and per input (rank within a slice, holds v, leaf).  Levels are
+    consistent with the segment's level count, a summed step has an input
+    holding the summed variable (Algorithm 1: a bucket holds the tensors that
+    contain its variable; a merged product's inputs may not), and a step's
+    output rank never exceeds the sum of its inputs' ranks less v."""
+    n, p = 40, 2
+    net = api.Network(N.amplitude_network(n, regular_graph(n, 3, 0), p))
+    sch = net.plan_slicing(4, algo="min_fill")
+    plan = api.Plan(net, sch.order, sch.groups, precision="c64", fold_prefix=True)
+    d = plan.describe()
+    assert d["segments"]
+    for s in d["segments"]:
+        steps = s["step_list"]
+        assert len(steps) == s["steps"]
+        assert max(st[0] for st in steps) == s["levels"] - 1
+        for level, rank, summed, ins in steps:
+            assert 0 <= level < s["levels"] and ins
+            if summed:
+                assert any(hv == 1 for _, hv, _ in ins)
+            assert rank <= sum(r - hv for r, hv, _ in ins)

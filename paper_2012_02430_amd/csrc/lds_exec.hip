@@ -579,15 +579,21 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
     // these loads; the busy ones never issue them.
     const int n_busy = u_end - u_beg < nw ? u_end - u_beg : nw;
     if (wave >= n_busy && L + 1 < X.n_levels) {
+      // the next level's descriptors are consecutive: its lines go round
+      // the idle wavefronts, four loads in flight per wavefront (indices
+      // clamped to the last line rather than branched on)
       const int nb = level_off[L + 1];
       const int ne = level_off[L + 2] < nb + nw ? level_off[L + 2] : nb + nw;
-      uint32_t touch = 0;
-      for (int u = nb + (wave - n_busy); u < ne; u += nw - n_busy) {
-        const uint32_t* d = reinterpret_cast<const uint32_t*>(steps + u);
-#pragma unroll
-        for (int q = 0; q < (int)(sizeof(XStep) / 4); q += 16) touch |= d[q];
+      constexpr int kLines = (int)(sizeof(XStep) / 64);
+      const int idle = nw - n_busy, nl = (ne - nb) * kLines;
+      const uint32_t* d = reinterpret_cast<const uint32_t*>(steps + nb);
+      for (int k = wave - n_busy; k < nl; k += 4 * idle) {
+        const uint32_t w0 = d[16 * k];
+        const uint32_t w1 = d[16 * min(k + idle, nl - 1)];
+        const uint32_t w2 = d[16 * min(k + 2 * idle, nl - 1)];
+        const uint32_t w3 = d[16 * min(k + 3 * idle, nl - 1)];
+        asm volatile("" : : "s"(w0), "s"(w1), "s"(w2), "s"(w3));  // keeps the loads; emits nothing
       }
-      asm volatile("" : : "s"(touch));  // keeps the loads; emits nothing
     }
     __syncthreads();
     if (tracing) trace[L + 1] = wall_clock64();
@@ -822,24 +828,27 @@ __device__ __forceinline__ void x_unit_pts(const XStep& st, uint32_t uy, uint32_
     }
   }
   float m = 0.f;
+  // the product over operands in their order, each scaled operand times its
+  // power of two first (an unscaled one is used as loaded)
+  E t0[EPU], t1[EPU];
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    if (SCALED && slot[j] >= 0) {
+#pragma unroll
+      for (int e = 0; e < EPU; ++e) {
+        a0[e][j] = xscale(a0[e][j], sc[j]);
+        a1[e][j] = xscale(a1[e][j], sc[j]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPU; ++e) {
+      t0[e] = j == 0 ? a0[e][0] : xmul(t0[e], a0[e][j]);
+      t1[e] = j == 0 ? a1[e][0] : xmul(t1[e], a1[e][j]);
+    }
+  }
 #pragma unroll
   for (int e = 0; e < EPU; ++e) {
-    E t0 = a0[e][0], t1 = a1[e][0];
-    if (SCALED) {
-      t0 = xscale(t0, sc[0]);
-      t1 = xscale(t1, sc[0]);
-    }
-#pragma unroll
-    for (int j = 1; j < NIN; ++j) {
-      E x0 = a0[e][j], x1 = a1[e][j];
-      if (SCALED) {
-        x0 = xscale(x0, sc[j]);
-        x1 = xscale(x1, sc[j]);
-      }
-      t0 = xmul(t0, x0);
-      t1 = xmul(t1, x1);
-    }
-    const E res = sum ? xadd(t0, t1) : t0;
+    const E res = sum ? xadd(t0[e], t1[e]) : t0[e];
     const uint32_t x = cx + e * 64u + xl;
     if (valid && x < n) {
       lds[qoff + o_off + x] = res;

@@ -180,6 +180,7 @@ struct XStep {
   int32_t chunk;
   XOp in[kMaxIn];
 };
+static_assert(sizeof(XStep) % 64 == 0, "step descriptors are whole 64-byte lines");
 
 // Work unit of the executor: steps of rank >= kXBigRank are cut into units
 // of kXEpu * 64 outputs (kXEpu per lane), smaller steps into 64-output units

@@ -194,6 +194,30 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
       eacc += exps[slot] + sh;
     }
   }
+  // Inputs that no output bit indexes (the last s.n_uni: gates and factors
+  // on v and slice variables alone) hold the same two values for every
+  // output of the item: their product is formed once, here, and multiplies
+  // the product of the others.
+  E g0 = Cx<E>::one(), g1 = Cx<E>::one();
+  const int nu = s.n_uni;
+#pragma unroll
+  for (int q = 0; q < kMaxIn - NIN; ++q) {
+    if (q >= nu) break;
+    const DevIn& in = s.in[NIN + q];
+    const E* blk = reinterpret_cast<const E*>(in.ptr) + (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                   ((int64_t)pext_bits(sid, in.smask) << in.slow);
+    E u0 = blk[0], u1 = blk[in.has_v];
+    if (SCALED && in.exp_base >= 0) {
+      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+      const int sh = scale_shift(maxbits[slot]);
+      const R f = (R)ldexp(1.0, -sh);
+      u0 = cscale(u0, f);
+      u1 = cscale(u1, f);
+      eacc += exps[slot] + sh;
+    }
+    g0 = q == 0 ? u0 : cmul(g0, u0);
+    g1 = q == 0 ? u1 : cmul(g1, u1);
+  }
   if (any_small) __syncthreads();
   E* const out = reinterpret_cast<E*>(s.out) + ((int64_t)item << s.r);
   float mx = 0.f;
@@ -229,24 +253,34 @@ __global__ __launch_bounds__(kWG) void k_step_big(const DevStep s, int* __restri
       }
     }
     const __amdgpu_buffer_rsrc_t ro = rsrc_of(out + ((int64_t)tile << kLgTile));
+    // product over the inputs in their order (a scaled input times its power
+    // of two first; an unscaled one as loaded), then the uniform factor
+    E t0[kEPT], t1[kEPT];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) {
+      if (SCALED && s.in[j].exp_base >= 0) {
+#pragma unroll
+        for (int e = 0; e < kEPT; ++e) {
+          a0[e][j] = cscale(a0[e][j], scale[j]);
+          a1[e][j] = cscale(a1[e][j], scale[j]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < kEPT; ++e) {
+        t0[e] = j == 0 ? a0[e][0] : cmul(t0[e], a0[e][j]);
+        t1[e] = j == 0 ? a1[e][0] : cmul(t1[e], a1[e][j]);
+      }
+    }
+    if (nu) {
+#pragma unroll
+      for (int e = 0; e < kEPT; ++e) {
+        t0[e] = cmul(t0[e], g0);
+        t1[e] = cmul(t1[e], g1);
+      }
+    }
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
-      E t0 = a0[e][0], t1 = a1[e][0];
-      if (SCALED) {
-        t0 = cscale(t0, scale[0]);
-        t1 = cscale(t1, scale[0]);
-      }
-#pragma unroll
-      for (int j = 1; j < NIN; ++j) {
-        E x0 = a0[e][j], x1 = a1[e][j];
-        if (SCALED) {
-          x0 = cscale(x0, scale[j]);
-          x1 = cscale(x1, scale[j]);
-        }
-        t0 = cmul(t0, x0);
-        t1 = cmul(t1, x1);
-      }
-      const E res = s.sum ? cadd(t0, t1) : t0;
+      const E res = s.sum ? cadd(t0[e], t1[e]) : t0[e];
       Cx<E>::bstore(ro, (((uint32_t)e << 8) | tid) * (uint32_t)sizeof(E), res);
       if (SCALED) mx = fmaxf(mx, abs_max(res));
     }
@@ -511,8 +545,28 @@ void launch_step_t(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_ele
 }
 
 template <typename E, bool SCALED>
-void launch_step_n(const DevStep& s, int* exps, uint32_t* maxbits, int64_t n_elems, hipStream_t stream) {
-  switch (s.n_in) {
+void launch_step_n(const DevStep& s0, int* exps, uint32_t* maxbits, int64_t n_elems, hipStream_t stream) {
+  DevStep s = s0;
+  int nin = s.n_in;
+  if (s.r >= kLgTile) {
+    // inputs that no output bit indexes go last; the big kernel multiplies
+    // their product in once per item (and stages only the others)
+    DevIn tmp[kMaxIn];
+    int k = 0;
+    for (int j = 0; j < s.n_in; ++j)
+      if (s.in[j].nruns != 0) tmp[k++] = s.in[j];
+    const int nn = k;
+    for (int j = 0; j < s.n_in; ++j)
+      if (s.in[j].nruns == 0) tmp[k++] = s.in[j];
+    if (nn > 0 && nn < s.n_in) {
+      for (int j = 0; j < s.n_in; ++j) s.in[j] = tmp[j];
+      for (int j = 0; j < nn; ++j)
+        if (s.in[j].small_n > x_small_cap(nn)) s.in[j].small_n = 0;
+      s.n_uni = s.n_in - nn;
+      nin = nn;
+    }
+  }
+  switch (nin) {
     case 1: launch_step_t<E, SCALED, 1>(s, exps, maxbits, n_elems, stream); break;
     case 2: launch_step_t<E, SCALED, 2>(s, exps, maxbits, n_elems, stream); break;
     case 3: launch_step_t<E, SCALED, 3>(s, exps, maxbits, n_elems, stream); break;

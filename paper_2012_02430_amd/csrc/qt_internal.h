@@ -114,6 +114,8 @@ struct DevStep {
   int32_t out_exp_pt;
   int32_t out_exp_sb;
   int32_t lg_tpb;        // BIG mode: log2(consecutive tiles of one item per workgroup)
+  int32_t n_uni;         // BIG mode: the last n_uni inputs are read by no output bit (set at launch)
+  int32_t pad;
   DevIn in[kMaxIn];
 };
 

@@ -94,11 +94,14 @@ struct DevIn {
   int32_t small_n;
   int32_t pad;
 };
-// Staging capacity per input, as measured on the 210-qubit plan: larger
-// static LDS slowed its three- and four-input steps (whose other inputs are
-// larger) and helped its five-input step, which carries a merged factor.
+// Staging capacity per input, by the count of inputs the kernel indexes
+// (inputs read by no output bit are not staged), as measured on the
+// 210-qubit plan: 1024 elements let its three-operand step (a merged
+// factor and a rank-10 input beside a large one) read both small inputs from
+// LDS; larger static LDS for two operands cost occupancy on its two-operand
+// steps.
 __host__ __device__ constexpr int x_small_cap(int n_in) {
-  return n_in <= 2 ? 512 : (n_in <= 4 ? 128 : (n_in == 5 ? 512 : 64));
+  return n_in <= 2 ? 512 : (n_in == 3 ? 1024 : (n_in == 4 ? 128 : (n_in == 5 ? 512 : 64)));
 }
 
 struct DevStep {

@@ -369,7 +369,7 @@ bool build_in(const qt_plan& plan, const qt_plan::Workspace& ws, int t, uint32_t
   d.slow = slow;
   d.has_v = has_v;
   const int block_rank = st.rank - __builtin_popcount(smask);
-  d.small_n = block_rank <= 9 ? (1 << block_rank) : 0;  // capped per step by x_small_cap
+  d.small_n = block_rank <= 10 ? (1 << block_rank) : 0;  // capped per step by x_small_cap
   if (!make_runs(mask, kMaxRuns, d.run_lo, d.run_len, d.run_dst, d.nruns)) return false;
   // tile part: the bits of x from 10 up, as runs over the tile index
   constexpr int kLgTile = 10;
@@ -1011,8 +1011,17 @@ qt_status layout_workspace(qt_plan& plan, qt_plan::Workspace& ws, int np, int64_
           return fail(QT_EPLAN, "internal: streaming step reads an LDS tensor");
         if (!build_in(plan, ws, si.tensor, si.mask, si.has_v, si.smask, si.slow, elt, d.in[j]))
           return fail(QT_EUNSUPPORTED, "input index map has more than 16 runs of bits");
-        if (d.in[j].small_n > x_small_cap(d.n_in)) d.in[j].small_n = 0;
       }
+      // staging cap by the count of inputs the kernel indexes: a large
+      // step's inputs read by no output bit are folded in once per item
+      int n_idx = d.n_in;
+      if (st.rank >= 10) {
+        n_idx = 0;
+        for (int j = 0; j < d.n_in; ++j) n_idx += d.in[j].nruns != 0;
+        if (n_idx == 0) n_idx = d.n_in;
+      }
+      for (int j = 0; j < d.n_in; ++j)
+        if (d.in[j].small_n > x_small_cap(n_idx)) d.in[j].small_n = 0;
       ws.steps.push_back(d);
     }
     ws.finals.clear();

@@ -31,7 +31,7 @@ PLAN_MAX_RANK = (10, 12, 14, 16)
 STEP_TILES = (1, 2, 4, 8, 16)
 GEMM_TILES = (1, 2, 4, 8, 16, 32)
 MULTI_WAVES = (1, 2, 4, 8)
-MULTI_LDS_CAPS = (4096, 8192, 12288, 16384, 24576, 49152, 163840)
+MULTI_LDS_CAPS = (4096, 8192, 12288, 16384, 24576, 32768, 49152, 65536, 163840)
 GEMM_MIN_RANKS = (8, 10, 12, 14, 16)
 
 
@@ -68,24 +68,27 @@ def _arch() -> str:
 
 
 def _time_ms(fn, repeats: int) -> float:
-    """Median over `repeats` timed calls (HIP events on torch's current stream), after two untimed calls
-    (the first may build the call's device state)."""
+    """Milliseconds per call in steady state: the median over three runs of `repeats` back-to-back calls
+    (HIP events on torch's current stream around each run), after two untimed calls (the first may build
+    the call's device state).  Back-to-back calls are how the work is used; a call timed alone after an
+    idle GPU can rank launch shapes differently."""
     import torch
 
     fn()
     fn()
     torch.cuda.synchronize()
     times = []
-    for _ in range(repeats):
+    for _ in range(3):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        fn()
+        for _ in range(repeats):
+            fn()
         b.record()
         b.synchronize()
-        times.append(a.elapsed_time(b))
+        times.append(a.elapsed_time(b) / repeats)
     times.sort()
-    return times[len(times) // 2]
+    return times[1]
 
 
 def _plan_caller(plan, n_points):

@@ -57,6 +57,15 @@ def source_sha1(files):
     return h.hexdigest()
 
 
+def lds_schedule(plan):
+    """The launch shape of a plan's LDS executor segments, as the profiles record it: wavefronts per
+    workgroup, then per segment its steps, dependency levels and LDS bytes (tunings that give the same
+    schedule run the same launches)."""
+    d = plan.describe()
+    return f"{plan.get_tuning()['lds_waves']}w:" + ",".join(
+        f"{s['steps']}s{s['levels']}l{s['lds_bytes']}b" for s in d["segments"])
+
+
 def measured_traffic(profile, files, **match):
     """HBM bytes per launch from a committed FETCH_SIZE/WRITE_SIZE summary, while the kernel sources (and
     the fields in `match`) are those the counters were taken with; else None."""
@@ -310,7 +319,7 @@ def c2_section(args):
     graph_value = steps / (time.perf_counter() - t0)
     tf = lds_flops / (lds_ms * 1e-3) / 1e12
     traffic = measured_traffic("lds_exec_qaoa_n60_p2_256slices.md", ["lds_exec.hip", "qt_internal.h"],
-                               tuning=f"{tuning['lds_waves']}/{tuning['lds_max_rank']}")
+                               schedule=lds_schedule(plan))
     log(f"n=60 amplitude: {value:.0f} amplitudes/s, k_lds_exec {1e3 * lds_ms:.1f} us ({tf:.2f} TFLOP/s), "
         f"graph {graph_value:.0f}/s, plain c128 {1 / el_p:.1f}/s, rel err {err:.1e}")
     return {

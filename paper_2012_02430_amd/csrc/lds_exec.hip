@@ -250,11 +250,13 @@ __device__ __forceinline__ void x_load_pairs(const E* __restrict__ lds, const ui
   }
 }
 
-// PRE: read the unit's descriptor fields, scale slots and maps in phases,
-// each one batch of loads (a few round trips per unit instead of one per
-// field), else read each field where it is used (kernels short of
-// registers).  FOLDED: the descriptor is the unit's own copy, with the
-// chunk's part of each operand index already in lds_off.
+// PRE: read the unit's descriptor words in one batch held in scalar
+// registers, then its scale slots and operands (a few round trips per unit
+// instead of one per field), else read each field where it is used (kernels
+// short of registers).  FOLDED: the descriptor is the unit's own copy, with
+// the chunk's part of each operand index already in lds_off.  PAIRS: the
+// step is flagged out.pairs (every operand holds v at an even base), and
+// each (v = 0, v = 1) pair is one aligned read.
 template <typename E, bool SCALED, int NIN, int EPU, bool PRE = true, bool FOLDED = false, bool PAIRS = false>
 __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XCtx& c, E* __restrict__ lds,
                                        uint32_t* __restrict__ smax, int* __restrict__ sexp, int* __restrict__ gexps,

@@ -237,7 +237,11 @@ def test_streaming_tile_groups_bitwise(precision, monkeypatch):
     for lg in ("0", "2", "4"):
         monkeypatch.setenv("QT_STEP_LG_TILES", lg)
         net, plan = build(n, p, edges, k=k, precision=precision)
-        assert sum(s["rank"] >= 14 for s in plan.describe()["stream_steps"]) >= 4
+        st = plan.describe()["stream_steps"]
+        assert sum(s["rank"] >= 14 for s in st) >= 4
+        # large steps with inputs indexed by no output bit (held on v and
+        # slice variables only), which the kernel multiplies in once per item
+        assert any(s["rank"] >= 10 and any(r == hv for r, hv in zip(s["in_ranks"], s["in_has_v"])) for s in st)
         res.append(plan.contract_batch(g, b, per_slice=True)[1])
     assert all(np.array_equal(res[0], r) for r in res[1:])
     for i in range(2):

@@ -360,14 +360,25 @@ __global__ __launch_bounds__(kWG) void k_step_small(const DevStep s, int* __rest
 // type (Section III-A conventions; see qtensor_hip.h for each kind).
 template <typename E>
 __global__ void k_leaves(const DevLeaf* __restrict__ leaves, int n_leaves, int leaf_block,
-                         const double* __restrict__ dense, const double* __restrict__ params, int p,
+                         const double* __restrict__ dense, double* __restrict__ params,
+                         const double* __restrict__ gammas, const double* __restrict__ betas, int p,
                          int n_points, E* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // parameters given in device memory ([points][p] each): read from there,
+  // and laid out as [points][2p] (gammas, then betas) for the later launches
+  if (gammas) {
+    const int64_t n2 = (int64_t)n_points * 2 * p;
+    for (int64_t i = t; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t q = i / (2 * p), k = i - q * 2 * p;
+      params[i] = k < p ? gammas[q * p + k] : betas[q * p + k - p];
+    }
+  }
   if (t >= (int64_t)n_leaves * n_points) return;
   const int pt = (int)(t / n_leaves);
   const DevLeaf L = leaves[t % n_leaves];
   E* o = out + (int64_t)pt * leaf_block + L.off;
-  const double* prm = params + (int64_t)pt * 2 * p;
+  const double* const gp = gammas ? gammas + (int64_t)pt * p : params + (int64_t)pt * 2 * p;
+  const double* const bp = gammas ? betas + (int64_t)pt * p : params + (int64_t)pt * 2 * p + p;
   switch (L.kind) {
     case QT_T_VEC_PLUS:
       o[0] = Cx<E>::from(1.0, 0.0);
@@ -380,7 +391,7 @@ __global__ void k_leaves(const DevLeaf* __restrict__ leaves, int n_leaves, int l
     case QT_T_ZZ:
     case QT_T_ZZ_DAG: {
       double sn, cs;
-      sincos(prm[L.layer - 1], &sn, &cs);
+      sincos(gp[L.layer - 1], &sn, &cs);
       const double im = L.kind == QT_T_ZZ ? -sn : sn;
       o[0] = Cx<E>::from(1.0, 0.0);
       o[1] = Cx<E>::from(cs, im);
@@ -391,7 +402,7 @@ __global__ void k_leaves(const DevLeaf* __restrict__ leaves, int n_leaves, int l
     case QT_T_RX:
     case QT_T_RX_DAG: {
       double sn, cs;
-      sincos(prm[p + L.layer - 1], &sn, &cs);
+      sincos(bp[L.layer - 1], &sn, &cs);
       const double im = L.kind == QT_T_RX ? -sn : sn;
       o[0] = Cx<E>::from(cs, 0.0);
       o[1] = Cx<E>::from(0.0, im);
@@ -512,17 +523,17 @@ __global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ pe
 }  // namespace
 
 hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, const double* dense,
-                         const double* params, int p, int n_points, void* out, bool c128,
-                         hipStream_t stream) {
-  const int64_t n = (int64_t)n_leaves * n_points;
+                         double* params, const double* gammas, const double* betas, int p, int n_points,
+                         void* out, bool c128, hipStream_t stream) {
+  const int64_t n = std::max<int64_t>((int64_t)n_leaves * n_points, gammas ? (int64_t)n_points * 2 * p : 0);
   if (n == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (c128)
-    hipLaunchKernelGGL(k_leaves<double2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params, p,
-                       n_points, reinterpret_cast<double2*>(out));
+    hipLaunchKernelGGL(k_leaves<double2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params,
+                       gammas, betas, p, n_points, reinterpret_cast<double2*>(out));
   else
-    hipLaunchKernelGGL(k_leaves<float2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params, p,
-                       n_points, reinterpret_cast<float2*>(out));
+    hipLaunchKernelGGL(k_leaves<float2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params,
+                       gammas, betas, p, n_points, reinterpret_cast<float2*>(out));
   return hipGetLastError();
 }
 

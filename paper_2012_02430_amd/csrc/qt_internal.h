@@ -534,9 +534,12 @@ struct qt_plan {
 namespace qt {
 
 // kernels.hip
+// gammas/betas: the points' parameters in device memory ([points][p] each),
+// which the launch also lays out in `params` ([points][2p]); null: `params`
+// already holds them.
 hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, const double* dense,
-                         const double* params, int p, int n_points, void* out, bool c128,
-                         hipStream_t stream);
+                         double* params, const double* gammas, const double* betas, int p, int n_points,
+                         void* out, bool c128, hipStream_t stream);
 // Launches one bucket step; returns the kernel class used (QT_KCLASS_*)
 // through *kclass.
 hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits,

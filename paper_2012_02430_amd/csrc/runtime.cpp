@@ -1078,17 +1078,22 @@ qt_status ensure_workspace(qt_plan& plan, int np, int64_t n_range) {
 // the sums in ws.sums ([np][2^a][3]).
 // The workspace `ws` is laid out for np points and the slice range.
 qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const double* gammas, const double* betas,
-                      int64_t begin, int64_t end, int64_t stop, hipStream_t stream) {
+                      int64_t begin, int64_t end, int64_t stop, hipStream_t stream, double* sums_out = nullptr) {
   const bool c128 = plan.precision == QT_C128;
   const bool scaled = plan.precision != QT_C128;
   const int k = (int)plan.slice_vars.size();
   const int64_t n_range = end - begin;
   int launches = 0;
-  QT_TRY(upload_params_to(ws.params, np, plan.net.p, gammas, betas, stream));
+  // parameters in device memory go to the leaf launch, which lays them out
+  // for the others; host parameters are uploaded first
+  const int pp = plan.net.p;
+  const bool dev_params = pp > 0 && !plan.dev_leaves.empty() && is_device_ptr(gammas) && is_device_ptr(betas);
+  if (!dev_params) QT_TRY(upload_params_to(ws.params, np, pp, gammas, betas, stream));
   const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
   QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
-    return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params, plan.net.p,
-                         np, ws.leaves, c128, stream);
+    return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params,
+                         dev_params ? gammas : nullptr, dev_params ? betas : nullptr, pp, np, ws.leaves, c128,
+                         stream);
   }));
   ++launches;
   if (scaled && ws.exp1_base) {
@@ -1168,8 +1173,10 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
       ++launches;
     }
   }
+  // the sums into the caller's device array when given (no copy after)
+  double* const sums = sums_out ? sums_out : ws.sums;
   QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
-                     [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, ws.sums, stream); }));
+                     [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, sums, stream); }));
   ++launches;
   if (ws.trace_on) {
     QT_HIP_CHECK(hipStreamSynchronize(stream));
@@ -1202,9 +1209,9 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
 }
 
 qt_status run_plan(qt_plan& plan, int np, const double* gammas, const double* betas, int64_t begin, int64_t end,
-                   int64_t stop, hipStream_t stream) {
+                   int64_t stop, hipStream_t stream, double* sums_out = nullptr) {
   QT_TRY(ensure_workspace(plan, np, end - begin));
-  return run_plan_ws(plan, *plan.ws, np, gammas, betas, begin, end, stop, stream);
+  return run_plan_ws(plan, *plan.ws, np, gammas, betas, begin, end, stop, stream, sums_out);
 }
 
 }  // namespace
@@ -1371,9 +1378,13 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
         (p == 0 || (is_device_ptr(gammas) && is_device_ptr(betas))) && is_device_ptr(out) &&
         (!per_slice_out || is_device_ptr(per_slice_out)))
       return contract_graph(*plans[0], n_points, gammas, betas, slice_begin, slice_end, out, per_slice_out, stream);
+    // results in device memory are written by the sum launch itself
+    const bool dev_out = !injected && is_device_ptr(out);
     for (int i = 0; i < n_plans; ++i) {
       qt_plan& plan = *plans[i];
-      if (stop > slice_begin) QT_TRY(run_plan(plan, n_points, gammas, betas, slice_begin, slice_end, stop, stream));
+      double* const direct = dev_out ? reinterpret_cast<double*>(out + (size_t)i * rows) : nullptr;
+      if (stop > slice_begin)
+        QT_TRY(run_plan(plan, n_points, gammas, betas, slice_begin, slice_end, stop, stream, direct));
       else QT_TRY(ensure_workspace(plan, n_points, n_range));
       auto& ws = *plan.ws;
       if (per_slice_out && stop > slice_begin) {
@@ -1381,7 +1392,7 @@ extern "C" qt_status qt_contract_batch(qt_plan* const* plans, int32_t n_plans, i
         const size_t width = (size_t)(stop - slice_begin) * 3 * sizeof(double);
         QT_TRY(copy_2d(per_slice_out + (size_t)i * rows * n_range * 3, row, ws.per_slice, row, width, rows, stream));
       }
-      if (!injected) {
+      if (!injected && !(dev_out && stop > slice_begin)) {
         const size_t bytes = (size_t)rows * sizeof(qt_amp);
         QT_TRY(copy_2d(out + (size_t)i * rows, bytes, ws.sums, bytes, bytes, 1, stream));
       }

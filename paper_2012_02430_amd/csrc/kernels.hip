@@ -437,7 +437,7 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 template <typename E, bool SCALED>
 __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_points, int64_t n_items,
                         const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
-                        double* __restrict__ per_slice, int64_t slice_end) {
+                        double* __restrict__ per_slice, int64_t slice_end, double* __restrict__ sums) {
   const int64_t tj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tj >= (n_items << f.n_open)) return;
   const uint32_t oj = (uint32_t)(tj & ((1ll << f.n_open) - 1));  // open output index
@@ -468,6 +468,15 @@ __global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_p
   o[0] = re;
   o[1] = im;
   o[2] = ex;
+  if (sums) {
+    // a range of one slice: its sum, as k_slice_sum forms it (a zero value
+    // reported with exponent 0)
+    const bool nz = re != 0.0 || im != 0.0;
+    double* s = sums + 3 * (((int64_t)pt << f.n_open) + oj);
+    s[0] = nz ? 0.0 + re : 0.0;
+    s[1] = nz ? 0.0 + im : 0.0;
+    s[2] = nz ? ex : 0.0;
+  }
 }
 
 // Deterministic FP64 sum over slices (Algorithm 1's final reduction): common
@@ -614,19 +623,20 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s
 
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items, bool c128,
                         bool scaled, const int* exps, const uint32_t* maxbits, double* per_slice,
-                        int64_t slice_end, hipStream_t stream) {
+                        int64_t slice_end, hipStream_t stream, double* sums) {
+  if (sums && f.n_range != 1) return hipErrorInvalidValue;
   const int64_t n = n_items << f.n_open;
   if (n > 0x7fffffffll * 256) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (c128)
     hipLaunchKernelGGL((k_final<double2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end);
+                       maxbits, per_slice, slice_end, sums);
   else if (scaled)
     hipLaunchKernelGGL((k_final<float2, true>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end);
+                       maxbits, per_slice, slice_end, sums);
   else
     hipLaunchKernelGGL((k_final<float2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end);
+                       maxbits, per_slice, slice_end, sums);
   return hipGetLastError();
 }
 

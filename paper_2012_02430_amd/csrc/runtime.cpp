@@ -1141,6 +1141,10 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
     });
   };
   for (const auto& op : ws.prefix_ops) QT_HIP_CHECK(run_op(op, 0));
+  // the sums go into the caller's device array when given (no copy after);
+  // a range of one slice has them formed by the final launch itself
+  double* const sums = sums_out ? sums_out : ws.sums;
+  double* const fold = n_range == 1 ? sums : nullptr;
   DevFinal f{};
   f.n_factors = (int)ws.finals.size();
   f.n_open = (int)plan.open_vars.size();
@@ -1151,7 +1155,7 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
     f.lg_nsb = 0;
     f.chunk_base = 0;
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
-      return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream);
+      return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream, fold);
     }));
     ++launches;
   } else {
@@ -1168,16 +1172,16 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
       f.chunk_base = cb;
       QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
         return launch_final(f, ws.dfinal, np, (int64_t)np * C, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, stop,
-                            stream);
+                            stream, fold);
       }));
       ++launches;
     }
   }
-  // the sums into the caller's device array when given (no copy after)
-  double* const sums = sums_out ? sums_out : ws.sums;
-  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
-                     [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, sums, stream); }));
-  ++launches;
+  if (!fold) {
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
+                       [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, sums, stream); }));
+    ++launches;
+  }
   if (ws.trace_on) {
     QT_HIP_CHECK(hipStreamSynchronize(stream));
     int max_levels = 1;

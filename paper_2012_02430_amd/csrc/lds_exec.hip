@@ -438,7 +438,7 @@ __device__ __forceinline__ void x_unit(const XStep& st, uint32_t chunk, const XC
 // Gate table entry t of the workgroup's point (layout: x_gate_off), FP64
 // trigonometry rounded to the element type (Section III-A conventions).
 template <typename E>
-__device__ __forceinline__ E x_gate(int t, const double* prm, int p) {
+__device__ __forceinline__ E x_gate2(int t, const double* gam, const double* bet) {
   using R = typename XReal<E>::R;
   E v;
   double re = 0.0, im = 0.0;
@@ -454,11 +454,11 @@ __device__ __forceinline__ E x_gate(int t, const double* prm, int p) {
     double sn, cs;
     const bool diag = i == 0 || i == 3;
     if (g < 2) {
-      sincos(prm[k], &sn, &cs);
+      sincos(gam[k], &sn, &cs);
       re = diag ? 1.0 : cs;
       im = diag ? 0.0 : (g == 0 ? -sn : sn);
     } else {
-      sincos(prm[p + k], &sn, &cs);
+      sincos(bet[k], &sn, &cs);
       re = diag ? cs : 0.0;
       im = diag ? 0.0 : (g == 2 ? -sn : sn);
     }
@@ -466,6 +466,10 @@ __device__ __forceinline__ E x_gate(int t, const double* prm, int p) {
   v.x = (R)re;
   v.y = (R)im;
   return v;
+}
+template <typename E>
+__device__ __forceinline__ E x_gate(int t, const double* prm, int p) {
+  return x_gate2<E>(t, prm, prm + p);
 }
 
 // The step, unit, level and copy tables are separate read-only, non-aliasing
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(kXMaxThreads) void k_lds_exec(const XLaunch X, cons
     lds[tid].y = 0;
   }
   for (int t = tid; t < x_gate_elems(X.p); t += blockDim.x)
-    lds[kXGate + t] = x_gate<E>(t, X.params + (int64_t)c.pt * 2 * X.p, X.p);
+    lds[kXGate + t] = x_gate2<E>(t, X.gam + (int64_t)c.pt * X.pstride, X.bet + (int64_t)c.pt * X.pstride);
   // stage the segment's external inputs (with their scale slots)
   for (int e = wave; e < X.n_copies; e += nw) {
     const XCopy& cp = copies[e];

@@ -251,7 +251,9 @@ struct XLaunch {
   const uint2* units;      // unused by the executor (kept for the host)
   const int32_t* level_off;  // n_levels + 1 offsets into units
   const XCopy* copies;     // inputs staged into LDS at the start
-  const double* params;    // [points][2p]: gammas then betas
+  const double* gam;       // point q's gammas at gam + q * pstride, its betas at bet + q * pstride
+  const double* bet;
+  int32_t pstride;
   int32_t n_levels;
   int32_t lg_nsb;
   int64_t chunk_base;

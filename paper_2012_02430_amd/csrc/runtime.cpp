@@ -167,6 +167,7 @@ struct qt_plan::Workspace {
   // per tensor its LDS offset/slot (-1: global) and global arena offset
   bool planned = false;
   std::vector<int> seg_of, depth;
+  bool leaves_read = true;  // some launch reads the leaf tensors from global memory
   std::vector<int64_t> lds_off;
   std::vector<int> lds_slot;
   std::vector<int> staged_in;  // segment that stages the tensor into LDS, -1: none
@@ -561,6 +562,19 @@ qt_status plan_schedule(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
   ws.unit_off.assign(ntens, 0);
   ws.arena0_units = place_intervals(iv0, ws.unit_off);
   ws.arena1_units = place_intervals(iv1, ws.unit_off);
+  // leaves read from global memory: by streaming steps and GEMMs, staged
+  // into a segment (all but the gate kinds, whose tables a segment builds
+  // itself), or as closing factors
+  ws.leaves_read = false;
+  for (int i = 0; i < nsteps; ++i)
+    for (const SymIn& in : plan.steps[i].ins) {
+      const SymTensor& T = plan.tensors[in.tensor];
+      if (T.leaf < 0) continue;
+      if (ws.seg_of[i] < 0 || x_gate_off(plan.net.leaves[T.leaf].kind, plan.net.leaves[T.leaf].layer) < 0)
+        ws.leaves_read = true;
+    }
+  for (int t : plan.finals)
+    if (plan.tensors[t].leaf >= 0) ws.leaves_read = true;
   ws.planned = true;
   if (env_int("QT_DEBUG_SCHEDULE", 0)) {
     for (size_t si = 0; si < ws.segs.size(); ++si) {
@@ -741,7 +755,9 @@ qt_status build_segment_tables(qt_plan& plan, qt_plan::Workspace& ws, int elt) {
     S.launch.level_off = (const int32_t*)put(S.level_off.data(), S.level_off.size() * sizeof(int32_t));
     S.launch.copies = (const XCopy*)put(S.copies.data(), S.copies.size() * sizeof(XCopy));
     S.launch.n_copies = (int)S.copies.size();
-    S.launch.params = ws.params;
+    S.launch.gam = ws.params;
+    S.launch.bet = ws.params + plan.net.p;
+    S.launch.pstride = 2 * plan.net.p;
     S.launch.p = plan.net.p;
     S.launch.n_levels = S.n_levels;
     S.launch.n_slots = S.n_slots;
@@ -1087,15 +1103,21 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
   // parameters in device memory go to the leaf launch, which lays them out
   // for the others; host parameters are uploaded first
   const int pp = plan.net.p;
-  const bool dev_params = pp > 0 && !plan.dev_leaves.empty() && is_device_ptr(gammas) && is_device_ptr(betas);
+  const bool dev_params = pp > 0 && is_device_ptr(gammas) && is_device_ptr(betas);
+  // no launch reads the leaves from global memory: with device parameters
+  // the segments read them where they are, and the leaf launch is skipped
+  const bool direct = dev_params && !ws.leaves_read;
   if (!dev_params) QT_TRY(upload_params_to(ws.params, np, pp, gammas, betas, stream));
   const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
-  QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
-    return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params,
-                         dev_params ? gammas : nullptr, dev_params ? betas : nullptr, pp, np, ws.leaves, c128,
-                         stream);
-  }));
-  ++launches;
+  if (!direct) {
+    // leaves, and the device parameters laid out for the segments
+    QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
+      return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params,
+                           dev_params ? gammas : nullptr, dev_params ? betas : nullptr, pp, np, ws.leaves, c128,
+                           stream);
+    }));
+    ++launches;
+  }
   if (scaled && ws.exp1_base) {
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
                        [&] { return launch_fill_u32(ws.maxbits, ws.exp1_base, 0u, stream); }));
@@ -1130,6 +1152,11 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
     auto& S = ws.segs[op.seg];
     XLaunch x = S.launch;
     x.chunk_base = cb;
+    if (direct) {
+      x.gam = gammas;
+      x.bet = betas;
+      x.pstride = pp;
+    }
     int max_levels = 1;
     for (auto& T : ws.segs) max_levels = std::max(max_levels, T.n_levels + 1);
     x.trace = ws.trace_on ? ws.trace_buf + (int64_t)op.seg * max_levels : nullptr;

@@ -399,3 +399,38 @@ def test_c4_slice_groups_per_slice_parity():
         err = np.abs(got[0] - want[0]).max() / np.abs(want[0]).max()
         print(f"n=210 two groups, slices [{lo},{hi}): max rel err {err:.2e}", flush=True)
         assert err < TOL["c64"], (lo, err)
+
+
+@pytest.mark.parametrize("case", ["unsliced_c128", "sliced_fold_c64", "sliced_c64", "streaming_c64"])
+def test_device_parameters_match_host_parameters(case, monkeypatch):
+    """Parameters and results in device memory take their own route (the
+    segments read device parameters where they are, or the leaf launch lays
+    them out; the final or sum launch writes the results in place); every
+    value equals the host-array route bit for bit, at several points."""
+    import torch
+
+    if case == "streaming_c64":
+        monkeypatch.setenv("QT_LDS_MAX_RANK", "4")  # leaves read by streaming steps
+    n, p = (16, 1) if case == "unsliced_c128" else (24, 2)
+    edges = regular_graph(n, 3, 3)
+    net = api.Network(N.amplitude_network(n, edges, p, random_bitstring(n, 4)))
+    if case == "unsliced_c128":
+        order, _ = net.order_greedy("min_fill")
+        plan = api.Plan(net, order, precision="c128")
+    else:
+        sch = net.plan_slicing(3, algo="min_fill")
+        plan = api.Plan(net, sch.order, sch.groups, precision="c64", fold_prefix=case == "sliced_fold_c64")
+    npt = 3
+    gs, bs = qaoa_params(p, npt, seed=11)
+    want, want_per = plan.contract_batch(gs, bs, per_slice=True)
+    g = torch.tensor(np.asarray(gs).reshape(npt, p), dtype=torch.float64, device="cuda")
+    b = torch.tensor(np.asarray(bs).reshape(npt, p), dtype=torch.float64, device="cuda")
+    out = torch.zeros(npt, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(npt, plan.n_slices, 3, dtype=torch.float64, device="cuda")
+    plan.contract_device(g, b, out, per)
+    torch.cuda.synchronize()
+    o, ps = out.cpu().numpy(), per.cpu().numpy()
+    got = np.array([api.amp_to_complex(*o[i]) for i in range(npt)])
+    got_per = np.vectorize(api.amp_to_complex)(ps[..., 0], ps[..., 1], ps[..., 2])
+    assert np.array_equal(got, want)
+    assert np.array_equal(got_per, want_per)

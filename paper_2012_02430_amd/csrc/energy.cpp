@@ -850,7 +850,9 @@ qt_status build_job(qt_plan* const* plans, int n, int np, bool grad, int64_t lds
   m.revs = (const XRev*)(base + at[6]);
   m.rec_off = (const int32_t*)(base + at[7]);
   m.items = (const int2*)(base + at[8]);
-  m.params = job.params;
+  m.gam = job.params;
+  m.bet = job.params + p;
+  m.pstride = 2 * p;
   m.out = job.out;
   m.gout = job.gout;
   m.n_points = np;
@@ -961,25 +963,43 @@ qt_status energy_grad(qt_plan* const* lightcones, int32_t n_edges, const double*
     // over edges and the results out.
     auto enqueue = [&](hipStream_t s) -> qt_status {
       EnergyJob& J = *job;
-      QT_TRY(upload_params_to(J.params, n_points, p, gammas, betas, s));
-      if (grad) QT_HIP_CHECK(launch_lds_grad(J.multi, J.n_blocks, J.smem, waves, s));
-      else QT_HIP_CHECK(launch_lds_multi(J.multi, J.n_blocks, J.smem, waves, J.wide, !J.wide, s));
+      // parameters in device memory are read where they are; host ones go
+      // to the job's buffer ([points][2p])
+      XMulti m = J.multi;
+      if (p > 0 && is_device_ptr(gammas) && is_device_ptr(betas)) {
+        m.gam = gammas;
+        m.bet = betas;
+        m.pstride = p;
+      } else {
+        QT_TRY(upload_params_to(J.params, n_points, p, gammas, betas, s));
+      }
+      if (grad) QT_HIP_CHECK(launch_lds_grad(m, J.n_blocks, J.smem, waves, s));
+      else QT_HIP_CHECK(launch_lds_multi(m, J.n_blocks, J.smem, waves, J.wide, !J.wide, s));
       for (int e : J.big) {
         const double* sums = nullptr;
         QT_TRY(run_plan_points(*lightcones[e], n_points, gammas, betas, s, &sums));
         QT_HIP_CHECK(hipMemcpy2DAsync(J.out + 3 * e, (size_t)n_edges * 3 * sizeof(double), sums, 3 * sizeof(double),
                                       3 * sizeof(double), n_points, hipMemcpyDeviceToDevice, s));
       }
+      // device weights and results are read and written where they are
       const double* w = nullptr;
-      if (weights) {
+      if (weights && is_device_ptr(weights)) {
+        w = weights;
+      } else if (weights) {
         const size_t wb = sizeof(double) * n_edges;
         QT_TRY(copy_2d(J.weights, wb, weights, wb, wb, 1, s));
         w = J.weights;
       }
       QT_HIP_CHECK(launch_slice_sum(J.out, n_points, n_edges, J.sums, s, w));
-      QT_HIP_CHECK(launch_amp_to_real(J.sums, n_points, J.reals, s));
-      QT_TRY(copy_out(energy, J.reals, n_points, s));
-      if (per_edge) {
+      if (energy && is_device_ptr(energy)) {
+        QT_HIP_CHECK(launch_amp_to_real(J.sums, n_points, energy, s));
+      } else {
+        QT_HIP_CHECK(launch_amp_to_real(J.sums, n_points, J.reals, s));
+        QT_TRY(copy_out(energy, J.reals, n_points, s));
+      }
+      if (per_edge && is_device_ptr(per_edge)) {
+        QT_HIP_CHECK(launch_amp_to_real(J.out, (int64_t)n_points * n_edges, per_edge, s));
+      } else if (per_edge) {
         QT_HIP_CHECK(launch_amp_to_real(J.out, (int64_t)n_points * n_edges, J.reals + n_points, s));
         QT_TRY(copy_out(per_edge, J.reals + n_points, (size_t)n_points * n_edges, s));
       }

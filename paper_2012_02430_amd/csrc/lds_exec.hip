@@ -682,7 +682,7 @@ __device__ __forceinline__ void x_multi_item(const XMulti& M, const XProg& P, in
     area[tid].y = 0;
   }
   for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x)
-    area[kXGate + t] = x_gate<E>(t, M.params + (int64_t)c.pt * 2 * M.p, M.p);
+    area[kXGate + t] = x_gate2<E>(t, M.gam + (int64_t)c.pt * M.pstride, M.bet + (int64_t)c.pt * M.pstride);
   x_level_sync<GLOBAL>();
   constexpr int kBig = sizeof(E) == 8 ? kXEpu : kXEpu / 2;
   for (int L = 0; L < P.n_levels; ++L) {
@@ -938,7 +938,7 @@ __device__ __forceinline__ void x_multi_pts(const XMulti& M, const XProg& P, int
       v.y = 0;
     } else {
       const uint32_t pq = pt0 + min(q, npts - 1u);
-      v = x_gate<E>((int)(t - kXGate), M.params + (int64_t)pq * 2 * M.p, M.p);
+      v = x_gate2<E>((int)(t - kXGate), M.gam + (int64_t)pq * M.pstride, M.bet + (int64_t)pq * M.pstride);
     }
     lds[q * stride + t] = v;
   }
@@ -1430,7 +1430,8 @@ __device__ __forceinline__ void x_grad_item(const XMulti& M, const XProg& P, int
                                             const XFinal* __restrict__ pfin, const int32_t* __restrict__ rec_off,
                                             const XCtx& c, int tid, int wave, int nw, E* area, uint32_t* smax,
                                             int* sexp, double* gacc) {
-  const double* prm = M.params + (int64_t)c.pt * 2 * M.p;
+  const double* prm = M.gam + (int64_t)c.pt * M.pstride;
+  const double* prb = M.bet + (int64_t)c.pt * M.pstride;
   for (int i = tid; i < P.n_slots; i += blockDim.x) {
     smax[i] = 0u;
     sexp[i] = 0;
@@ -1439,7 +1440,7 @@ __device__ __forceinline__ void x_grad_item(const XMulti& M, const XProg& P, int
     area[tid].x = 1;
     area[tid].y = 0;
   }
-  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x) area[kXGate + t] = x_gate<E>(t, prm, M.p);
+  for (int t = tid; t < x_gate_elems(M.p); t += blockDim.x) area[kXGate + t] = x_gate2<E>(t, prm, prb);
   x_level_sync<GLOBAL>();
   for (int L = 0; L < P.n_levels; ++L) {
     const int u_end = plev[L + 1];
@@ -1482,7 +1483,7 @@ __device__ __forceinline__ void x_grad_pts(const XMulti& M, const XProg& P, int 
       v.y = 0;
     } else {
       const uint32_t pq = pt0 + min(q, npts - 1u);
-      v = x_gate<E>((int)(t - kXGate), M.params + (int64_t)pq * 2 * M.p, M.p);
+      v = x_gate2<E>((int)(t - kXGate), M.gam + (int64_t)pq * M.pstride, M.bet + (int64_t)pq * M.pstride);
     }
     lds[q * stride + t] = v;
   }

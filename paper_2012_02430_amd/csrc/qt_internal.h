@@ -346,7 +346,10 @@ struct XMulti {
   const int32_t* level_off;
   const XFinal* finals;
   const int32_t* item_prog;
-  const double* params;    // [points][2p]
+  const double* gam;       // point q's gammas at gam + q * pstride, its betas at bet + q * pstride
+  const double* bet;
+  int32_t pstride;
+  int32_t pad;
   double* out;             // [points][programs][3]: re, im, log2 scale
   const XRev* revs;        // gradient executor only
   const int32_t* rec_off;

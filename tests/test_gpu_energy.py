@@ -276,3 +276,26 @@ def test_energy_job_cache_eviction_and_threads():
     for t in threads:
         t.join()
     assert not errors, errors
+
+
+@pytest.mark.parametrize("dedup", [False, True])
+@pytest.mark.parametrize("grad", [False, True])
+def test_device_arguments_match_host_arguments(grad, dedup):
+    """With parameters, weights and results in device memory the batched
+    launch reads the parameters where they are and the sums write the
+    caller's arrays; energies, per-edge values and gradients equal the
+    host-array route bit for bit."""
+    import torch
+
+    n, p, npt = 30, 2, 5
+    edges = regular_graph(n, 3, 4)
+    model = api.EnergyModel(n, edges, p, precision="c64", dedup=dedup)
+    gs, bs = qaoa_params(p, npt, seed=13)
+    host = model.energy(gs, bs, per_edge=True, grad=grad)
+    g = torch.tensor(np.asarray(gs).reshape(npt, p), dtype=torch.float64, device="cuda")
+    b = torch.tensor(np.asarray(bs).reshape(npt, p), dtype=torch.float64, device="cuda")
+    dev = model.energy_device(g, b, grad=grad, per_edge=True)
+    torch.cuda.synchronize()
+    assert len(host) == len(dev)
+    for h, d in zip(host, dev):
+        assert np.array_equal(h, d.cpu().numpy())

@@ -362,8 +362,10 @@ template <typename E>
 __global__ void k_leaves(const DevLeaf* __restrict__ leaves, int n_leaves, int leaf_block,
                          const double* __restrict__ dense, double* __restrict__ params,
                          const double* __restrict__ gammas, const double* __restrict__ betas, int p,
-                         int n_points, E* __restrict__ out) {
+                         int n_points, E* __restrict__ out, uint32_t* __restrict__ clear, int64_t n_clear) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // scale slots the run starts from zero (its first fill, folded in here)
+  for (int64_t i = t; i < n_clear; i += (int64_t)gridDim.x * blockDim.x) clear[i] = 0u;
   // parameters given in device memory ([points][p] each): read from there,
   // and laid out as [points][2p] (gammas, then betas) for the later launches
   if (gammas) {
@@ -533,16 +535,17 @@ __global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ pe
 
 hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, const double* dense,
                          double* params, const double* gammas, const double* betas, int p, int n_points,
-                         void* out, bool c128, hipStream_t stream) {
-  const int64_t n = std::max<int64_t>((int64_t)n_leaves * n_points, gammas ? (int64_t)n_points * 2 * p : 0);
+                         void* out, bool c128, hipStream_t stream, uint32_t* clear, int64_t n_clear) {
+  int64_t n = std::max<int64_t>((int64_t)n_leaves * n_points, gammas ? (int64_t)n_points * 2 * p : 0);
+  n = std::max<int64_t>(n, std::min<int64_t>(n_clear, (int64_t)1 << 20));  // the clear strides over the grid
   if (n == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (c128)
     hipLaunchKernelGGL(k_leaves<double2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params,
-                       gammas, betas, p, n_points, reinterpret_cast<double2*>(out));
+                       gammas, betas, p, n_points, reinterpret_cast<double2*>(out), clear, n_clear);
   else
     hipLaunchKernelGGL(k_leaves<float2>, grid, block, 0, stream, leaves, n_leaves, leaf_block, dense, params,
-                       gammas, betas, p, n_points, reinterpret_cast<float2*>(out));
+                       gammas, betas, p, n_points, reinterpret_cast<float2*>(out), clear, n_clear);
   return hipGetLastError();
 }
 

@@ -541,10 +541,12 @@ namespace qt {
 // kernels.hip
 // gammas/betas: the points' parameters in device memory ([points][p] each),
 // which the launch also lays out in `params` ([points][2p]); null: `params`
-// already holds them.
+// already holds them.  clear[0, n_clear): words set to zero by the same
+// launch.
 hipError_t launch_leaves(const DevLeaf* leaves, int n_leaves, int leaf_block, const double* dense,
                          double* params, const double* gammas, const double* betas, int p, int n_points,
-                         void* out, bool c128, hipStream_t stream);
+                         void* out, bool c128, hipStream_t stream, uint32_t* clear = nullptr,
+                         int64_t n_clear = 0);
 // Launches one bucket step; returns the kernel class used (QT_KCLASS_*)
 // through *kclass.
 hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint32_t* maxbits,

@@ -1109,16 +1109,19 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
   const bool direct = dev_params && !ws.leaves_read;
   if (!dev_params) QT_TRY(upload_params_to(ws.params, np, pp, gammas, betas, stream));
   const double eb = c128 ? 2.0 : 1.0;  // algorithmic byte counts are kept at 8 B per element
+  // the leaf launch also clears the scale slots of the prefix and of the
+  // first chunk
+  const int64_t n_clear = scaled && !direct ? ws.exp1_base + (k > 0 ? ws.exp1_count : 0) : 0;
   if (!direct) {
     // leaves, and the device parameters laid out for the segments
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
       return launch_leaves(ws.dleaves, (int)plan.dev_leaves.size(), plan.leaf_block, ws.ddense, ws.params,
                            dev_params ? gammas : nullptr, dev_params ? betas : nullptr, pp, np, ws.leaves, c128,
-                           stream);
+                           stream, ws.maxbits, n_clear);
     }));
     ++launches;
   }
-  if (scaled && ws.exp1_base) {
+  if (scaled && ws.exp1_base && n_clear == 0) {
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
                        [&] { return launch_fill_u32(ws.maxbits, ws.exp1_base, 0u, stream); }));
     ++launches;
@@ -1188,7 +1191,7 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
   } else {
     const int64_t C = ws.chunk;
     for (int64_t cb = begin & ~(C - 1); cb < stop; cb += C) {
-      if (scaled && ws.exp1_count) {
+      if (scaled && ws.exp1_count && !(n_clear > 0 && cb == (begin & ~(C - 1)))) {
         QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
           return launch_fill_u32(ws.maxbits + ws.exp1_base, ws.exp1_count, 0u, stream);
         }));

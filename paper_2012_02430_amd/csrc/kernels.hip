@@ -430,68 +430,13 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-// Per-slice value: product of the plan's closing factors (results of
-// buckets that closed to a scalar, Algorithm 1 "result <- result * R"), with
-// its exponent, in FP64.  With open output variables the closing factors
-// are tensors over subsets of them, and thread (item, j) forms output
-// element j (the open variables' values): the product of every factor at
-// the bits of j it holds (its runs over j), i.e. their outer product.
-template <typename E, bool SCALED>
-__global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_points, int64_t n_items,
-                        const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
-                        double* __restrict__ per_slice, int64_t slice_end, double* __restrict__ sums) {
-  const int64_t tj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tj >= (n_items << f.n_open)) return;
-  const uint32_t oj = (uint32_t)(tj & ((1ll << f.n_open) - 1));  // open output index
-  const int64_t t = tj >> f.n_open;
-  const uint32_t sb = (uint32_t)(t & ((1ll << f.lg_nsb) - 1));
-  const uint32_t pt = (uint32_t)(t >> f.lg_nsb);
-  const uint64_t sid = (uint64_t)f.chunk_base + sb;
-  if ((int64_t)sid < f.slice_begin || (int64_t)sid >= slice_end) return;
-  double re = 1.0, im = 0.0, ex = f.log2_const;
-  for (int j = 0; j < f.n_factors; ++j) {
-    const DevIn in = fac[j];
-    const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
-                        ((int64_t)pext_bits(sid, in.smask) << in.slow) + (int64_t)pext_runs(oj, in);
-    const E a = reinterpret_cast<const E*>(in.ptr)[idx];
-    double ar = (double)a.x, ai = (double)a.y;
-    if (SCALED && in.exp_base >= 0) {
-      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
-      const int sh = scale_shift(maxbits[slot]);
-      ar = ldexp(ar, -sh);
-      ai = ldexp(ai, -sh);
-      ex += exps[slot] + sh;
-    }
-    const double nr = re * ar - im * ai;
-    im = re * ai + im * ar;
-    re = nr;
-  }
-  double* o = per_slice + 3 * ((((int64_t)pt << f.n_open) + oj) * f.n_range + (int64_t)(sid - f.slice_begin));
-  o[0] = re;
-  o[1] = im;
-  o[2] = ex;
-  if (sums) {
-    // a range of one slice: its sum, as k_slice_sum forms it (a zero value
-    // reported with exponent 0)
-    const bool nz = re != 0.0 || im != 0.0;
-    double* s = sums + 3 * (((int64_t)pt << f.n_open) + oj);
-    s[0] = nz ? 0.0 + re : 0.0;
-    s[1] = nz ? 0.0 + im : 0.0;
-    s[2] = nz ? ex : 0.0;
-  }
-}
-
-// Deterministic FP64 sum over slices (Algorithm 1's final reduction): common
-// exponent = max over non-zero slices, thread t adds slices t, t+256, ... in
-// order, then a fixed-shape tree over the 256 partial sums.  With weights w
-// (non-negative), slice i enters w[i] times (the same sum over edges whose
-// lightcones are deduplicated: each class once, times its size).
-__global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ per_slice, int64_t n_range,
-                                                   const double* __restrict__ w, double* __restrict__ out) {
-  __shared__ double sre[256], sim[256];
-  const int pt = blockIdx.x;
+// Sum over a range of slices of one result row (a workgroup of 256
+// threads): the largest exponent of the nonzero values, then each value
+// rescaled to it, weighted, in a fixed order of partial sums.
+__device__ __forceinline__ void x_slice_sum_block(const double* __restrict__ ps, int64_t n_range,
+                                                  const double* __restrict__ w, double* __restrict__ out,
+                                                  double* sre, double* sim) {
   const int tid = threadIdx.x;
-  const double* ps = per_slice + 3 * (int64_t)pt * n_range;
   double emax = -INFINITY;
   for (int64_t i = tid; i < n_range; i += 256)
     if (ps[3 * i] != 0.0 || ps[3 * i + 1] != 0.0) emax = fmax(emax, ps[3 * i + 2]);
@@ -525,10 +470,88 @@ __global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ pe
     __syncthreads();
   }
   if (tid == 0) {
-    out[3 * pt] = sre[0];
-    out[3 * pt + 1] = sim[0];
-    out[3 * pt + 2] = emax == -INFINITY ? 0.0 : emax;
+    out[0] = sre[0];
+    out[1] = sim[0];
+    out[2] = emax == -INFINITY ? 0.0 : emax;
   }
+}
+
+// Per-slice value: product of the plan's closing factors (results of
+// buckets that closed to a scalar, Algorithm 1 "result <- result * R"), with
+// its exponent, in FP64.  With open output variables the closing factors
+// are tensors over subsets of them, and thread (item, j) forms output
+// element j (the open variables' values): the product of every factor at
+// the bits of j it holds (its runs over j), i.e. their outer product.
+template <typename E, bool SCALED>
+__device__ __forceinline__ void x_final_value(const DevFinal& f, const DevIn* __restrict__ fac,
+                                              const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
+                                              double* __restrict__ per_slice, double* __restrict__ sums,
+                                              int sum_mode, uint32_t oj, uint32_t sb, uint32_t pt, uint64_t sid) {
+  double re = 1.0, im = 0.0, ex = f.log2_const;
+  for (int j = 0; j < f.n_factors; ++j) {
+    const DevIn in = fac[j];
+    const int64_t idx = (int64_t)pt * in.pt_stride + (int64_t)sb * in.sb_stride +
+                        ((int64_t)pext_bits(sid, in.smask) << in.slow) + (int64_t)pext_runs(oj, in);
+    const E a = reinterpret_cast<const E*>(in.ptr)[idx];
+    double ar = (double)a.x, ai = (double)a.y;
+    if (SCALED && in.exp_base >= 0) {
+      const int slot = in.exp_base + (int)pt * in.exp_pt + (int)sb * in.exp_sb;
+      const int sh = scale_shift(maxbits[slot]);
+      ar = ldexp(ar, -sh);
+      ai = ldexp(ai, -sh);
+      ex += exps[slot] + sh;
+    }
+    const double nr = re * ar - im * ai;
+    im = re * ai + im * ar;
+    re = nr;
+  }
+  double* o = per_slice + 3 * ((((int64_t)pt << f.n_open) + oj) * f.n_range + (int64_t)(sid - f.slice_begin));
+  o[0] = re;
+  o[1] = im;
+  o[2] = ex;
+  if (sum_mode == 1) {
+    // a range of one slice: its sum, as k_slice_sum forms it (a zero value
+    // reported with exponent 0)
+    const bool nz = re != 0.0 || im != 0.0;
+    double* s = sums + 3 * (((int64_t)pt << f.n_open) + oj);
+    s[0] = nz ? 0.0 + re : 0.0;
+    s[1] = nz ? 0.0 + im : 0.0;
+    s[2] = nz ? ex : 0.0;
+  }
+}
+
+template <typename E, bool SCALED>
+__global__ void k_final(const DevFinal f, const DevIn* __restrict__ fac, int n_points, int64_t n_items,
+                        const int* __restrict__ exps, const uint32_t* __restrict__ maxbits,
+                        double* __restrict__ per_slice, int64_t slice_end, double* __restrict__ sums,
+                        int sum_mode) {
+  const int64_t tj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t oj = (uint32_t)(tj & ((1ll << f.n_open) - 1));  // open output index
+  const int64_t t = tj >> f.n_open;
+  const uint32_t sb = (uint32_t)(t & ((1ll << f.lg_nsb) - 1));
+  const uint32_t pt = (uint32_t)(t >> f.lg_nsb);
+  const uint64_t sid = (uint64_t)f.chunk_base + sb;
+  if (tj < (n_items << f.n_open) && (int64_t)sid >= f.slice_begin && (int64_t)sid < slice_end)
+    x_final_value<E, SCALED>(f, fac, exps, maxbits, per_slice, sums, sum_mode, oj, sb, pt, sid);
+  if (sum_mode == 2) {
+    // the whole range in this one workgroup (one point, no open output):
+    // its sum, as k_slice_sum forms it
+    __shared__ double sre[256], sim[256];
+    __syncthreads();
+    x_slice_sum_block(per_slice, f.n_range, nullptr, sums, sre, sim);
+  }
+}
+
+// Deterministic FP64 sum over slices (Algorithm 1's final reduction): common
+// exponent = max over non-zero slices, thread t adds slices t, t+256, ... in
+// order, then a fixed-shape tree over the 256 partial sums.  With weights w
+// (non-negative), slice i enters w[i] times (the same sum over edges whose
+// lightcones are deduplicated: each class once, times its size).
+__global__ __launch_bounds__(256) void k_slice_sum(const double* __restrict__ per_slice, int64_t n_range,
+                                                   const double* __restrict__ w, double* __restrict__ out) {
+  __shared__ double sre[256], sim[256];
+  const int pt = blockIdx.x;
+  x_slice_sum_block(per_slice + 3 * (int64_t)pt * n_range, n_range, w, out + 3 * pt, sre, sim);
 }
 
 }  // namespace
@@ -626,20 +649,24 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s
 
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items, bool c128,
                         bool scaled, const int* exps, const uint32_t* maxbits, double* per_slice,
-                        int64_t slice_end, hipStream_t stream, double* sums) {
-  if (sums && f.n_range != 1) return hipErrorInvalidValue;
+                        int64_t slice_end, hipStream_t stream, double* sums, int sum_mode) {
   const int64_t n = n_items << f.n_open;
+  // sums: 1, a range of one slice; 2, the whole range in one workgroup (one
+  // point, no open output)
+  if (sum_mode < 0 || sum_mode > 2 || (sum_mode && !sums) || (sum_mode == 1 && f.n_range != 1) ||
+      (sum_mode == 2 && (n_points != 1 || f.n_open != 0 || n > 256)))
+    return hipErrorInvalidValue;
   if (n > 0x7fffffffll * 256) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (c128)
     hipLaunchKernelGGL((k_final<double2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end, sums);
+                       maxbits, per_slice, slice_end, sums, sum_mode);
   else if (scaled)
     hipLaunchKernelGGL((k_final<float2, true>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end, sums);
+                       maxbits, per_slice, slice_end, sums, sum_mode);
   else
     hipLaunchKernelGGL((k_final<float2, false>), grid, block, 0, stream, f, factors, n_points, n_items, exps,
-                       maxbits, per_slice, slice_end, sums);
+                       maxbits, per_slice, slice_end, sums, sum_mode);
   return hipGetLastError();
 }
 

@@ -554,11 +554,13 @@ hipError_t launch_step(const DevStep& s, bool c128, bool scaled, int* exps, uint
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t stream);
 // gemm.hip: one fused GEMM bucket for all batch items (complex64, MFMA).
 hipError_t launch_gemm(const DevGemm& g, bool scaled, int* exps, uint32_t* maxbits, hipStream_t stream);
-// sums (non-null only for a range of one slice): also the range's sums,
-// as launch_slice_sum would form them.
+// sum_mode 1 (a range of one slice) or 2 (one point, no open output, the
+// whole range in this launch's single workgroup of 256): also the range's
+// sums into `sums`, as launch_slice_sum would form them.
 hipError_t launch_final(const DevFinal& f, const DevIn* factors, int n_points, int64_t n_items,
                         bool c128, bool scaled, const int* exps, const uint32_t* maxbits,
-                        double* per_slice, int64_t slice_end, hipStream_t stream, double* sums = nullptr);
+                        double* per_slice, int64_t slice_end, hipStream_t stream, double* sums = nullptr,
+                        int sum_mode = 0);
 hipError_t launch_lds_exec(const XLaunch& x, int64_t n_items, int waves, bool c128, bool scaled, int* exps,
                            uint32_t* maxbits, hipStream_t stream);
 hipError_t launch_lds_multi(const XMulti& m, int n_items, size_t smem, int waves, bool c128, bool scaled,

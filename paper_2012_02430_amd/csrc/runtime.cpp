@@ -1174,7 +1174,14 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
   // the sums go into the caller's device array when given (no copy after);
   // a range of one slice has them formed by the final launch itself
   double* const sums = sums_out ? sums_out : ws.sums;
-  double* const fold = n_range == 1 ? sums : nullptr;
+  // the final launch forms the sums itself for a range of one slice, or
+  // for one point without open outputs whose whole range is one launch of
+  // one workgroup
+  int sum_mode = n_range == 1 ? 1 : 0;
+  if (!sum_mode && k > 0 && np == 1 && plan.open_vars.empty()) {
+    const int64_t C = ws.chunk, first = begin & ~(C - 1);
+    if (first + C >= end && C <= 256) sum_mode = 2;
+  }
   DevFinal f{};
   f.n_factors = (int)ws.finals.size();
   f.n_open = (int)plan.open_vars.size();
@@ -1185,7 +1192,8 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
     f.lg_nsb = 0;
     f.chunk_base = 0;
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
-      return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream, fold);
+      return launch_final(f, ws.dfinal, np, np, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, end, stream, sums,
+                          sum_mode);
     }));
     ++launches;
   } else {
@@ -1202,12 +1210,12 @@ qt_status run_plan_ws(qt_plan& plan, qt_plan::Workspace& ws, int np, const doubl
       f.chunk_base = cb;
       QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0, [&] {
         return launch_final(f, ws.dfinal, np, (int64_t)np * C, c128, scaled, ws.exps, ws.maxbits, ws.per_slice, stop,
-                            stream, fold);
+                            stream, sums, sum_mode);
       }));
       ++launches;
     }
   }
-  if (!fold) {
+  if (!sum_mode || stop <= begin) {
     QT_HIP_CHECK(timed(plan, stream, QT_KCLASS_OTHER, -1, 0, 0,
                        [&] { return launch_slice_sum(ws.per_slice, np << f.n_open, n_range, sums, stream); }));
     ++launches;

@@ -434,3 +434,21 @@ def test_device_parameters_match_host_parameters(case, monkeypatch):
     got_per = np.vectorize(api.amp_to_complex)(ps[..., 0], ps[..., 1], ps[..., 2])
     assert np.array_equal(got, want)
     assert np.array_equal(got_per, want_per)
+
+
+def test_single_point_sums_match_batched_points():
+    """One point without open outputs has its slice sum formed inside the
+    final launch (one workgroup), several points by the sum launch: the same
+    arithmetic, so each point's amplitude is bit for bit the same either
+    way, at one slice and at a range of slices."""
+    n, p = 24, 2
+    edges = regular_graph(n, 3, 7)
+    net = api.Network(N.amplitude_network(n, edges, p, random_bitstring(n, 8)))
+    sch = net.plan_slicing(4, algo="min_fill")
+    plan = api.Plan(net, sch.order, sch.groups, precision="c64", fold_prefix=True)
+    gs, bs = qaoa_params(p, 3, seed=21)
+    for lo, hi in ((0, plan.n_slices), (3, 4), (2, 11)):
+        batch, _ = plan.contract_batch(gs, bs, lo, hi)
+        for i in range(3):
+            one, _ = plan.contract_batch(np.asarray(gs)[i:i + 1], np.asarray(bs)[i:i + 1], lo, hi)
+            assert one[0] == batch[i], (lo, hi, i)

@@ -21,6 +21,10 @@
  *     pointers.  Results written to host memory are complete when the call
  *     returns (the call synchronises `hip_stream`); results written to
  *     device memory are ordered on `hip_stream` and the call does not wait.
+ *     Device parameter (and weight) arrays are read by the call's launches
+ *     where they are, in stream order, and device results are written by
+ *     them in place: change or free such arrays only after the work on
+ *     `hip_stream` has run.
  *   - `hip_stream` is a hipStream_t (NULL = the default stream).  The
  *     library allocates its device workspace on first use of a plan and
  *     keeps it with the plan; calls on one plan must not overlap.

@@ -106,10 +106,20 @@ __device__ __forceinline__ uint32_t slot_part(const uint32_t* w, int q) {
   return s;
 }
 
+// s_waitcnt on the vector memory counter alone (at most N operations in
+// flight; the LDS and export counters at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
 // Tile: NB = 2^TB batch indices x TM = 2^LM rows x TN = 2^LN columns, the
-// low bits of the b, m and n counters.  TK is the LDS depth of a K stage
-// (the stage itself is g.tk <= TK deep).  Wavefront w owns the 16 x 16
-// sub-tile (batch, m block, n block) number w.
+// low bits of the b, m and n counters.  TK is the depth of a K stage (a
+// compile-time constant: the guards of the stage loads fold away, and the
+// compiler counts the loads and stores in flight exactly, so a tile's stage
+// does not wait for the previous tile's output stores).  Wavefront w owns
+// the 16 x 16 sub-tile (batch, m block, n block) number w.
 //
 // Tiles are numbered n fastest, then m, then the batch tile, then the item.
 // A workgroup takes `tiles_per_block` consecutive tiles, a power of two that
@@ -132,10 +142,15 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
   // read row li (0..15) at depth lk (0..3) per lane, and 16 + 1 and 64 + 4
   // put those 64 reads in distinct banks; BF16 planes: each lane reads 16
   // bytes (eight K values), rows 80 bytes apart
-  constexpr int kP = MODE == 1 ? TK + 8 : (TK == 64 ? TK + 4 : TK + 1);
-  constexpr int kALoads = kARows * TK / kGThreads, kBLoads = kBRows * TK / kGThreads;
+  constexpr int kP = MODE == 1 ? TK + 8 : (TK == 64 ? 68 : 17);
+  // stage elements per operand: a multiple of the block size, or (8-deep
+  // stages of the smallest tiles) less than it
+  constexpr uint32_t a_elems = kARows * TK, b_elems = kBRows * TK;
+  constexpr int kALoads = (a_elems + kGThreads - 1) / kGThreads, kBLoads = (b_elems + kGThreads - 1) / kGThreads;
   constexpr int kCWrites = kTileElems / kGThreads;
-  static_assert(kARows * TK % kGThreads == 0 && kBRows * TK % kGThreads == 0 && kTileElems % kGThreads == 0, "");
+  static_assert((a_elems < kGThreads || a_elems % kGThreads == 0) && (b_elems < kGThreads || b_elems % kGThreads == 0) &&
+                    kTileElems % kGThreads == 0,
+                "");
   // FP32: real and imaginary planes of A and B; BF16: nine planes each
   // (parts h, m, l of Re, Im and Re + Im), two bytes per element
   constexpr int kOpFloats = MODE == 1 ? 9 * (kARows + kBRows) * kP / 2 : 2 * (kARows + kBRows) * kP;
@@ -169,10 +184,9 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
 
   const uint32_t lg_nt = (uint32_t)(g.nn - LN), lg_mt = (uint32_t)(g.nm - LM), lg_bt = (uint32_t)(g.nb - TB);
   const uint32_t n_nt = 1u << lg_nt;
-  const uint32_t n_stages = (1u << g.nk) / (uint32_t)g.tk;
-  const int tk = g.tk;
-  const uint32_t a_elems = (uint32_t)(kARows * tk), b_elems = (uint32_t)(kBRows * tk);
-  const bool a_lane = (uint32_t)tid < a_elems, b_lane = (uint32_t)tid < b_elems;
+  const uint32_t n_stages = (1u << g.nk) / (uint32_t)TK;
+  const bool a_lane = a_elems >= kGThreads || (uint32_t)tid < a_elems;
+  const bool b_lane = b_elems >= kGThreads || (uint32_t)tid < b_elems;
   const int wb = wave / (kSubM * kSubN), wm = (wave / kSubN) % kSubM, wn = wave % kSubN;
   const int li = lane & 15, lk = lane >> 4;
 
@@ -237,6 +251,13 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
 
   uint32_t ka = 0, kb = 0;  // k parts of the stage in registers
   fetch(am, bn);
+  // The loads and stores in flight share one counter, which the compiler
+  // counts per path: with the first stage's loads complete on entry and the
+  // prefetched stage's loads complete at the end of each tile (only that
+  // tile's output stores may still be in flight), both ways into the loop
+  // agree, and the first stage write of a tile does not wait for the previous
+  // tile's stores to leave.
+  wait_vm<0>();
   float mrun = 0.f;  // output max over the range
   for (uint32_t it = 0; it < n_here; ++it) {
     v4f totR, totI;                                                 // running sums
@@ -290,13 +311,13 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       }
       __syncthreads();
       // the next stage, of this tile or of the next one, in flight during the products
-      if (s + 1u < n_stages) {
-        ka = ((ka | ~g.a_kh) + 1u) & g.a_kh;
-        kb = ((kb | ~g.b_kh) + 1u) & g.b_kh;
-        fetch(am + ka, bn + kb);
-      } else if (it + 1u < n_here) {
-        ka = kb = 0;
-        fetch(am2, bn2);
+      // (one call site: the stage registers have one definition in the loop,
+      // which the compiler neither copies nor waits for before the products)
+      {
+        const bool more = s + 1u < n_stages;
+        ka = more ? ((ka | ~g.a_kh) + 1u) & g.a_kh : 0u;
+        kb = more ? ((kb | ~g.b_kh) + 1u) & g.b_kh : 0u;
+        if (more || it + 1u < n_here) fetch((more ? am : am2) + ka, (more ? bn : bn2) + kb);
       }
       if (wave < kSubs) {
         v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
@@ -336,7 +357,7 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
               accI[r] = t3[r] - t1[r] - t2[r];
             }
           } else {
-            for (int kk = 0; kk < tk; kk += 4) {
+            for (int kk = 0; kk < TK; kk += 4) {
               const float ar = ar_p[kk], ai = ai_p[kk], br = br_p[kk], bi = bi_p[kk];
               accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accR, 0, 0, 0);
               accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, accR, 0, 0, 0);
@@ -410,6 +431,7 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(const DevGemm g, int* __rest
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), rC, c_vo, (cm + cn + slot_part(g.cw, q)) * 8u, 0);
       mrun = fmaxf(mrun, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
+    wait_vm<kCWrites>();  // the stage loads issued before these stores
     __syncthreads();  // the staging is overwritten by the next tile's first stage
     nt = nt + 1u < n_nt ? nt + 1u : 0u;
     am = am2;
@@ -470,7 +492,8 @@ hipError_t launch_gemm(const DevGemm& g, bool scaled, int* exps, uint32_t* maxbi
   // split-BF16 products take 32-deep stages (K >= 32)
   if (g.mode == 1) return g.tk == 32 && g.nk >= 5 ? go_shape<32, 1>(g, exps, maxbits, stream) : hipErrorInvalidValue;
   if (g.tk == 64 && g.nk >= 6) return go_shape<64, 0>(g, exps, maxbits, stream);
-  if ((g.tk == 16 && g.nk >= 4) || (g.tk == 8 && g.nk == 3)) return go_shape<16, 0>(g, exps, maxbits, stream);
+  if (g.tk == 16 && g.nk >= 4) return go_shape<16, 0>(g, exps, maxbits, stream);
+  if (g.tk == 8 && g.nk == 3) return go_shape<8, 0>(g, exps, maxbits, stream);
   return hipErrorInvalidValue;
 }
 

@@ -114,17 +114,19 @@ def test_gemm_profile_class(monkeypatch):
     assert prof["gemm"][0] == 1 and prof["gemm"][3] == 8.0 * 2 ** (2 + 5 + 5 + 6)
 
 
+@pytest.mark.parametrize("nk", [3, 4, 7])
 @pytest.mark.parametrize("tiles", ["1", "2", "8", "64"])
-def test_gemm_tile_ranges_bitwise(monkeypatch, tiles):
+def test_gemm_tile_ranges_bitwise(monkeypatch, tiles, nk):
     # a workgroup's range of tiles (n fastest, then m, inside one batch tile)
     # changes only which workgroup computes a tile: results are bitwise equal
     # to one tile per workgroup, on a bucket with several n and m tiles per
-    # batch tile and a short K (the cross-tile prefetch path)
+    # batch tile, with 8- and 16-deep single-stage tiles and 64-deep tiles of
+    # two stages (the cross-tile prefetch path and the stage cursor's wrap)
     monkeypatch.setenv("QT_GEMM_MIN_RANK", "6")
-    spec, tensors, order, _ = dense_case(21, 1, 7, 6, 4)
+    spec, tensors, order, _ = dense_case(21, 1, 7, 6, nk)
     plan = api.Plan(api.Network(spec), order, precision="c64_mfma_fp32")
     g = gemm_steps(plan)[0]["gemm"]
-    assert g["k_bits"] == 4
+    assert g["k_bits"] == nk and g["tile"][3] == {3: 8, 4: 16, 7: 64}[nk], g
     monkeypatch.setenv("QT_GEMM_TILES", "1")
     ref = plan.contract_amplitude([], [])
     monkeypatch.setenv("QT_GEMM_TILES", tiles)
